@@ -1,0 +1,30 @@
+"""Plain FP64 CPU oracle for the three-phonon linewidth path (test infrastructure).
+
+This package is test infrastructure only.  It is imported by the tests, by the
+smoke check and by the CPU-baseline leg of the benchmark, and by nothing else:
+the GPU library never calls it, and it shares no code, constants or tables with
+the GPU library.
+
+It evaluates the definitions of Barbalinardo et al., "Efficient Anharmonic
+Lattice Dynamics Calculations of Thermal Transport in Crystalline and
+Disordered Solids" (arXiv:2009.01967) literally, in float64, with NumPy/LAPACK:
+
+* ``phonons``      -- dynamical matrix, Bloch transform and eigenmodes
+                      (Sec. II.A, eq. eigenvectors / eigenvectors_crystal),
+                      group velocities (Sec. II.B, eq. velocity_crystal).
+* ``anharmonic``   -- Bose-Einstein occupations (eq. bose_einstein), the
+                      projections phi+ and phi- (eq. projection_plus), phase-space
+                      weights and scattering rates (eq. gamma_operators,
+                      phase_space, delta_deconstructed), and the linewidth
+                      Gamma^0 (Sec. II.B).
+* ``conductivity`` -- modal heat capacity (eq. heat_capacity), RTA conductivity
+                      (eq. RTA), and the QHGK conductivity with generalised heat
+                      capacity, velocity and Lorentzian lifetime (Sec. II.C,
+                      eqs. conductivity_amorphous .. lorentzian_amorphous), and
+                      the classical limit (Sec. II.D).
+
+Readings of points the paper leaves open are listed in each module's header.
+Every function here is pinned by tests that do not re-type its formula.
+"""
+
+from . import units, phonons, anharmonic, conductivity  # noqa: F401

@@ -1,0 +1,119 @@
+"""Conductivity stage of the oracle: modal heat capacity, RTA conductivity and
+QHGK conductivity.  Plain FP64 NumPy.
+
+Paper passages followed:
+* Sec. II.B, eq. heat_capacity: c_mu = hbar omega_mu dn_mu/dT.
+* Sec. II.B, eq. RTA: kappa = 1/(N_k V) sum_mu c_mu v_mu,a v_mu,b tau_mu,
+  tau_mu = 1/(2 Gamma^0_mu).
+* Sec. II.C, eq. conductivity_amorphous: kappa = (1/V) sum_{mu mu'} c_{mu mu'}
+  v_{mu mu' a} v_{mu mu' b} tau_{mu mu'}.
+* Sec. II.C, eq. twod_heat_capacity, generalized_velocity, lorentzian_amorphous.
+* Sec. II.D: classical limit, c = c_{mu mu'} = k_B.
+
+Readings of points the paper leaves open:
+* The printed generalised heat capacity (hbar w w'/T)(n - n')/(w - w') is
+  negative for w != w'; the sign is fixed to (hbar w w'/T)(n' - n)/(w - w'),
+  which is positive, tends to c_mu as w' -> w and equals k_B in the classical
+  limit.  When |w - w'| < 1e-9 w the limit c_mu at the mean frequency is used.
+* The generalised velocity sums over the fc2 blocks (i, j, R) with the
+  displacement x_i - (x_j + R) of the actual image, and D = phi''/sqrt(m m').
+* V is the unit-cell volume and N_k the grid size for RTA; for QHGK (Gamma
+  point) V is the cell volume and N_k = 1.
+* Conductivity is in W/(m K); masked modes (nu < 0.01 THz) are excluded.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import units
+from .anharmonic import occupation
+
+
+def heat_capacity(omega, T, stats='quantum'):
+    """c = hbar omega dn/dT [eV/K] (quantum) or k_B (classical)."""
+    omega = np.asarray(omega, dtype=float)
+    if stats == 'classical':
+        return np.full_like(omega, units.KB)
+    x = units.HBAR * omega / (units.KB * T)
+    with np.errstate(over='ignore', invalid='ignore', divide='ignore'):
+        h = 0.5 * x / np.sinh(0.5 * x)
+        return units.KB * np.where(x == 0, 1.0, h * h)
+
+
+def volume(crystal):
+    return abs(np.linalg.det(crystal.cell))
+
+
+def kappa_rta(crystal, ph, gamma, T, stats='quantum'):
+    """gamma: (nT, Nk, n) set-averaged linewidths [rad/ps]. Returns (nT, 3, 3) W/m/K."""
+    T = np.atleast_1d(np.asarray(T, dtype=float))
+    V = volume(crystal)
+    out = np.zeros((len(T), 3, 3))
+    for it, t in enumerate(T):
+        c = heat_capacity(ph.omega, t, stats)
+        with np.errstate(divide='ignore', invalid='ignore'):
+            tau = np.where(ph.mask, 1.0 / (2.0 * gamma[it]), 0.0)
+        w = np.where(ph.mask, c * tau, 0.0)
+        out[it] = np.einsum('ks,ksab->ab', w, ph.vv) / (ph.n_k * V)
+    return out * units.KAPPA_TO_SI
+
+
+def generalized_velocity(crystal, ph):
+    """v_{mu mu' a} at Gamma, shape (3, n, n) in A/ps."""
+    n = crystal.n_modes
+    E = ph.eigvec[0]
+    w = ph.omega[0]
+    m = crystal.masses
+    M = np.zeros((3, n, n))
+    for i, j, R, b in zip(crystal.fc2_i, crystal.fc2_j, crystal.fc2_R, crystal.fc2_val):
+        dx = crystal.positions[i] - (crystal.positions[j] + np.asarray(R, float) @ crystal.cell)
+        blk = b / np.sqrt(m[i] * m[j]) * units.EV_IN_AMU_A2_PS2
+        for a in range(3):
+            M[a, 3 * i:3 * i + 3, 3 * j:3 * j + 3] += dx[a] * blk
+    v = np.einsum('as,xab,bt->xst', E.conj(), M, E, optimize=True)
+    with np.errstate(divide='ignore', invalid='ignore'):
+        sq = np.sqrt(np.outer(np.abs(w), np.abs(w)))
+        v = v / (2.0 * sq[None])
+    mm = np.outer(ph.mask[0], ph.mask[0])
+    return np.where(mm[None], v, 0.0)
+
+
+def generalized_heat_capacity(omega, T, stats='quantum'):
+    w1 = omega[:, None]
+    w2 = omega[None, :]
+    if stats == 'classical':
+        return np.full((len(omega), len(omega)), units.KB)
+    n = occupation(omega, T, stats)
+    n1 = n[:, None]
+    n2 = n[None, :]
+    with np.errstate(divide='ignore', invalid='ignore'):
+        c = units.HBAR * w1 * w2 / T * (n2 - n1) / (w1 - w2)
+    near = np.abs(w1 - w2) < 1e-9 * np.maximum(np.abs(w1), np.abs(w2))
+    cd = heat_capacity(0.5 * (w1 + w2), T, stats)
+    return np.where(near, cd, c)
+
+
+def lorentzian_lifetime(omega, gamma):
+    g = gamma[:, None] + gamma[None, :]
+    dw = omega[:, None] - omega[None, :]
+    with np.errstate(divide='ignore', invalid='ignore'):
+        return g / (dw * dw + g * g)
+
+
+def kappa_qhgk(crystal, ph, gamma, T, stats='quantum'):
+    """gamma: (nT, 1, n) linewidths at Gamma [rad/ps]. Returns (nT, 3, 3) W/m/K."""
+    assert ph.n_k == 1
+    T = np.atleast_1d(np.asarray(T, dtype=float))
+    V = volume(crystal)
+    v = generalized_velocity(crystal, ph)              # (3, n, n)
+    w = ph.omega[0]
+    mask = ph.mask[0]
+    mm = np.outer(mask, mask)
+    out = np.zeros((len(T), 3, 3))
+    for it, t in enumerate(T):
+        c = generalized_heat_capacity(w, t, stats)
+        tau = lorentzian_lifetime(w, gamma[it, 0])
+        wgt = np.where(mm, c * tau, 0.0)
+        out[it] = np.real(np.einsum('st,ast,bst->ab', wgt, v, v.conj())) / V
+    return out * units.KAPPA_TO_SI

@@ -1,0 +1,105 @@
+"""Pins of the oracle's heat capacities and conductivities: the defining
+derivative of c, classical limits, limits of the generalised heat capacity,
+antisymmetry of the generalised velocity, and QHGK on a folded crystal
+supercell reducing to the RTA of the crystal as the linewidths go to zero."""
+
+import numpy as np
+import pytest
+
+from gen import diamond_si
+from gen.crystals import M_SI, M_GE
+from oracle import phonons as P, anharmonic as A, conductivity as C
+from tests.supercell import fold
+
+HBAR = 6.582119569e-4
+KB = 8.617333262e-5
+
+
+def test_heat_capacity_is_temperature_derivative_of_energy():
+    w = np.array([0.3, 3.0, 30.0, 90.0])
+    for T in (20.0, 300.0, 1500.0):
+        h = 1e-3 * T
+        dn = (A.occupation(w, T + h) - A.occupation(w, T - h)) / (2 * h)
+        assert np.allclose(C.heat_capacity(w, T), HBAR * w * dn, rtol=1e-7)
+
+
+def test_heat_capacity_classical_limits():
+    w = np.array([1.0, 10.0, 60.0])
+    assert np.allclose(C.heat_capacity(w, 1e6), KB, rtol=1e-6)
+    assert np.all(C.heat_capacity(w, 300.0, 'classical') == KB)
+    assert np.all(C.generalized_heat_capacity(w, 300.0, 'classical') == KB)
+
+
+def test_generalized_heat_capacity_limits_and_sign():
+    w = np.array([5.0, 5.0 * (1 + 1e-7), 20.0, 70.0])
+    T = 300.0
+    c2 = C.generalized_heat_capacity(w, T)
+    assert np.all(c2 > 0)
+    assert np.allclose(np.diag(c2), C.heat_capacity(w, T), rtol=1e-12)
+    assert c2[0, 1] == pytest.approx(C.heat_capacity(np.array([5.0]), T)[0], rel=1e-6)
+    assert np.allclose(c2, c2.T, rtol=1e-12)
+    # quantum -> classical at high T
+    c_hot = C.generalized_heat_capacity(w, 1e6)
+    assert np.allclose(c_hot, KB, rtol=1e-6)
+
+
+def test_lorentzian_diagonal_is_rta_lifetime():
+    w = np.array([1.0, 2.0, 3.0])
+    g = np.array([0.1, 0.02, 0.3])
+    tau = C.lorentzian_lifetime(w, g)
+    assert np.allclose(np.diag(tau), 1.0 / (2.0 * g))
+
+
+@pytest.fixture(scope="module")
+def folded():
+    c = diamond_si(grid=(3, 3, 3), rc3=2.6, masses=(M_SI, M_GE), seed=41)
+    ph = P.phonons(c)
+    sc = fold(c)
+    phs = P.phonons(sc)
+    return c, ph, sc, phs
+
+
+def test_generalized_velocity_antisymmetric(folded):
+    _, _, sc, phs = folded
+    v = C.generalized_velocity(sc, phs)
+    assert np.allclose(v, -np.transpose(v, (0, 2, 1)).conj(), atol=1e-10 * np.abs(v).max())
+    assert np.abs(np.imag(v)).max() < 1e-12 * np.abs(v).max()
+
+
+@pytest.mark.parametrize("scale", [1e-4, 1e-6])
+def test_qhgk_on_folded_crystal_reduces_to_rta(folded, scale):
+    c, ph, sc, phs = folded
+    T = [300.0]
+
+    def gfun(w):          # linewidths that depend on frequency only
+        return scale * (0.2 + 0.01 * w + 1e-3 * w * w)
+
+    g_c = np.where(ph.mask, gfun(ph.omega), 0.0)[None]
+    g_s = np.where(phs.mask, gfun(phs.omega), 0.0)[None]
+    k_rta = C.kappa_rta(c, ph, g_c, T)[0]
+    k_qhgk = C.kappa_qhgk(sc, phs, g_s, T)[0]
+    # off-diagonal Lorentzian terms are O(gamma^2 / dw^2) relative
+    tol = 50 * scale + 1e-9
+    assert np.allclose(k_qhgk, k_rta, rtol=tol, atol=tol * np.abs(k_rta).max())
+
+
+def test_rta_kappa_scales_as_inverse_fc3_squared():
+    c = diamond_si(grid=(3, 3, 3), rc3=2.6, seed=3)
+    ph = P.phonons(c)
+    g = A.linewidths(c, ph, [300.0], 0.2)
+    g3 = A.linewidths(c.with_fc3_scaled(3.0), ph, [300.0], 0.2)
+    k1 = C.kappa_rta(c, ph, g, [300.0])
+    k3 = C.kappa_rta(c, ph, g3, [300.0])
+    assert np.allclose(k3 * 9.0, k1, rtol=1e-12)
+    assert np.all(np.linalg.eigvalsh(k1[0]) > 0)
+
+
+def test_rta_kappa_classical_capacity_is_kb():
+    c = diamond_si(grid=(3, 3, 3), rc3=2.6, seed=3)
+    ph = P.phonons(c)
+    g = np.where(ph.mask, 0.01, 0.0)[None]
+    kc = C.kappa_rta(c, ph, g, [300.0], stats='classical')[0]
+    # classical: kappa = k_B / (2 gamma) * sum vv / (N_k V)
+    V = abs(np.linalg.det(c.cell))
+    expect = KB / 0.02 * np.einsum('ksab->ab', ph.vv) / (ph.n_k * V) * 1.602176634e3
+    assert np.allclose(kc, expect, rtol=1e-12)
