@@ -1,0 +1,169 @@
+/*
+ * kaldo.h -- C ABI of the MI355X (gfx950) three-phonon linewidth library.
+ *
+ * The library computes, on one GPU, the hot path of anharmonic lattice
+ * dynamics (Barbalinardo et al., arXiv:2009.01967):
+ *
+ *   kaldo_phonons     harmonic modes on a Gamma-centred q grid
+ *                     (Sec. II.A: D = phi''/sqrt(m m'), eq. eigenvectors_crystal;
+ *                      Sec. II.B eq. velocity_crystal for group velocities)
+ *   kaldo_linewidths  three-phonon projection and scattering-rate sum
+ *                     (Sec. II.B: eq. projection_plus, gamma_operators,
+ *                      phase_space, delta_deconstructed, and Gamma^0), giving
+ *                     the linewidth gamma of every mode
+ *   kaldo_kappa_rta   RTA conductivity of a crystal (Sec. II.B, eq. RTA)
+ *   kaldo_kappa_qhgk  QHGK conductivity at Gamma (Sec. II.C,
+ *                     eq. conductivity_amorphous .. lorentzian_amorphous)
+ *
+ * Units: length A, mass amu, energy eV (fc2 in eV/A^2, fc3 in eV/A^3),
+ * temperature K, frequency nu in THz, angular frequency and linewidth in
+ * rad/ps, velocity in A/ps, conductivity in W/(m K).
+ *
+ * Conventions (the same as the paper's, with its open points read as follows):
+ *  - fc2 block (i, j, R): d2E / du(i, home cell) du(j, cell R); R integer
+ *    lattice coordinates; Cartesian offset R . cell (cell rows are lattice
+ *    vectors).  fc3 block (i, j, R1, l, R2): d3E / du(i,0) du(j,R1) du(l,R2).
+ *    Blocks with equal keys are summed.  The Bloch phase uses the lattice
+ *    vector only: chi = exp(-2 pi i q.R).
+ *  - The q grid is Gamma centred: q_k = (m1/G1, m2/G2, m3/G3) in reduced
+ *    reciprocal coordinates with k = (m1 G2 + m2) G3 + m3.
+ *  - omega = sign(lambda) sqrt(|lambda|).  Modes with nu < 0.01 THz take no
+ *    part anywhere (gamma = 0, no kappa contribution).
+ *  - gamma_mu = Gamma^0_mu = (1/N_k) [sum Gamma+ + 1/2 sum Gamma-] is the
+ *    half width (rad/ps); tau = 1 / (2 gamma).  The energy delta is a Gaussian
+ *    of standard deviation 2 pi sigma_thz in angular frequency.
+ *  - gamma is averaged over each set of degenerate modes at one k (chained
+ *    frequency gaps below 1e-5 THz); only set averages are basis independent.
+ *
+ * Memory and ownership:
+ *  - Input arrays passed in the structs below are HOST memory owned by the
+ *    caller; they are read during the call, copied into device memory owned
+ *    by the context, and never retained.
+ *  - Output arrays may be host memory or device memory of the context's GPU
+ *    (HIP unified addressing decides).  Device outputs are written in order
+ *    on the context's stream; host outputs are complete when the call returns.
+ *  - Passing NULL for a structure, fc2 or fc3 argument reuses the copy already
+ *    resident on the device from the previous call on the same context (no
+ *    host-to-device transfer).  It is an error (KALDO_ESTATE) when none exists.
+ *
+ * Errors: every call returns a kaldo_status; nothing aborts or throws across
+ * the ABI.  kaldo_last_error() gives a text for the last failing call.  A
+ * context is not thread safe.  Calls are ordered phonons -> linewidths ->
+ * kappa; a call whose prerequisites are missing returns KALDO_ESTATE.
+ */
+#ifndef KALDO_H
+#define KALDO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kaldo_ctx_s* kaldo_ctx;
+
+typedef enum {
+  KALDO_OK = 0,
+  KALDO_EINVAL = -1,    /* bad argument: shape, index, NULL pointer, value range */
+  KALDO_ENOMEM = -2,    /* device allocation failed */
+  KALDO_EDEVICE = -3,   /* HIP / rocSOLVER runtime error */
+  KALDO_ESTATE = -4,    /* call out of order (no phonons / linewidths yet) */
+  KALDO_EUNSTABLE = -5  /* imaginary mode below -0.05 THz (offending k, s in error text) */
+} kaldo_status;
+
+typedef enum {
+  KALDO_FP64 = 0,      /* projection and epilogue in FP64 (reference GPU path) */
+  KALDO_FP32 = 1,      /* projection in FP32, FP32 partial sums, FP64 accumulation */
+  KALDO_BF16X3 = 2     /* projection GEMMs as BF16 hi+lo split (3 MFMAs), FP32 accumulate */
+} kaldo_precision;
+
+typedef enum {
+  KALDO_DELTA_GAUSS = 0 /* Gaussian energy delta (Appendix A) */
+} kaldo_delta;
+
+typedef enum {
+  KALDO_QUANTUM = 0,    /* Bose-Einstein occupations (eq. bose_einstein) */
+  KALDO_CLASSICAL = 1   /* n = k_B T / (hbar omega) (Sec. II.D) */
+} kaldo_stats;
+
+/* At most this many temperatures per kaldo_linewidths call. */
+#define KALDO_MAX_T 8
+
+typedef struct {
+  double cell[9];            /* rows = lattice vectors [A] */
+  int32_t n_atoms;           /* N >= 1; number of modes n = 3N */
+  const double* positions;   /* [N][3] Cartesian [A] */
+  const double* masses;      /* [N] [amu], > 0 */
+} kaldo_structure;
+
+typedef struct {
+  int64_t n_blocks;
+  const int32_t* i;          /* [nb], 0 <= i < N */
+  const int32_t* j;          /* [nb] */
+  const int32_t* R;          /* [nb][3], |R_c| <= 15 */
+  const double* blocks;      /* [nb][3][3] eV/A^2 */
+} kaldo_fc2;
+
+typedef struct {
+  int64_t n_blocks;
+  const int32_t* i;          /* [nb] home-cell atom */
+  const int32_t* j;          /* [nb] */
+  const int32_t* l;          /* [nb] */
+  const int32_t* R1;         /* [nb][3] cell of atom j, |R_c| <= 7 */
+  const int32_t* R2;         /* [nb][3] cell of atom l, |R_c| <= 7 */
+  const double* blocks;      /* [nb][3][3][3] eV/A^3 */
+} kaldo_fc3;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on (NULL: the context creates and owns its own stream). */
+kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream);
+
+/* Release all device memory of the context.  NULL is accepted. */
+void kaldo_destroy(kaldo_ctx ctx);
+
+/* Text of the last error on this context ("" if none); valid until the next
+ * call on the context. */
+const char* kaldo_last_error(kaldo_ctx ctx);
+
+/* Harmonic modes (paper Sec. II.A-B).  Builds D(q_k) = sum_R fc2 / sqrt(m m')
+ * exp(-2 pi i q_k.R) for every grid point, diagonalises it in FP64 on the GPU,
+ * and keeps frequencies, eigenvectors and velocity data resident for the later
+ * calls.
+ *   grid     [3] grid sizes, each >= 1, product <= 2^22
+ *   nu_out   [Nk][n] frequencies nu = omega / 2 pi [THz], or NULL
+ *   vel_out  [Nk][n][3] group velocities [A/ps] (basis dependent inside a
+ *            degenerate set), or NULL.  Not computed for grid {1,1,1}.
+ * Returns KALDO_EUNSTABLE if some nu < -0.05 THz. */
+kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
+                           const int32_t grid[3], double* nu_out, double* vel_out);
+
+/* Three-phonon linewidths (paper Sec. II.B) of every mode on the grid of the
+ * last kaldo_phonons call, for each of nT temperatures.
+ *   T          [nT] temperatures [K] (> 0 unless classical), 1 <= nT <= KALDO_MAX_T
+ *   sigma_thz  Gaussian width (standard deviation) in THz, > 0
+ *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
+ *              resident for kaldo_kappa_*)
+ * KALDO_BF16X3 is accepted only for grids {1,1,1} (the Gamma-point path). */
+kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
+                              double sigma_thz, kaldo_delta delta, kaldo_stats stats,
+                              kaldo_precision precision, double* gamma_out);
+
+/* RTA conductivity (paper eq. RTA) from the last linewidths:
+ *   kappa_out [nT][3][3] W/(m K).  Degenerate sets enter through the basis
+ *   invariant Re Tr(W_a W_b) / (4 omega^2), W = E_set^H dD/dq E_set.
+ * Requires a grid other than {1,1,1}. */
+kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
+
+/* QHGK conductivity (paper Sec. II.C) at Gamma from the last linewidths:
+ *   kappa_out [nT][3][3] W/(m K).  Requires grid {1,1,1}; V is the cell volume.
+ * Generalised heat capacity with the sign that makes it positive,
+ * (hbar w w'/T)(n' - n)/(w - w'); generalised velocity summed over fc2 blocks
+ * with the displacement x_i - (x_j + R.cell). */
+kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KALDO_H */

@@ -1,0 +1,390 @@
+// Three-phonon projection and scattering-rate sum (paper Sec. II.B) for
+// crystals with few branches.
+//
+// With k'' = k + p on the grid, the phases of eq. projection_plus factor as
+//   exp(-2 pi i p.R1) exp(2 pi i (k+p).R2) = exp(2 pi i k.R2) exp(2 pi i p.Delta),
+// Delta = R2 - R1, so the work splits into
+//   step A  A_k[s][Delta][a'][a''] = sum_{blocks with Delta} sum_a eta_ks[a] phi[a,a',a''] / sqrt(m m' m'') e^{2 pi i k.R2}
+//   step B  Phi_ks(p)[a'][a''] = sum_Delta e^{2 pi i p.Delta} A_k[s][Delta][a'][a'']
+//   step C  V[s][s'][s''] = sum_{a' a''} eta_p[a'][s'] conj(eta_{k+p}[a''][s'']) Phi_ks(p)[a'][a'']
+// V is phi+ of (k,s),(p,s'),(k+p,s'').  Because D(-p) = conj(D(p)), the span of
+// conj(eta_{-p}) inside each degenerate set equals that of eta_p, so the same V
+// also gives phi- of (k,s),(-p,s'),(k+p,s'') after the sums over s', s'':
+// one V feeds both the annihilation (+) and creation (-) weights.
+//
+// Epilogue (fused, V never leaves registers):
+//   w = (n' - n'') G(w + w' - w'') + 1/2 (1 + n' + n'') G(w - w' - w''),
+//   gamma_ks += |V|^2 w / (w w' w'') for every temperature,
+// with G the unnormalised Gaussian; the constant hbar pi / 8, the Gaussian
+// normalisation, 1 / N_k and 1 / w are applied by the finalising kernel.
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+
+namespace kaldo {
+
+struct ProjArgs {
+  int G0, G1, G2;
+  int nk, nd, nT;
+  int k0;
+  int ppt;       // p points per thread
+  double c;      // 1 / (2 sigma_omega^2)
+};
+
+// ---- mode tables ---------------------------------------------------------------
+// OM[s][k], IW[s][k] (1/omega or 0 if masked), OCC[t][s][k]
+__global__ void k_tables(double* __restrict__ OM, double* __restrict__ IW, double* __restrict__ OCC,
+                         const double* __restrict__ omega, int nk, int n, int nT, double4 T03, double4 T47,
+                         int classical) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)nk * n) return;
+  const int s = (int)(idx % n);
+  const int k = (int)(idx / n);
+  const double w = omega[idx];
+  const bool on = w / kTwoPi >= kNuMinThz;
+  const size_t o = (size_t)s * nk + k;
+  OM[o] = w;
+  IW[o] = on ? 1.0 / w : 0.0;
+  const double Ts[8] = {T03.x, T03.y, T03.z, T03.w, T47.x, T47.y, T47.z, T47.w};
+  for (int t = 0; t < nT; ++t) {
+    double occ = 0.0;
+    if (on) {
+      if (classical) occ = kBoltzmann * Ts[t] / (kHbar * w);
+      else if (Ts[t] > 0.0) occ = 1.0 / expm1(kHbar * w / (kBoltzmann * Ts[t]));
+    }
+    OCC[((size_t)t * n + s) * nk + k] = occ;
+  }
+}
+
+// PH[d][p] = exp(2 pi i q_p . Delta_d)
+template <typename R>
+__global__ void k_delta_phase(cplx<R>* __restrict__ PH, const int* __restrict__ delta, int nd, int G0, int G1,
+                              int G2) {
+  const int nk = G0 * G1 * G2;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)nk * nd) return;
+  const int p = (int)(idx % nk);
+  const int d = (int)(idx / nk);
+  const int m0 = p / (G1 * G2), m1 = (p / G2) % G1, m2 = p % G2;
+  const long long num = (long long)m0 * delta[3 * d] * (G1 * G2) + (long long)m1 * delta[3 * d + 1] * (G0 * G2) +
+                        (long long)m2 * delta[3 * d + 2] * (G0 * G1);
+  double c, s;
+  unit_phase(num, (long long)nk, c, s);
+  PH[idx] = {(R)c, (R)s};
+}
+
+// ET[s][a][k] = eta_ks[a]
+template <typename R>
+__global__ void k_evec_transpose(cplx<R>* __restrict__ ET, const cplx<double>* __restrict__ E, int nk, int n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)nk * n * n) return;
+  const int k = (int)(idx % nk);
+  const int a = (int)((idx / nk) % n);
+  const int s = (int)(idx / ((long long)nk * n));
+  const cplx<double> v = E[((size_t)k * n + s) * n + a];
+  ET[idx] = {(R)v.re, (R)v.im};
+}
+
+// ---- step A ---------------------------------------------------------------------
+template <typename R>
+__global__ void k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict__ E, const int2* __restrict__ group,
+                         const int* __restrict__ bi, const int* __restrict__ bR2, const double* __restrict__ bval,
+                         int N, int nd, int G0, int G1, int G2, int k0, int kcount) {
+  const int n = 3 * N;
+  const long long per_k = (long long)n * nd * n * n;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= per_k * kcount) return;
+  const int app = (int)(idx % n);
+  const int ap = (int)((idx / n) % n);
+  const int d = (int)((idx / ((long long)n * n)) % nd);
+  const int s = (int)((idx / ((long long)n * n * nd)) % n);
+  const int kl = (int)(idx / per_k);
+  const int k = k0 + kl;
+  const int j = ap / 3, be = ap % 3, l = app / 3, ga = app % 3;
+  const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
+  const long long Gt = (long long)G0 * G1 * G2;
+  const int2 g = group[((size_t)d * N + j) * N + l];
+  const cplx<double>* e = E + ((size_t)k * n + s) * n;
+  double re = 0.0, im = 0.0;
+  for (int b = g.x; b < g.y; ++b) {
+    const int i = bi[b];
+    const double* v = bval + 27 * (size_t)b + 3 * be + ga;
+    double sr = 0.0, si = 0.0;
+    for (int al = 0; al < 3; ++al) {
+      const cplx<double> ev = e[3 * i + al];
+      const double f = v[9 * al];
+      sr += ev.re * f;
+      si += ev.im * f;
+    }
+    const long long num = (long long)m0 * bR2[3 * b] * (G1 * G2) + (long long)m1 * bR2[3 * b + 1] * (G0 * G2) +
+                          (long long)m2 * bR2[3 * b + 2] * (G0 * G1);
+    double c, sn;
+    unit_phase(num, Gt, c, sn);  // exp(+2 pi i k.R2)
+    re += sr * c - si * sn;
+    im += sr * sn + si * c;
+  }
+  A[idx] = {(R)re, (R)im};
+}
+
+// ---- fused step B + step C + epilogue ----------------------------------------------
+template <typename R>
+__device__ __forceinline__ double gauss(double x, double c);
+
+template <>
+__device__ __forceinline__ double gauss<double>(double x, double c) {
+  return exp(-x * x * c);
+}
+
+template <>
+__device__ __forceinline__ double gauss<float>(double x, double c) {
+  return (double)__expf((float)(-x * x * c));
+}
+
+// Opaque zero: keeps loads inside a loop (bounds register pressure).
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
+
+template <typename R, int NM, int NT>
+__global__ void __launch_bounds__(256)
+    k_project_small(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ PH, const cplx<R>* __restrict__ ET,
+                    const double* __restrict__ OM, const double* __restrict__ IW, const double* __restrict__ OCC,
+                    ProjArgs P, double* __restrict__ partial) {
+  const int kl = blockIdx.y;
+  const int k = P.k0 + kl;
+  const int nk = P.nk;
+  const int km0 = k / (P.G1 * P.G2), km1 = (k / P.G2) % P.G1, km2 = k % P.G2;
+  // per-wave partial sums [wave][s][t]
+  __shared__ double red[4][NM * NT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 4 * NM * NT) (&red[0][0])[threadIdx.x] = 0.0;
+  __syncthreads();
+
+  for (int it = 0; it < P.ppt; ++it) {
+    const int p = (blockIdx.x * P.ppt + it) * blockDim.x + threadIdx.x;
+    if (p < nk) {
+      const int pm0 = p / (P.G1 * P.G2), pm1 = (p / P.G2) % P.G1, pm2 = p % P.G2;
+      int q0 = km0 + pm0, q1 = km1 + pm1, q2 = km2 + pm2;
+      q0 -= q0 >= P.G0 ? P.G0 : 0;
+      q1 -= q1 >= P.G1 ? P.G1 : 0;
+      q2 -= q2 >= P.G2 ? P.G2 : 0;
+      const int kk = (q0 * P.G1 + q1) * P.G2 + q2;
+      // p-side mode data stays in registers for all first modes s
+      cplx<R> Ep[NM][NM];
+      double wp[NM], np_[NT][NM];
+      R iwp[NM];
+#pragma unroll
+      for (int s1 = 0; s1 < NM; ++s1) {
+#pragma unroll
+        for (int a = 0; a < NM; ++a) Ep[a][s1] = ET[((size_t)s1 * NM + a) * nk + p];
+        wp[s1] = OM[(size_t)s1 * nk + p];
+        iwp[s1] = (R)IW[(size_t)s1 * nk + p];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) np_[t][s1] = t < P.nT ? OCC[((size_t)t * NM + s1) * nk + p] : 0.0;
+      }
+#pragma unroll 1
+      for (int s = 0; s < NM; ++s) {
+        const double iws = IW[(size_t)s * nk + k];
+        if (iws == 0.0) continue;  // masked first mode: uniform across the block
+        const double ws = OM[(size_t)s * nk + k];
+        double acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+        // step B: Phi = sum_Delta e^{2 pi i p.Delta} A_k[s][Delta]
+        cplx<R> F[NM][NM];
+#pragma unroll
+        for (int a = 0; a < NM; ++a)
+#pragma unroll
+          for (int b = 0; b < NM; ++b) F[a][b] = {(R)0, (R)0};
+        const cplx<R>* As = A + ((size_t)kl * NM + s) * (size_t)P.nd * NM * NM;
+        for (int d = 0; d < P.nd; ++d) {
+          const cplx<R> ph = PH[(size_t)d * nk + p];
+          const cplx<R>* Ad = As + (size_t)d * NM * NM;
+#pragma unroll
+          for (int a = 0; a < NM; ++a)
+#pragma unroll
+            for (int b = 0; b < NM; ++b) cfma(F[a][b], ph, Ad[a * NM + b]);
+        }
+        // step C + epilogue, one column s'' at a time; k''-side data is
+        // re-read per column instead of being held for all s.
+        const int z = opaque_zero();
+#pragma unroll 1
+        for (int s2 = 0; s2 < NM; ++s2) {
+          const size_t col = (size_t)s2 * NM * nk + kk + z;
+          cplx<R> Tc[NM];
+#pragma unroll
+          for (int a = 0; a < NM; ++a) {
+            Tc[a] = {(R)0, (R)0};
+#pragma unroll
+            for (int b = 0; b < NM; ++b) cfma_conj(Tc[a], F[a][b], ET[col + (size_t)b * nk]);
+          }
+          const double w2 = OM[(size_t)s2 * nk + kk + z];
+          const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
+          double n2[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) n2[t] = t < P.nT ? OCC[((size_t)t * NM + s2) * nk + kk + z] : 0.0;
+#pragma unroll
+          for (int s1 = 0; s1 < NM; ++s1) {
+            cplx<R> V = {(R)0, (R)0};
+#pragma unroll
+            for (int a = 0; a < NM; ++a) cfma(V, Ep[a][s1], Tc[a]);
+            const double v2 = (double)((V.re * V.re + V.im * V.im) * (iwp[s1] * iw2));
+            const double xp = ws + wp[s1] - w2;
+            const double xm = ws - wp[s1] - w2;
+            const double gp = gauss<R>(xp, P.c) * v2;
+            const double gm = 0.5 * gauss<R>(xm, P.c) * v2;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const double n1 = np_[t][s1];
+              acc[t] += gp * (n1 - n2[t]) + gm * (1.0 + n1 + n2[t]);
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          double v = acc[t];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+          if (lane == 0) red[wave][s * NT + t] += v;
+        }
+      }
+    }
+  }
+  // block reduction -> partial[kl][blockIdx.x][t][s]
+  __syncthreads();
+  if (threadIdx.x < NM * NT) {
+    const int s = threadIdx.x / NT, t = threadIdx.x % NT;
+    const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    if (t < P.nT) partial[(((size_t)kl * gridDim.x + blockIdx.x) * P.nT + t) * NM + s] = v;
+  }
+}
+
+// gamma[t][k][s] = C / w_ks * sum_chunks partial, then the mean over each degenerate set.
+__global__ void k_finalize(double* __restrict__ gamma, const double* __restrict__ partial, const double* __restrict__ IW,
+                           const int* __restrict__ setid, int nk, int n, int nT, int nchunk, int k0, int kcount,
+                           double C) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)kcount * nT) return;
+  const int kl = (int)(idx % kcount);
+  const int t = (int)(idx / kcount);
+  const int k = k0 + kl;
+  double g[64];
+  for (int s = 0; s < n; ++s) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += partial[(((size_t)kl * nchunk + c) * nT + t) * n + s];
+    g[s] = C * IW[(size_t)s * nk + k] * v;
+  }
+  const int* sid = setid + (size_t)k * n;
+  for (int s = 0; s < n;) {
+    int e = s + 1;
+    while (e < n && sid[e] == sid[s]) ++e;
+    double m = 0.0;
+    for (int u = s; u < e; ++u) m += g[u];
+    m /= (e - s);
+    for (int u = s; u < e; ++u) gamma[((size_t)t * nk + k) * n + u] = m;
+    s = e;
+  }
+}
+
+template <typename R, int NM>
+static void launch_project(dim3 grid, hipStream_t st, const cplx<R>* A, const cplx<R>* PH, const cplx<R>* ET,
+                           const double* OM, const double* IW, const double* OCC, const ProjArgs& P,
+                           double* partial) {
+  if (P.nT <= 1)
+    hipLaunchKernelGGL((k_project_small<R, NM, 1>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  else if (P.nT <= 2)
+    hipLaunchKernelGGL((k_project_small<R, NM, 2>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  else if (P.nT <= 3)
+    hipLaunchKernelGGL((k_project_small<R, NM, 3>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  else if (P.nT <= 4)
+    hipLaunchKernelGGL((k_project_small<R, NM, 4>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  else
+    hipLaunchKernelGGL((k_project_small<R, NM, 8>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+}
+
+template <typename R>
+static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
+  const int N = ctx->n_atoms, n = ctx->nm, nk = ctx->nk, nT = ctx->nT;
+  const int nd = ctx->fc3.n_delta;
+  hipStream_t st = ctx->stream;
+  const int TB = 256;
+  // tables: OM, IW [n][nk], OCC [nT][n][nk], PH [nd][nk], ET [n][n][nk]
+  const size_t nmode = (size_t)nk * n;
+  const size_t tab_bytes = (2 + (size_t)nT) * nmode * sizeof(double);
+  const size_t ph_bytes = (size_t)nd * nk * sizeof(cplx<R>);
+  const size_t et_bytes = (size_t)n * n * nk * sizeof(cplx<R>);
+  KALDO_HIP(ctx, ctx->d_tabs.ensure(tab_bytes + ph_bytes + et_bytes + 256));
+  double* OM = ctx->d_tabs.as<double>();
+  double* IW = OM + nmode;
+  double* OCC = IW + nmode;
+  cplx<R>* PH = reinterpret_cast<cplx<R>*>(OCC + (size_t)nT * nmode);
+  cplx<R>* ET = PH + (size_t)nd * nk;
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  hipLaunchKernelGGL(k_tables, dim3(blocks_for((long long)nmode, TB)), dim3(TB), 0, st, OM, IW, OCC,
+                     ctx->d_omega.as<double>(), nk, n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL((k_delta_phase<R>), dim3(blocks_for((long long)nd * nk, TB)), dim3(TB), 0, st, PH,
+                     ctx->fc3.d_delta.as<int>(), nd, ctx->grid[0], ctx->grid[1], ctx->grid[2]);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL((k_evec_transpose<R>), dim3(blocks_for((long long)n * n * nk, TB)), dim3(TB), 0, st, ET,
+                     ctx->d_evec.as<cplx<double>>(), nk, n);
+  KALDO_HIP(ctx, hipGetLastError());
+
+  // k chunks bounded by the size of the step-A intermediate
+  const size_t a_per_k = (size_t)n * nd * n * n * sizeof(cplx<R>);
+  const size_t a_budget = (size_t)1 << 30;
+  int kchunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, a_budget / a_per_k));
+  const int ppt = 1;
+  const int nchunk = (int)blocks_for(nk, TB * ppt);
+  kchunk = std::min(kchunk, 65535);
+  KALDO_HIP(ctx, ctx->d_A.ensure(a_per_k * kchunk));
+  KALDO_HIP(ctx, ctx->d_partial.ensure((size_t)kchunk * nchunk * nT * n * sizeof(double)));
+  KALDO_HIP(ctx, ctx->d_gamma.ensure((size_t)nT * nmode * sizeof(double)));
+  const double sig = kTwoPi * sigma_thz;
+  ProjArgs P;
+  P.G0 = ctx->grid[0];
+  P.G1 = ctx->grid[1];
+  P.G2 = ctx->grid[2];
+  P.nk = nk;
+  P.nd = nd;
+  P.nT = nT;
+  P.ppt = ppt;
+  P.c = 1.0 / (2.0 * sig * sig);
+  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
+  cplx<R>* A = ctx->d_A.as<cplx<R>>();
+  double* partial = ctx->d_partial.as<double>();
+  for (int k0 = 0; k0 < nk; k0 += kchunk) {
+    const int kc = std::min(kchunk, nk - k0);
+    P.k0 = k0;
+    hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)a_per_k / sizeof(cplx<R>) * kc, TB)), dim3(TB), 0,
+                       st, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(), ctx->fc3.d_blk_i.as<int>(),
+                       ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, k0, kc);
+    KALDO_HIP(ctx, hipGetLastError());
+    dim3 grid(nchunk, kc);
+    if (n == 6)
+      launch_project<R, 6>(grid, st, A, PH, ET, OM, IW, OCC, P, partial);
+    else
+      launch_project<R, 3>(grid, st, A, PH, ET, OM, IW, OCC, P, partial);
+    KALDO_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for((long long)kc * nT, TB)), dim3(TB), 0, st,
+                       ctx->d_gamma.as<double>(), partial, IW, ctx->d_setid.as<int>(), nk, n, nT, nchunk, k0, kc, C);
+    KALDO_HIP(ctx, hipGetLastError());
+  }
+  return KALDO_OK;
+}
+
+kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision) {
+  const int n = ctx->nm;
+  if (n == 3 || n == 6) {
+    if (precision == KALDO_FP64) return linewidths_small<double>(ctx, sigma_thz);
+    if (precision == KALDO_FP32) return linewidths_small<float>(ctx, sigma_thz);
+    return fail(ctx, KALDO_EINVAL, "BF16X3 needs the Gamma-point path (grid {1,1,1})");
+  }
+  return fail(ctx, KALDO_EINVAL, "this build handles cells of 1 or 2 atoms (n = 3 or 6) on crystal grids");
+}
+
+}  // namespace kaldo

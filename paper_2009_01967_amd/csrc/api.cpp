@@ -1,0 +1,358 @@
+// C ABI entry points: argument validation, host-to-device staging of the
+// structure and force constants, and dispatch to the device stages.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <sstream>
+#include <tuple>
+
+#include "internal.h"
+
+namespace kaldo {
+
+kaldo_status fail(kaldo_ctx ctx, kaldo_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what) {
+  std::ostringstream os;
+  os << what << ": " << hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? KALDO_ENOMEM : KALDO_EDEVICE, os.str());
+}
+
+kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (!dst || bytes == 0) return KALDO_OK;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  bool device = false;
+  hipError_t e = hipPointerGetAttributes(&attr, dst);
+  if (e == hipSuccess) {
+    device = attr.type == hipMemoryTypeDevice;
+  } else {
+    (void)hipGetLastError();
+  }
+  if (device) {
+    KALDO_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    KALDO_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return KALDO_OK;
+}
+
+template <typename T>
+static kaldo_status upload(kaldo_ctx ctx, DevBuf& buf, const T* src, size_t count) {
+  KALDO_HIP(ctx, buf.ensure(count * sizeof(T)));
+  if (count) KALDO_HIP(ctx, hipMemcpy(buf.p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return KALDO_OK;
+}
+
+static bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static kaldo_status load_structure(kaldo_ctx ctx, const kaldo_structure* s) {
+  if (!s->positions || !s->masses) return fail(ctx, KALDO_EINVAL, "structure: NULL positions or masses");
+  if (s->n_atoms < 1 || s->n_atoms > 100000) return fail(ctx, KALDO_EINVAL, "structure: n_atoms out of range");
+  const int N = s->n_atoms;
+  if (!finite_all(s->cell, 9) || !finite_all(s->positions, 3 * (size_t)N))
+    return fail(ctx, KALDO_EINVAL, "structure: non-finite cell or positions");
+  const double* c = s->cell;
+  double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+               c[2] * (c[3] * c[7] - c[4] * c[6]);
+  if (!(std::fabs(det) > 1e-6)) return fail(ctx, KALDO_EINVAL, "structure: singular cell");
+  for (int a = 0; a < N; ++a)
+    if (!(s->masses[a] > 0.0) || !std::isfinite(s->masses[a]))
+      return fail(ctx, KALDO_EINVAL, "structure: masses must be positive");
+  ctx->n_atoms = N;
+  std::memcpy(ctx->cell, s->cell, sizeof(ctx->cell));
+  ctx->positions.assign(s->positions, s->positions + 3 * N);
+  ctx->masses.assign(s->masses, s->masses + N);
+  kaldo_status st;
+  if ((st = upload(ctx, ctx->d_positions, s->positions, 3 * (size_t)N)) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_masses, s->masses, (size_t)N)) != KALDO_OK) return st;
+  ctx->have_structure = true;
+  // force constants refer to atom indices of the previous structure
+  ctx->have_fc2 = ctx->have_fc3 = ctx->have_phonons = ctx->have_gamma = false;
+  return KALDO_OK;
+}
+
+static kaldo_status load_fc2(kaldo_ctx ctx, const kaldo_fc2* f) {
+  const int N = ctx->n_atoms;
+  const int64_t nb = f->n_blocks;
+  if (nb < 1 || !f->i || !f->j || !f->R || !f->blocks) return fail(ctx, KALDO_EINVAL, "fc2: empty or NULL arrays");
+  for (int64_t b = 0; b < nb; ++b) {
+    if (f->i[b] < 0 || f->i[b] >= N || f->j[b] < 0 || f->j[b] >= N)
+      return fail(ctx, KALDO_EINVAL, "fc2: atom index out of range at block " + std::to_string(b));
+    for (int c = 0; c < 3; ++c)
+      if (std::abs(f->R[3 * b + c]) > 15) return fail(ctx, KALDO_EINVAL, "fc2: |R| > 15 at block " + std::to_string(b));
+  }
+  if (!finite_all(f->blocks, 9 * (size_t)nb)) return fail(ctx, KALDO_EINVAL, "fc2: non-finite values");
+  std::vector<int64_t> order(nb);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return std::make_pair(f->i[x], f->j[x]) < std::make_pair(f->i[y], f->j[y]);
+  });
+  std::vector<int> pair(2 * (size_t)N * N, 0), R(3 * nb), bi(nb), bj(nb);
+  std::vector<double> val(9 * nb);
+  for (int64_t q = 0; q < nb; ++q) {
+    int64_t b = order[q];
+    bi[q] = f->i[b];
+    bj[q] = f->j[b];
+    for (int c = 0; c < 3; ++c) R[3 * q + c] = f->R[3 * b + c];
+    for (int c = 0; c < 9; ++c) val[9 * q + c] = f->blocks[9 * b + c];
+  }
+  for (int64_t q = 0; q < nb; ++q) {
+    size_t p = (size_t)bi[q] * N + bj[q];
+    if (pair[2 * p + 1] == 0) pair[2 * p] = (int)q;
+    pair[2 * p + 1] = (int)q + 1;
+  }
+  kaldo_status st;
+  if ((st = upload(ctx, ctx->d_fc2_pair, pair.data(), pair.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_fc2_R, R.data(), R.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_fc2_val, val.data(), val.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_fc2_i, bi.data(), bi.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_fc2_j, bj.data(), bj.size())) != KALDO_OK) return st;
+  ctx->nb2 = nb;
+  ctx->have_fc2 = true;
+  ctx->have_phonons = ctx->have_gamma = false;
+  return KALDO_OK;
+}
+
+static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
+  const int N = ctx->n_atoms;
+  const int64_t nb = f->n_blocks;
+  if (nb < 0 || (nb > 0 && (!f->i || !f->j || !f->l || !f->R1 || !f->R2 || !f->blocks)))
+    return fail(ctx, KALDO_EINVAL, "fc3: NULL arrays");
+  if (nb > (int64_t)1 << 30) return fail(ctx, KALDO_EINVAL, "fc3: too many blocks");
+  for (int64_t b = 0; b < nb; ++b) {
+    if (f->i[b] < 0 || f->i[b] >= N || f->j[b] < 0 || f->j[b] >= N || f->l[b] < 0 || f->l[b] >= N)
+      return fail(ctx, KALDO_EINVAL, "fc3: atom index out of range at block " + std::to_string(b));
+    for (int c = 0; c < 3; ++c)
+      if (std::abs(f->R1[3 * b + c]) > 7 || std::abs(f->R2[3 * b + c]) > 7)
+        return fail(ctx, KALDO_EINVAL, "fc3: |R| > 7 at block " + std::to_string(b));
+  }
+  if (nb && !finite_all(f->blocks, 27 * (size_t)nb)) return fail(ctx, KALDO_EINVAL, "fc3: non-finite values");
+  // distinct Delta = R2 - R1
+  std::map<std::tuple<int, int, int>, int> dmap;
+  std::vector<int> didx(nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    auto key = std::make_tuple(f->R2[3 * b] - f->R1[3 * b], f->R2[3 * b + 1] - f->R1[3 * b + 1],
+                               f->R2[3 * b + 2] - f->R1[3 * b + 2]);
+    dmap.emplace(key, 0);
+  }
+  Fc3Layout& L = ctx->fc3;
+  L.delta.clear();
+  int nd = 0;
+  for (auto& kv : dmap) {
+    kv.second = nd++;
+    L.delta.push_back(std::get<0>(kv.first));
+    L.delta.push_back(std::get<1>(kv.first));
+    L.delta.push_back(std::get<2>(kv.first));
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    auto key = std::make_tuple(f->R2[3 * b] - f->R1[3 * b], f->R2[3 * b + 1] - f->R1[3 * b + 1],
+                               f->R2[3 * b + 2] - f->R1[3 * b + 2]);
+    didx[b] = dmap[key];
+  }
+  std::vector<int64_t> order(nb);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return std::make_tuple(didx[x], f->j[x], f->l[x]) < std::make_tuple(didx[y], f->j[y], f->l[y]);
+  });
+  const size_t ngroup = (size_t)std::max(nd, 1) * N * N;
+  std::vector<int> group(2 * ngroup, 0), bi(std::max<int64_t>(nb, 1)), bj(std::max<int64_t>(nb, 1)),
+      bl(std::max<int64_t>(nb, 1)), R2(3 * std::max<int64_t>(nb, 1));
+  std::vector<double> val(27 * std::max<int64_t>(nb, 1), 0.0);
+  for (int64_t q = 0; q < nb; ++q) {
+    const int64_t b = order[q];
+    bi[q] = f->i[b];
+    bj[q] = f->j[b];
+    bl[q] = f->l[b];
+    for (int c = 0; c < 3; ++c) R2[3 * q + c] = f->R2[3 * b + c];
+    const double s = 1.0 / std::sqrt(ctx->masses[bi[q]] * ctx->masses[bj[q]] * ctx->masses[bl[q]]);
+    for (int c = 0; c < 27; ++c) val[27 * q + c] = f->blocks[27 * b + c] * s;
+    const size_t g = ((size_t)didx[b] * N + bj[q]) * N + bl[q];
+    if (group[2 * g + 1] == 0) group[2 * g] = (int)q;
+    group[2 * g + 1] = (int)q + 1;
+  }
+  if (nd == 0) {
+    L.delta.assign(3, 0);
+    nd = 1;
+  }
+  kaldo_status st;
+  if ((st = upload(ctx, L.d_group, group.data(), group.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_blk_i, bi.data(), bi.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_blk_j, bj.data(), bj.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_blk_l, bl.data(), bl.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_blk_R2, R2.data(), R2.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_blk_val, val.data(), val.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_delta, L.delta.data(), L.delta.size())) != KALDO_OK) return st;
+  L.n_blocks = nb;
+  L.n_delta = nd;
+  ctx->have_fc3 = true;
+  ctx->have_gamma = false;
+  return KALDO_OK;
+}
+
+}  // namespace kaldo
+
+using namespace kaldo;
+
+extern "C" {
+
+kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream) {
+  if (!out) return KALDO_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return KALDO_EDEVICE;
+  if (device < 0 || device >= ndev) return KALDO_EINVAL;
+  kaldo_ctx ctx = new (std::nothrow) kaldo_ctx_s();
+  if (!ctx) return KALDO_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return KALDO_EDEVICE;
+  }
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return KALDO_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return KALDO_EDEVICE;
+  }
+  rocblas_set_stream(ctx->blas, ctx->stream);
+  *out = ctx;
+  return KALDO_OK;
+}
+
+void kaldo_destroy(kaldo_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* kaldo_last_error(kaldo_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
+                           const int32_t grid[3], double* nu_out, double* vel_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!grid) return fail(ctx, KALDO_EINVAL, "grid is NULL");
+  int64_t nk = 1;
+  for (int c = 0; c < 3; ++c) {
+    if (grid[c] < 1 || grid[c] > 4096) return fail(ctx, KALDO_EINVAL, "grid entries must be in [1, 4096]");
+    nk *= grid[c];
+  }
+  if (nk > (1 << 22)) return fail(ctx, KALDO_EINVAL, "grid too large");
+  kaldo_status st;
+  if (structure) {
+    if ((st = load_structure(ctx, structure)) != KALDO_OK) return st;
+  } else if (!ctx->have_structure) {
+    return fail(ctx, KALDO_ESTATE, "no structure resident: pass one");
+  }
+  if (fc2) {
+    if ((st = load_fc2(ctx, fc2)) != KALDO_OK) return st;
+  } else if (!ctx->have_fc2) {
+    return fail(ctx, KALDO_ESTATE, "no fc2 resident: pass one");
+  }
+  for (int c = 0; c < 3; ++c) ctx->grid[c] = grid[c];
+  ctx->nk = (int)nk;
+  ctx->nm = 3 * ctx->n_atoms;
+  ctx->have_phonons = false;
+  ctx->have_gamma = false;
+  const bool want_vel = nk > 1;
+  if ((st = run_phonons(ctx, want_vel)) != KALDO_OK) return st;
+  ctx->have_phonons = true;
+  const size_t nmode = (size_t)ctx->nk * ctx->nm;
+  if (nu_out) {
+    // nu = omega / 2 pi is computed on the device into the scratch buffer
+    if ((st = copy_out(ctx, nu_out, ctx->d_work.p, nmode * sizeof(double))) != KALDO_OK) return st;
+  }
+  if (vel_out) {
+    if (!want_vel) {
+      KALDO_HIP(ctx, ctx->d_vel.ensure(nmode * 3 * sizeof(double)));
+      KALDO_HIP(ctx, hipMemsetAsync(ctx->d_vel.p, 0, nmode * 3 * sizeof(double), ctx->stream));
+    }
+    if ((st = copy_out(ctx, vel_out, ctx->d_vel.p, nmode * 3 * sizeof(double))) != KALDO_OK) return st;
+  }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
+                              double sigma_thz, kaldo_delta delta, kaldo_stats stats,
+                              kaldo_precision precision, double* gamma_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_linewidths before kaldo_phonons");
+  if (!T || nT < 1 || nT > KALDO_MAX_T) return fail(ctx, KALDO_EINVAL, "need 1 <= nT <= KALDO_MAX_T temperatures");
+  if (delta != KALDO_DELTA_GAUSS) return fail(ctx, KALDO_EINVAL, "only the Gaussian delta is available");
+  if (stats != KALDO_QUANTUM && stats != KALDO_CLASSICAL) return fail(ctx, KALDO_EINVAL, "bad statistics");
+  if (precision != KALDO_FP64 && precision != KALDO_FP32 && precision != KALDO_BF16X3)
+    return fail(ctx, KALDO_EINVAL, "bad precision");
+  if (!(sigma_thz > 0.0) || !std::isfinite(sigma_thz)) return fail(ctx, KALDO_EINVAL, "sigma must be > 0");
+  for (int t = 0; t < nT; ++t) {
+    if (!std::isfinite(T[t]) || T[t] < 0.0 || (T[t] == 0.0 && stats == KALDO_CLASSICAL))
+      return fail(ctx, KALDO_EINVAL, "temperatures must be finite, >= 0 (> 0 for classical)");
+  }
+  kaldo_status st;
+  if (fc3) {
+    if ((st = load_fc3(ctx, fc3)) != KALDO_OK) return st;
+  } else if (!ctx->have_fc3) {
+    return fail(ctx, KALDO_ESTATE, "no fc3 resident: pass one");
+  }
+  ctx->nT = nT;
+  for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
+  ctx->stats = stats;
+  ctx->have_gamma = false;
+  if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
+  ctx->have_gamma = true;
+  if (gamma_out) {
+    const size_t bytes = (size_t)nT * ctx->nk * ctx->nm * sizeof(double);
+    if ((st = copy_out(ctx, gamma_out, ctx->d_gamma.p, bytes)) != KALDO_OK) return st;
+  }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_rta before kaldo_linewidths");
+  if (ctx->nk == 1) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_rta needs a grid other than {1,1,1}");
+  kaldo_status st;
+  if ((st = run_kappa_rta(ctx)) != KALDO_OK) return st;
+  if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_qhgk before kaldo_linewidths");
+  if (ctx->nk != 1) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_qhgk needs grid {1,1,1}");
+  kaldo_status st;
+  if ((st = run_kappa_qhgk(ctx)) != KALDO_OK) return st;
+  if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
+  return KALDO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of the gfx950 linewidth library: context, device
+// buffers, physical constants and kernel launchers.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kaldo.h"
+
+namespace kaldo {
+
+// ---- physical constants (CODATA 2018) -------------------------------------
+constexpr double kHbar = 6.582119569e-4;                  // eV ps
+constexpr double kBoltzmann = 8.617333262e-5;             // eV / K
+constexpr double kElectronVolt = 1.602176634e-19;         // J
+constexpr double kAmu = 1.66053906660e-27;                // kg
+// 1 eV in amu A^2 / ps^2
+constexpr double kEvUnit = kElectronVolt / (kAmu * 1e-20 / 1e-24);
+// eV / (K A ps) -> W / (m K)
+constexpr double kKappaSI = kElectronVolt / (1e-10 * 1e-12);
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279;
+constexpr double kNuMinThz = 0.01;       // modes below are excluded
+constexpr double kNuUnstableThz = -0.05; // below: imaginary mode error
+constexpr double kDegenerateThz = 1e-5;  // chained gap for degenerate sets
+
+// ---- device buffer ----------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // (Re)allocate to at least n bytes; contents are not preserved.
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Fc3Layout {
+  int64_t n_blocks = 0;
+  int n_delta = 0;
+  std::vector<int> delta;            // [nD][3]
+  // Blocks sorted by (delta, j, l); groups (delta, j, l) -> [start, end).
+  DevBuf d_group;                    // int2 [nD * N * N]
+  DevBuf d_blk_i;                    // int  [nb]
+  DevBuf d_blk_R2;                   // int  [nb][3]
+  DevBuf d_blk_val;                  // double [nb][27], divided by sqrt(m_i m_j m_l)
+  DevBuf d_delta;                    // int  [nD][3]
+  // Raw block list for the Gamma-point sparse path (same order).
+  DevBuf d_blk_j, d_blk_l;           // int [nb]
+};
+
+}  // namespace kaldo
+
+struct kaldo_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+  std::string err;
+
+  // structure
+  bool have_structure = false;
+  int n_atoms = 0;
+  double cell[9] = {0};
+  std::vector<double> positions, masses;
+  kaldo::DevBuf d_positions, d_masses;
+
+  // fc2, blocks sorted by (i, j)
+  bool have_fc2 = false;
+  int64_t nb2 = 0;
+  kaldo::DevBuf d_fc2_pair;          // int2 [N*N] -> [start, end)
+  kaldo::DevBuf d_fc2_R;             // int [nb][3]
+  kaldo::DevBuf d_fc2_val;           // double [nb][9]
+  kaldo::DevBuf d_fc2_i, d_fc2_j;    // int [nb]
+
+  // phonons
+  bool have_phonons = false;
+  int grid[3] = {1, 1, 1};
+  int nk = 0, nm = 0;
+  kaldo::DevBuf d_dyn;               // complex double [Nk][n][n] (column major per k)
+  kaldo::DevBuf d_lambda;            // double [Nk][n]
+  kaldo::DevBuf d_evec;              // complex double [Nk][n(s)][n(a)]: eta_ks[a]
+  kaldo::DevBuf d_omega;             // double [Nk][n] (signed)
+  kaldo::DevBuf d_setid;             // int [Nk][n] first mode of the degenerate set
+  kaldo::DevBuf d_vv;                // double [Nk][n][9]
+  kaldo::DevBuf d_vel;               // double [Nk][n][3]
+  kaldo::DevBuf d_info;              // int [Nk]
+  kaldo::DevBuf d_work;              // scratch
+
+  // fc3
+  bool have_fc3 = false;
+  kaldo::Fc3Layout fc3;
+
+  // linewidths
+  bool have_gamma = false;
+  int nT = 0;
+  double T[KALDO_MAX_T] = {0};
+  int stats = 0;
+  kaldo::DevBuf d_gamma;             // double [nT][Nk][n]
+  kaldo::DevBuf d_tabs;              // per-call mode tables
+  kaldo::DevBuf d_A;                 // step-A intermediate
+  kaldo::DevBuf d_partial;           // partial sums
+  kaldo::DevBuf d_kappa;             // double [nT][9]
+  kaldo::DevBuf d_scratch2;
+};
+
+namespace kaldo {
+
+// error helpers ---------------------------------------------------------------
+kaldo_status fail(kaldo_ctx ctx, kaldo_status s, const std::string& msg);
+kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what);
+
+#define KALDO_HIP(ctx, call)                                          \
+  do {                                                                \
+    hipError_t _e = (call);                                           \
+    if (_e != hipSuccess) return ::kaldo::hip_fail((ctx), _e, #call); \
+  } while (0)
+
+// copy a device result into a caller pointer that may be host or device memory
+kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
+
+// stages ------------------------------------------------------------------------
+kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity);
+kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision);
+kaldo_status run_kappa_rta(kaldo_ctx ctx);
+kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
+
+}  // namespace kaldo

@@ -1,0 +1,202 @@
+// Conductivities from the linewidths.
+//   RTA  (paper eq. RTA):   kappa_ab = 1/(N_k V) sum_mu c_mu tau_mu v_mu,a v_mu,b, tau = 1/(2 gamma)
+//   QHGK (Sec. II.C):       kappa_ab = 1/V sum_{mu mu'} c_{mu mu'} v_{mu mu' a} v_{mu mu' b} tau_{mu mu'}
+// All accumulation is FP64 with fixed-order (deterministic) reductions.
+#include <rocblas/rocblas.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace kaldo {
+
+__device__ __forceinline__ double heat_capacity(double w, double T, int classical) {
+  if (classical) return kBoltzmann;
+  const double x = kHbar * w / (kBoltzmann * T);
+  if (x == 0.0) return kBoltzmann;
+  const double h = 0.5 * x / sinh(0.5 * x);
+  return kBoltzmann * h * h;
+}
+
+__device__ __forceinline__ double occupation(double w, double T, int classical) {
+  if (classical) return kBoltzmann * T / (kHbar * w);
+  if (T <= 0.0) return 0.0;
+  return 1.0 / expm1(kHbar * w / (kBoltzmann * T));
+}
+
+template <int B>
+__device__ void block_sum9(double (&v)[9], double* out) {
+  __shared__ double red[B / 64][9];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double x = 0.0;
+    for (int w = 0; w < B / 64; ++w) x += red[w][threadIdx.x];
+    out[threadIdx.x] = x;
+  }
+}
+
+// one block per (temperature, slice of modes); partial[t][slice][9]
+__global__ void __launch_bounds__(256) k_kappa_rta(double* __restrict__ partial, const double* __restrict__ gamma,
+                                                   const double* __restrict__ omega, const double* __restrict__ vv,
+                                                   int nmode, double4 T03, double4 T47, int classical) {
+  const int t = blockIdx.y;
+  const double Ts[8] = {T03.x, T03.y, T03.z, T03.w, T47.x, T47.y, T47.z, T47.w};
+  const double T = Ts[t];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nmode; m += gridDim.x * blockDim.x) {
+    const double w = omega[m];
+    if (w / kTwoPi < kNuMinThz) continue;
+    const double ct = heat_capacity(w, T, classical) / (2.0 * gamma[(size_t)t * nmode + m]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += ct * vv[(size_t)m * 9 + c];
+  }
+  block_sum9<256>(acc, partial + ((size_t)t * gridDim.x + blockIdx.x) * 9);
+}
+
+__global__ void k_reduce_slices(double* __restrict__ out, const double* __restrict__ partial, int nslice, int nT,
+                                double scale) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nT * 9) return;
+  const int t = idx / 9, c = idx % 9;
+  double s = 0.0;
+  for (int b = 0; b < nslice; ++b) s += partial[((size_t)t * nslice + b) * 9 + c];
+  out[idx] = s * scale;
+}
+
+static double cell_volume(const double* c) {
+  const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+                     c[2] * (c[3] * c[7] - c[4] * c[6]);
+  return det < 0 ? -det : det;
+}
+
+kaldo_status run_kappa_rta(kaldo_ctx ctx) {
+  const int nmode = ctx->nk * ctx->nm;
+  const int nT = ctx->nT;
+  const int nslice = 64;
+  hipStream_t st = ctx->stream;
+  KALDO_HIP(ctx, ctx->d_kappa.ensure((size_t)nT * 9 * sizeof(double)));
+  KALDO_HIP(ctx, ctx->d_partial.ensure((size_t)nT * nslice * 9 * sizeof(double)));
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  hipLaunchKernelGGL(k_kappa_rta, dim3(nslice, nT), dim3(256), 0, st, ctx->d_partial.as<double>(),
+                     ctx->d_gamma.as<double>(), ctx->d_omega.as<double>(), ctx->d_vv.as<double>(), nmode, T03, T47,
+                     ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  const double scale = kKappaSI / (ctx->nk * cell_volume(ctx->cell));
+  hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(),
+                     ctx->d_partial.as<double>(), nslice, nT, scale);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
+// ---- QHGK ---------------------------------------------------------------------------
+// M_a (column major): M_a[a][b] = sum_R (x_i - x_j - R.cell)_a fc2 / sqrt(m_i m_j), ps^-2 A
+__global__ void k_displacement_hessian(double* __restrict__ M, const int2* __restrict__ pair,
+                                       const int* __restrict__ R, const double* __restrict__ val,
+                                       const double* __restrict__ mass, const double* __restrict__ pos,
+                                       const double* __restrict__ cell, int N) {
+  const int n = 3 * N;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const int a = (int)(idx % n), b = (int)(idx / n);
+  const int i = a / 3, al = a % 3, j = b / 3, be = b % 3;
+  const int2 pr = pair[i * N + j];
+  double acc[3] = {0, 0, 0};
+  for (int q = pr.x; q < pr.y; ++q) {
+    const double v = val[9 * q + 3 * al + be];
+    for (int d = 0; d < 3; ++d) {
+      const double Rc = R[3 * q] * cell[d] + R[3 * q + 1] * cell[3 + d] + R[3 * q + 2] * cell[6 + d];
+      acc[d] += (pos[3 * i + d] - pos[3 * j + d] - Rc) * v;
+    }
+  }
+  const double scale = kEvUnit / sqrt(mass[i] * mass[j]);
+  for (int d = 0; d < 3; ++d) M[(size_t)d * n * n + (size_t)b * n + a] = acc[d] * scale;
+}
+
+// pair sum over (s, u) of c tau v_a v_b; V_d column major: V_d[u * n + s] = (E^T M_d E)[s][u]
+__global__ void __launch_bounds__(256) k_qhgk_pairs(double* __restrict__ partial, const double* __restrict__ Vm,
+                                                    const double* __restrict__ omega, const double* __restrict__ gamma,
+                                                    int n, double4 T03, double4 T47, int classical) {
+  const int t = blockIdx.y;
+  const double Ts[8] = {T03.x, T03.y, T03.z, T03.w, T47.x, T47.y, T47.z, T47.w};
+  const double T = Ts[t];
+  const double* g = gamma + (size_t)t * n;
+  const size_t nn = (size_t)n * n;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < nn; m += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(m % n), u = (int)(m / n);
+    const double ws = omega[s], wu = omega[u];
+    if (ws / kTwoPi < kNuMinThz || wu / kTwoPi < kNuMinThz) continue;
+    double c;
+    if (classical) {
+      c = kBoltzmann;
+    } else if (fabs(ws - wu) < 1e-9 * fmax(fabs(ws), fabs(wu))) {
+      c = heat_capacity(0.5 * (ws + wu), T, 0);
+    } else {
+      c = kHbar * ws * wu / T * (occupation(wu, T, 0) - occupation(ws, T, 0)) / (ws - wu);
+    }
+    const double gs = g[s] + g[u];
+    const double dw = ws - wu;
+    const double tau = gs / (dw * dw + gs * gs);
+    const double inv = 1.0 / (2.0 * sqrt(ws * wu));
+    const double v0 = Vm[m] * inv, v1 = Vm[nn + m] * inv, v2 = Vm[2 * nn + m] * inv;
+    const double w = c * tau;
+    acc[0] += w * v0 * v0;
+    acc[1] += w * v0 * v1;
+    acc[2] += w * v0 * v2;
+    acc[3] += w * v1 * v0;
+    acc[4] += w * v1 * v1;
+    acc[5] += w * v1 * v2;
+    acc[6] += w * v2 * v0;
+    acc[7] += w * v2 * v1;
+    acc[8] += w * v2 * v2;
+  }
+  block_sum9<256>(acc, partial + ((size_t)t * gridDim.x + blockIdx.x) * 9);
+}
+
+kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
+  const int N = ctx->n_atoms, n = ctx->nm, nT = ctx->nT;
+  const size_t nn = (size_t)n * n;
+  hipStream_t st = ctx->stream;
+  // real eigenvectors: column s of d_dyn (Gamma path keeps them real)
+  const double* E = ctx->d_dyn.as<double>();
+  KALDO_HIP(ctx, ctx->d_scratch2.ensure(3 * nn * sizeof(double) * 2 + 64 * 9 * KALDO_MAX_T * sizeof(double)));
+  double* M = ctx->d_scratch2.as<double>();
+  double* X = M + 3 * nn;  // X then V reuses M
+  double* part = X + 3 * nn;
+  KALDO_HIP(ctx, ctx->d_tabs.ensure(9 * sizeof(double)));
+  KALDO_HIP(ctx, hipMemcpyAsync(ctx->d_tabs.p, ctx->cell, 9 * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_displacement_hessian, dim3(blocks_for((long long)nn, 256)), dim3(256), 0, st, M,
+                     ctx->d_fc2_pair.as<int2>(), ctx->d_fc2_R.as<int>(), ctx->d_fc2_val.as<double>(),
+                     ctx->d_masses.as<double>(), ctx->d_positions.as<double>(), ctx->d_tabs.as<double>(), N);
+  KALDO_HIP(ctx, hipGetLastError());
+  const double one = 1.0, zero = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, M + d * nn, n, E, n,
+                      &zero, X + d * nn, n) != rocblas_status_success)
+      return fail(ctx, KALDO_EDEVICE, "rocblas_dgemm failed");
+    if (rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one, E, n, X + d * nn,
+                      n, &zero, M + d * nn, n) != rocblas_status_success)
+      return fail(ctx, KALDO_EDEVICE, "rocblas_dgemm failed");
+  }
+  const int nslice = 64;
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  hipLaunchKernelGGL(k_qhgk_pairs, dim3(nslice, nT), dim3(256), 0, st, part, M, ctx->d_omega.as<double>(),
+                     ctx->d_gamma.as<double>(), n, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  KALDO_HIP(ctx, ctx->d_kappa.ensure((size_t)nT * 9 * sizeof(double)));
+  hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(), part, nslice, nT,
+                     kKappaSI / cell_volume(ctx->cell));
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
+}  // namespace kaldo

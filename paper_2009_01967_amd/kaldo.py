@@ -1,0 +1,277 @@
+"""Python binding of ``libkaldo.so`` (argument marshalling only).
+
+Every function of the C ABI in ``include/kaldo.h`` is exposed under the same
+name; the ``Context`` class bundles them for numpy inputs and numpy or torch
+outputs.  All arithmetic runs in the library's HIP kernels; this module never
+computes results itself, and it raises if the library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkaldo.so")
+
+KALDO_OK = 0
+KALDO_EINVAL = -1
+KALDO_ENOMEM = -2
+KALDO_EDEVICE = -3
+KALDO_ESTATE = -4
+KALDO_EUNSTABLE = -5
+
+KALDO_FP64 = 0
+KALDO_FP32 = 1
+KALDO_BF16X3 = 2
+PRECISIONS = {"fp64": KALDO_FP64, "fp32": KALDO_FP32, "bf16x3": KALDO_BF16X3}
+
+KALDO_DELTA_GAUSS = 0
+KALDO_QUANTUM = 0
+KALDO_CLASSICAL = 1
+KALDO_MAX_T = 8
+
+STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALDO_EDEVICE",
+                -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
+
+EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
+            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk"]
+
+
+class kaldo_structure(C.Structure):
+    _fields_ = [("cell", C.c_double * 9), ("n_atoms", C.c_int32),
+                ("positions", C.POINTER(C.c_double)), ("masses", C.POINTER(C.c_double))]
+
+
+class kaldo_fc2(C.Structure):
+    _fields_ = [("n_blocks", C.c_int64), ("i", C.POINTER(C.c_int32)), ("j", C.POINTER(C.c_int32)),
+                ("R", C.POINTER(C.c_int32)), ("blocks", C.POINTER(C.c_double))]
+
+
+class kaldo_fc3(C.Structure):
+    _fields_ = [("n_blocks", C.c_int64), ("i", C.POINTER(C.c_int32)), ("j", C.POINTER(C.c_int32)),
+                ("l", C.POINTER(C.c_int32)), ("R1", C.POINTER(C.c_int32)), ("R2", C.POINTER(C.c_int32)),
+                ("blocks", C.POINTER(C.c_double))]
+
+
+class KaldoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkaldo.so; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2009_01967_amd.build`")
+    lib = C.CDLL(path)
+    lib.kaldo_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]
+    lib.kaldo_create.restype = C.c_int
+    lib.kaldo_destroy.argtypes = [C.c_void_p]
+    lib.kaldo_destroy.restype = None
+    lib.kaldo_last_error.argtypes = [C.c_void_p]
+    lib.kaldo_last_error.restype = C.c_char_p
+    lib.kaldo_phonons.argtypes = [C.c_void_p, C.POINTER(kaldo_structure), C.POINTER(kaldo_fc2),
+                                  C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]
+    lib.kaldo_phonons.restype = C.c_int
+    lib.kaldo_linewidths.argtypes = [C.c_void_p, C.POINTER(kaldo_fc3), C.POINTER(C.c_double), C.c_int32,
+                                     C.c_double, C.c_int, C.c_int, C.c_int, C.c_void_p]
+    lib.kaldo_linewidths.restype = C.c_int
+    lib.kaldo_kappa_rta.argtypes = [C.c_void_p, C.c_void_p]
+    lib.kaldo_kappa_rta.restype = C.c_int
+    lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
+    lib.kaldo_kappa_qhgk.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+# ---- same-name thin wrappers ---------------------------------------------------
+
+def kaldo_create(device: int = 0, stream: Optional[int] = None):
+    lib = load_library()
+    h = C.c_void_p()
+    st = lib.kaldo_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+    if st != KALDO_OK:
+        raise KaldoError(st, "kaldo_create failed")
+    return h
+
+
+def kaldo_destroy(ctx) -> None:
+    load_library().kaldo_destroy(ctx)
+
+
+def kaldo_last_error(ctx) -> str:
+    return load_library().kaldo_last_error(ctx).decode()
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _out_ptr(out):
+    """Host numpy array or device tensor (anything with data_ptr) -> void*."""
+    if out is None:
+        return None
+    if hasattr(out, "data_ptr"):
+        return C.c_void_p(out.data_ptr())
+    return C.c_void_p(out.ctypes.data)
+
+
+def _check(ctx, st):
+    if st != KALDO_OK:
+        raise KaldoError(st, kaldo_last_error(ctx))
+
+
+class _Keep:
+    """Holds contiguous copies so ctypes pointers stay valid during a call."""
+
+    def __init__(self):
+        self.items = []
+
+    def arr(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.items.append(a)
+        return a
+
+
+def make_structure(cell, positions, masses, keep: _Keep):
+    s = kaldo_structure()
+    cell = keep.arr(cell, np.float64).reshape(9)
+    for c in range(9):
+        s.cell[c] = float(cell[c])
+    pos = keep.arr(positions, np.float64)
+    m = keep.arr(masses, np.float64)
+    s.n_atoms = int(m.shape[0])
+    s.positions = _ptr(pos, C.c_double)
+    s.masses = _ptr(m, C.c_double)
+    return s
+
+
+def make_fc2(i, j, R, blocks, keep: _Keep):
+    f = kaldo_fc2()
+    i = keep.arr(i, np.int32)
+    f.n_blocks = int(i.shape[0])
+    f.i = _ptr(i, C.c_int32)
+    f.j = _ptr(keep.arr(j, np.int32), C.c_int32)
+    f.R = _ptr(keep.arr(R, np.int32), C.c_int32)
+    f.blocks = _ptr(keep.arr(blocks, np.float64), C.c_double)
+    return f
+
+
+def make_fc3(i, j, l, R1, R2, blocks, keep: _Keep):
+    f = kaldo_fc3()
+    i = keep.arr(i, np.int32)
+    f.n_blocks = int(i.shape[0])
+    f.i = _ptr(i, C.c_int32)
+    f.j = _ptr(keep.arr(j, np.int32), C.c_int32)
+    f.l = _ptr(keep.arr(l, np.int32), C.c_int32)
+    f.R1 = _ptr(keep.arr(R1, np.int32), C.c_int32)
+    f.R2 = _ptr(keep.arr(R2, np.int32), C.c_int32)
+    f.blocks = _ptr(keep.arr(blocks, np.float64), C.c_double)
+    return f
+
+
+def kaldo_phonons(ctx, structure, fc2, grid, nu_out=None, vel_out=None) -> int:
+    g = (C.c_int32 * 3)(*[int(x) for x in grid])
+    return load_library().kaldo_phonons(ctx, C.byref(structure) if structure is not None else None,
+                                        C.byref(fc2) if fc2 is not None else None, g,
+                                        _out_ptr(nu_out), _out_ptr(vel_out))
+
+
+def kaldo_linewidths(ctx, fc3, T: Sequence[float], sigma_thz: float, stats: int = KALDO_QUANTUM,
+                     precision: int = KALDO_FP64, gamma_out=None, delta: int = KALDO_DELTA_GAUSS) -> int:
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    return load_library().kaldo_linewidths(ctx, C.byref(fc3) if fc3 is not None else None, Ts, len(T),
+                                           float(sigma_thz), int(delta), int(stats), int(precision),
+                                           _out_ptr(gamma_out))
+
+
+def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
+    return load_library().kaldo_kappa_rta(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
+    return load_library().kaldo_kappa_qhgk(ctx, _out_ptr(kappa_out))
+
+
+# ---- convenience context ---------------------------------------------------------
+
+class Context:
+    """One library context on one GPU.  Inputs are numpy arrays; outputs are
+    numpy arrays unless a device tensor is passed as ``out``."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.h = kaldo_create(device, stream)
+        self.nk = 0
+        self.n = 0
+        self.nT = 0
+
+    def close(self):
+        if self.h:
+            kaldo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def phonons(self, crystal=None, grid=None, nu_out=None, vel_out=None, want_host=True):
+        """Upload structure + fc2 of ``crystal`` (or reuse the resident ones when
+        crystal is None) and compute the modes on ``grid``."""
+        keep = _Keep()
+        s = f2 = None
+        if crystal is not None:
+            s = make_structure(crystal.cell, crystal.positions, crystal.masses, keep)
+            f2 = make_fc2(crystal.fc2_i, crystal.fc2_j, crystal.fc2_R, crystal.fc2_val, keep)
+            self.n = 3 * crystal.n_atoms
+            grid = crystal.grid if grid is None else grid
+        grid = tuple(int(x) for x in grid)
+        self.nk = int(np.prod(grid))
+        if want_host and nu_out is None:
+            nu_out = np.zeros((self.nk, self.n))
+        _check(self.h, kaldo_phonons(self.h, s, f2, grid, nu_out, vel_out))
+        return nu_out
+
+    def linewidths(self, crystal=None, T=(300.0,), sigma_thz=0.1, precision="fp64", classical=False,
+                   gamma_out=None, want_host=True):
+        keep = _Keep()
+        f3 = None
+        if crystal is not None:
+            f3 = make_fc3(crystal.fc3_i, crystal.fc3_j, crystal.fc3_l, crystal.fc3_R1, crystal.fc3_R2,
+                          crystal.fc3_val, keep)
+        self.nT = len(T)
+        if want_host and gamma_out is None:
+            gamma_out = np.zeros((len(T), self.nk, self.n))
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(self.h, kaldo_linewidths(self.h, f3, T, sigma_thz,
+                                        KALDO_CLASSICAL if classical else KALDO_QUANTUM, prec, gamma_out))
+        return gamma_out
+
+    def kappa_rta(self, out=None, want_host=True):
+        if want_host and out is None:
+            out = np.zeros((self.nT, 3, 3))
+        _check(self.h, kaldo_kappa_rta(self.h, out))
+        return out
+
+    def kappa_qhgk(self, out=None, want_host=True):
+        if want_host and out is None:
+            out = np.zeros((self.nT, 3, 3))
+        _check(self.h, kaldo_kappa_qhgk(self.h, out))
+        return out
