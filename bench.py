@@ -1,0 +1,201 @@
+"""Benchmark of the three-phonon linewidth path on one MI355X.
+
+One step = the whole hot path on resident inputs: harmonic modes on the grid
+(D(q) assembly + FP64 eigensolve + mode tables + velocities), the three-phonon
+projection and scattering-rate sum for every mode and temperature, and the RTA
+conductivity.  Inputs (structure, fc2, fc3) are uploaded once before timing;
+outputs stay in device memory.  The mixed-precision (FP32 projection) path
+gives ``value``; the FP64 path is timed beside it.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "diamond-2at-16x16x16-shell3"
+METRIC = "phonon linewidths/s + projection TFLOP/s, mixed vs FP64, at rel err ≤1e-4"
+FP32_VECTOR_PEAK = 157.3e12     # MI355X published vector FP32 (TFLOP/s)
+FP64_VECTOR_PEAK = 78.6e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(nk, n, nd):
+    """Projection work of one linewidth pass (steps B and C, one V for both signs)."""
+    f_b = 8.0 * nk * nk * nd * n ** 3
+    f_c = 16.0 * nk * nk * n ** 4
+    return f_b, f_c
+
+
+def run_gpu(args):
+    import torch
+    from gen import workload, WORKLOADS
+    from paper_2009_01967_amd import kaldo
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    w = WORKLOADS[WORKLOAD]
+    c = workload(WORKLOAD)
+    T = list(w["T"])
+    sigma = w["sigma_thz"]
+    nk, n = c.n_k, c.n_modes
+    dev = torch.device("cuda:0")
+    # a torch-owned stream (default priority); the library launches on it and
+    # the timing events are recorded on it
+    stream = torch.cuda.Stream(device=dev)
+    ctx = kaldo.Context(0, stream.cuda_stream)
+    # upload the inputs once; later calls pass NULL and reuse the resident copies
+    ctx.phonons(c)
+    ctx.linewidths(c, T=T, sigma_thz=sigma, precision="fp64")
+    nu_d = torch.empty((nk, n), dtype=torch.float64, device=dev)
+    g_d = torch.empty((len(T), nk, n), dtype=torch.float64, device=dev)
+    k_d = torch.empty((len(T), 3, 3), dtype=torch.float64, device=dev)
+
+    def step(prec):
+        h = ctx.h
+        kaldo._check(h, kaldo.kaldo_phonons(h, None, None, c.grid, nu_d, None))
+        kaldo._check(h, kaldo.kaldo_linewidths(h, None, T, sigma, kaldo.KALDO_QUANTUM, prec, g_d))
+        kaldo._check(h, kaldo.kaldo_kappa_rta(h, k_d))
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        kaldo.kaldo_profile_enable(ctx.h, True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step(prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        ms = e0.elapsed_time(e1) / steps
+        kern = {}
+        for name in ("dyn_assemble", "eigensolve", "step_a", "project", "finalize", "kappa_rta"):
+            tot, cnt = kaldo.kaldo_profile_read(ctx.h, name)
+            kern[name] = {"avg_ms": tot / cnt if cnt else None, "launches": cnt}
+        kaldo.kaldo_profile_enable(ctx.h, False)
+        return ms, wall, kern, g_d.cpu().numpy().copy(), k_d.cpu().numpy().copy()
+
+    ms32, wall32, kern32, g32, k32 = timed(kaldo.KALDO_FP32, args.steps, args.warmup)
+    log(f"fp32: {ms32:.3f} ms/step (wall {wall32:.3f}), kernels {kern32}")
+    ms64, wall64, kern64, g64, k64 = timed(kaldo.KALDO_FP64, max(2, args.steps // 2), 1)
+    log(f"fp64: {ms64:.3f} ms/step (wall {wall64:.3f}), kernels {kern64}")
+    nd = int(len({tuple(x) for x in (c.fc3_R2 - c.fc3_R1)}))
+    ctx.close()
+    return dict(c=c, w=w, T=T, sigma=sigma, nk=nk, n=n, nd=nd, ms32=ms32, ms64=ms64, wall32=wall32,
+                wall64=wall64, kern32=kern32, kern64=kern64, g32=g32, g64=g64, k32=k32, k64=k64)
+
+
+def cpu_baseline(r, budget_s=20.0):
+    """The FP64 oracle on the host, on a bounded sample of first-mode k points."""
+    from oracle import phonons as P, anharmonic as A
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    c, w, T = r["c"], r["w"], r["T"]
+    ph = P.phonons(c, velocities=False)
+    rng = np.random.default_rng(7)
+    cand = [0, 1, 17, 273, 2080] + list(rng.choice(c.n_k, size=64, replace=False))
+    done = []
+    g_ref = []
+    t0 = time.perf_counter()
+    for k in cand:
+        g_ref.append(A.linewidths(c, ph, T, r["sigma"], k_subset=[int(k)])[:, 0])
+        done.append(int(k))
+        if time.perf_counter() - t0 > budget_s and len(done) >= 4:
+            break
+    el = time.perf_counter() - t0
+    g_ref = np.stack(g_ref, axis=1)               # (nT, nsample, n)
+    mask = ph.mask[done]
+    ref = g_ref[:, mask]
+    floor = 1e-6 * np.abs(ref).max()
+
+    def err(g):
+        gs = g[:, done][:, mask]
+        return float(np.max(np.abs(gs - ref) / np.maximum(np.abs(ref), floor)))
+
+    lw = len(done) * c.n_modes * len(T)
+    return {"value": lw / el, "unit": "linewidths/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(done)} of {c.n_k} first-mode k points x {c.n_modes} modes x {len(T)} T "
+                      f"({el:.1f} s, numpy float64, host cores {os.cpu_count()})"}, \
+        {"fp32": err(r["g32"]), "fp64": err(r["g64"]), "k_sample": len(done)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part "
+              f"of this build", file=sys.stderr)
+        sys.exit(2)
+    r = run_gpu(args)
+    nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
+    lw = nk * n * nT
+    f_b, f_c = algorithmic_flops(nk, n, nd)
+    value = lw / (r["ms32"] * 1e-3)
+    proj32 = r["kern32"]["project"]["avg_ms"]
+    proj64 = r["kern64"]["project"]["avg_ms"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "linewidths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms32"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n_k": nk, "n_modes": n, "n_T": nT, "T_K": r["T"],
+                   "sigma_thz": r["sigma"], "fc3_blocks": int(len(r["c"].fc3_i)), "n_delta": nd,
+                   "projection": "fp32", "accumulation": "fp64"},
+        "projection_tflops": (f_b + f_c) / (r["ms32"] * 1e-3) / 1e12,
+        "fp64": {"ms_per_step": r["ms64"], "value": lw / (r["ms64"] * 1e-3),
+                 "projection_tflops": (f_b + f_c) / (r["ms64"] * 1e-3) / 1e12,
+                 "project_kernel_ms": proj64},
+        "speedup_fp32_vs_fp64": r["ms64"] / r["ms32"],
+        "kernels_ms": {k: v["avg_ms"] for k, v in r["kern32"].items()},
+        "roofline": {
+            "bound": "alu", "kernel": "k_project_small<float,6,3>",
+            "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
+            "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
+            "traffic": None,
+            "flops_per_launch": f_b + f_c,
+        },
+    }
+    if not args.no_cpu:
+        base, err = cpu_baseline(r)
+        out["cpu_baseline"] = base
+        out["err_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,18 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
  * with the displacement x_i - (x_j + R.cell). */
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
 
+/* Kernel timing instrumentation (not a step of the method).  While enabled,
+ * the library records a pair of HIP events on the context's stream around
+ * every launch of its main kernels, named
+ *   "dyn_assemble", "eigensolve", "step_a", "project", "finalize",
+ *   "kappa_rta", "kappa_qhgk".
+ * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables.
+ * kaldo_profile_read synchronises the stream and returns, for one kernel
+ * name, the summed duration (ms) and the number of launches since enabling;
+ * an unknown name gives 0 and 0. */
+kaldo_status kaldo_profile_enable(kaldo_ctx ctx, int enable);
+kaldo_status kaldo_profile_read(kaldo_ctx ctx, const char* kernel, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

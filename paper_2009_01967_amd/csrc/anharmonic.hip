@@ -360,19 +360,25 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   for (int k0 = 0; k0 < nk; k0 += kchunk) {
     const int kc = std::min(kchunk, nk - k0);
     P.k0 = k0;
+    prof_begin(ctx);
     hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)a_per_k / sizeof(cplx<R>) * kc, TB)), dim3(TB), 0,
                        st, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(), ctx->fc3.d_blk_i.as<int>(),
                        ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, k0, kc);
     KALDO_HIP(ctx, hipGetLastError());
+    prof_end(ctx, "step_a");
     dim3 grid(nchunk, kc);
+    prof_begin(ctx);
     if (n == 6)
       launch_project<R, 6>(grid, st, A, PH, ET, OM, IW, OCC, P, partial);
     else
       launch_project<R, 3>(grid, st, A, PH, ET, OM, IW, OCC, P, partial);
     KALDO_HIP(ctx, hipGetLastError());
+    prof_end(ctx, "project");
+    prof_begin(ctx);
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for((long long)kc * nT, TB)), dim3(TB), 0, st,
                        ctx->d_gamma.as<double>(), partial, IW, ctx->d_setid.as<int>(), nk, n, nT, nchunk, k0, kc, C);
     KALDO_HIP(ctx, hipGetLastError());
+    prof_end(ctx, "finalize");
   }
   return KALDO_OK;
 }

@@ -23,6 +23,45 @@ kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what) {
   return fail(ctx, e == hipErrorOutOfMemory ? KALDO_ENOMEM : KALDO_EDEVICE, os.str());
 }
 
+void prof_begin(kaldo_ctx ctx) {
+  if (!ctx->prof) return;
+  if (hipEventCreate(&ctx->prof_open) != hipSuccess) {
+    ctx->prof_open = nullptr;
+    return;
+  }
+  (void)hipEventRecord(ctx->prof_open, ctx->stream);
+}
+
+void prof_end(kaldo_ctx ctx, const char* name) {
+  if (!ctx->prof || !ctx->prof_open) return;
+  hipEvent_t stop;
+  if (hipEventCreate(&stop) != hipSuccess) return;
+  (void)hipEventRecord(stop, ctx->stream);
+  ctx->prof_tab[name].pending.emplace_back(ctx->prof_open, stop);
+  ctx->prof_open = nullptr;
+}
+
+static void prof_collect(kaldo_ctx ctx) {
+  for (auto& kv : ctx->prof_tab) {
+    for (auto& ev : kv.second.pending) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+        kv.second.total_ms += ms;
+        kv.second.launches += 1;
+      }
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    kv.second.pending.clear();
+  }
+}
+
+void prof_clear(kaldo_ctx ctx) {
+  (void)hipStreamSynchronize(ctx->stream);
+  prof_collect(ctx);
+  ctx->prof_tab.clear();
+}
+
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {
   if (!dst || bytes == 0) return KALDO_OK;
   hipPointerAttribute_t attr;
@@ -242,6 +281,7 @@ void kaldo_destroy(kaldo_ctx ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  prof_clear(ctx);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -352,6 +392,25 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
   kaldo_status st;
   if ((st = run_kappa_qhgk(ctx)) != KALDO_OK) return st;
   if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_profile_enable(kaldo_ctx ctx, int enable) {
+  if (!ctx) return KALDO_EINVAL;
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  prof_clear(ctx);
+  ctx->prof = enable != 0;
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_profile_read(kaldo_ctx ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel) return KALDO_EINVAL;
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  prof_collect(ctx);
+  auto it = ctx->prof_tab.find(kernel);
+  if (total_ms) *total_ms = it == ctx->prof_tab.end() ? 0.0 : it->second.total_ms;
+  if (launches) *launches = it == ctx->prof_tab.end() ? 0 : it->second.launches;
   return KALDO_OK;
 }
 

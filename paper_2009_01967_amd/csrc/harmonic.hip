@@ -201,24 +201,30 @@ kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity) {
     hipLaunchKernelGGL(k_dyn_assemble_real, dim3(blocks_for((long long)nn, T)), dim3(T), 0, st, Dr, pair,
                        ctx->d_fc2_val.as<double>(), ctx->d_masses.as<double>(), N);
     KALDO_HIP(ctx, hipGetLastError());
+    prof_begin(ctx);
     rocblas_status rs = rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, Dr, n,
                                          ctx->d_lambda.as<double>(), offd, info);
     if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_dsyevd failed");
+    prof_end(ctx, "eigensolve");
     hipLaunchKernelGGL(k_real_to_complex, dim3(blocks_for((long long)nn, T)), dim3(T), 0, st,
                        ctx->d_evec.as<zc>(), Dr, (long long)nn);
     KALDO_HIP(ctx, hipGetLastError());
   } else {
     zc* D = ctx->d_evec.as<zc>();
+    prof_begin(ctx);
     hipLaunchKernelGGL(k_dyn_assemble, dim3(blocks_for((long long)nn * nk, T)), dim3(T), 0, st, D, pair,
                        ctx->d_fc2_R.as<int>(), ctx->d_fc2_val.as<double>(), ctx->d_masses.as<double>(), N,
                        ctx->grid[0], ctx->grid[1], ctx->grid[2], nk);
     KALDO_HIP(ctx, hipGetLastError());
+    prof_end(ctx, "dyn_assemble");
     KALDO_HIP(ctx, ctx->d_dyn.ensure((size_t)nk * n * sizeof(double)));
+    prof_begin(ctx);
     rocblas_status rs = rocsolver_zheevd_strided_batched(
         ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, reinterpret_cast<rocblas_double_complex*>(D), n,
         (rocblas_stride)nn, ctx->d_lambda.as<double>(), (rocblas_stride)n, ctx->d_dyn.as<double>(),
         (rocblas_stride)n, info, nk);
     if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_zheevd_strided_batched failed");
+    prof_end(ctx, "eigensolve");
   }
   hipLaunchKernelGGL(k_modes, dim3(blocks_for(nk, T)), dim3(T), 0, st, ctx->d_lambda.as<double>(), info,
                      ctx->d_omega.as<double>(), ctx->d_work.as<double>(), ctx->d_setid.as<int>(), flag, nk, n);

@@ -6,6 +6,7 @@
 #include <rocblas/rocblas.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,16 @@ struct Fc3Layout {
 }  // namespace kaldo
 
 struct kaldo_ctx_s {
+  // kernel timing instrumentation
+  bool prof = false;
+  struct ProfEntry {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+  };
+  std::map<std::string, ProfEntry> prof_tab;
+  hipEvent_t prof_open = nullptr;
+
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -134,6 +145,11 @@ kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what);
     hipError_t _e = (call);                                           \
     if (_e != hipSuccess) return ::kaldo::hip_fail((ctx), _e, #call); \
   } while (0)
+
+// timing instrumentation around a launch (no-ops unless enabled)
+void prof_begin(kaldo_ctx ctx);
+void prof_end(kaldo_ctx ctx, const char* name);
+void prof_clear(kaldo_ctx ctx);
 
 // copy a device result into a caller pointer that may be host or device memory
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);

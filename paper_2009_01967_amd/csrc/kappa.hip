@@ -85,10 +85,12 @@ kaldo_status run_kappa_rta(kaldo_ctx ctx) {
   KALDO_HIP(ctx, ctx->d_partial.ensure((size_t)nT * nslice * 9 * sizeof(double)));
   double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  prof_begin(ctx);
   hipLaunchKernelGGL(k_kappa_rta, dim3(nslice, nT), dim3(256), 0, st, ctx->d_partial.as<double>(),
                      ctx->d_gamma.as<double>(), ctx->d_omega.as<double>(), ctx->d_vv.as<double>(), nmode, T03, T47,
                      ctx->stats == KALDO_CLASSICAL ? 1 : 0);
   KALDO_HIP(ctx, hipGetLastError());
+  prof_end(ctx, "kappa_rta");
   const double scale = kKappaSI / (ctx->nk * cell_volume(ctx->cell));
   hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(),
                      ctx->d_partial.as<double>(), nslice, nT, scale);
@@ -189,9 +191,11 @@ kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
   const int nslice = 64;
   double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  prof_begin(ctx);
   hipLaunchKernelGGL(k_qhgk_pairs, dim3(nslice, nT), dim3(256), 0, st, part, M, ctx->d_omega.as<double>(),
                      ctx->d_gamma.as<double>(), n, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
   KALDO_HIP(ctx, hipGetLastError());
+  prof_end(ctx, "kappa_qhgk");
   KALDO_HIP(ctx, ctx->d_kappa.ensure((size_t)nT * 9 * sizeof(double)));
   hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(), part, nslice, nT,
                      kKappaSI / cell_volume(ctx->cell));

@@ -38,7 +38,8 @@ STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALD
                 -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
 
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
-            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk"]
+            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_profile_enable",
+            "kaldo_profile_read"]
 
 
 class kaldo_structure(C.Structure):
@@ -90,6 +91,10 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
+    lib.kaldo_profile_enable.argtypes = [C.c_void_p, C.c_int]
+    lib.kaldo_profile_enable.restype = C.c_int
+    lib.kaldo_profile_read.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.kaldo_profile_read.restype = C.c_int
     _lib = lib
     return lib
 
@@ -201,6 +206,19 @@ def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
 
 def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_qhgk(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_profile_enable(ctx, enable: bool = True) -> int:
+    return load_library().kaldo_profile_enable(ctx, 1 if enable else 0)
+
+
+def kaldo_profile_read(ctx, kernel: str):
+    """(total_ms, launches) of a named kernel since profiling was enabled."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    st = load_library().kaldo_profile_read(ctx, kernel.encode(), C.byref(ms), C.byref(n))
+    _check(ctx, st)
+    return ms.value, n.value
 
 
 # ---- convenience context ---------------------------------------------------------
