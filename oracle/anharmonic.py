@@ -179,6 +179,9 @@ def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset
     T = np.atleast_1d(np.asarray(T, dtype=float))
     n = crystal.n_modes
     E = ph.eigvec[0]
+    if not np.any(E.imag):
+        # real eigenvectors at Gamma: same numbers, real arithmetic (contiguous for BLAS)
+        E = np.ascontiguousarray(E.real)
     w = ph.omega[0]
     mask = ph.mask[0]
     sig = units.TWO_PI * sigma_thz
@@ -195,7 +198,7 @@ def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset
             continue
         ea = E[3 * crystal.fc3_i[:, None] + np.arange(3)[None, :], s]        # (nb, 3)
         contrib = np.einsum('bx,bxyz->byz', ea, vals)                          # (nb, 3, 3)
-        F = np.zeros((n, n), dtype=np.complex128)
+        F = np.zeros((n, n), dtype=contrib.dtype)
         np.add.at(F, (rows.ravel(), cols.ravel()), contrib.ravel())
         w2 = w[:, None]
         w3 = w[None, :]

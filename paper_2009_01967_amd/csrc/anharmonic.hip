@@ -385,6 +385,7 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
 
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision) {
   const int n = ctx->nm;
+  if (ctx->nk == 1) return run_linewidths_gamma(ctx, sigma_thz, precision);
   if (n == 3 || n == 6) {
     if (precision == KALDO_FP64) return linewidths_small<double>(ctx, sigma_thz);
     if (precision == KALDO_FP32) return linewidths_small<float>(ctx, sigma_thz);

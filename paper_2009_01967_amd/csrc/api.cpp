@@ -224,6 +224,30 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
     L.delta.assign(3, 0);
     nd = 1;
   }
+  // Gamma-point layout: blocks grouped by atom pair (j, l), all cells merged
+  std::vector<int64_t> gorder(nb);
+  std::iota(gorder.begin(), gorder.end(), 0);
+  std::stable_sort(gorder.begin(), gorder.end(), [&](int64_t x, int64_t y) {
+    return std::make_pair(f->j[x], f->l[x]) < std::make_pair(f->j[y], f->l[y]);
+  });
+  std::vector<int> gpstart, gpl, grow(N + 1, 0), gbi(std::max<int64_t>(nb, 1));
+  std::vector<double> gval(27 * std::max<int64_t>(nb, 1), 0.0);
+  for (int64_t q = 0; q < nb; ++q) {
+    const int64_t b = gorder[q];
+    const bool fresh = q == 0 || f->j[b] != f->j[gorder[q - 1]] || f->l[b] != f->l[gorder[q - 1]];
+    if (fresh) {
+      gpstart.push_back((int)q);
+      gpl.push_back(f->l[b]);
+      grow[f->j[b] + 1] += 1;
+    }
+    gbi[q] = f->i[b];
+    const double s = 1.0 / std::sqrt(ctx->masses[f->i[b]] * ctx->masses[f->j[b]] * ctx->masses[f->l[b]]);
+    for (int c = 0; c < 27; ++c) gval[27 * q + c] = f->blocks[27 * b + c] * s;
+  }
+  const int npairs = (int)gpl.size();
+  gpstart.push_back((int)nb);
+  for (int a = 0; a < N; ++a) grow[a + 1] += grow[a];
+  if (gpl.empty()) gpl.push_back(0);
   kaldo_status st;
   if ((st = upload(ctx, L.d_group, group.data(), group.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_blk_i, bi.data(), bi.size())) != KALDO_OK) return st;
@@ -232,6 +256,12 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
   if ((st = upload(ctx, L.d_blk_R2, R2.data(), R2.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_blk_val, val.data(), val.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_delta, L.delta.data(), L.delta.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_gpair_start, gpstart.data(), gpstart.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_gpair_l, gpl.data(), gpl.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_grow_start, grow.data(), grow.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_gblk_i, gbi.data(), gbi.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_gblk_val, gval.data(), gval.size())) != KALDO_OK) return st;
+  L.n_pairs = npairs;
   L.n_blocks = nb;
   L.n_delta = nd;
   ctx->have_fc3 = true;

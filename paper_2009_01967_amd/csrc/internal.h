@@ -65,8 +65,15 @@ struct Fc3Layout {
   DevBuf d_blk_R2;                   // int  [nb][3]
   DevBuf d_blk_val;                  // double [nb][27], divided by sqrt(m_i m_j m_l)
   DevBuf d_delta;                    // int  [nD][3]
-  // Raw block list for the Gamma-point sparse path (same order).
+  // Raw block list (same order as above).
   DevBuf d_blk_j, d_blk_l;           // int [nb]
+  // Gamma-point layout: blocks sorted by the atom pair (j, l), all cells merged.
+  int n_pairs = 0;
+  DevBuf d_gpair_start;              // int [npairs + 1] -> block range of each pair
+  DevBuf d_gpair_l;                  // int [npairs] atom l of each pair
+  DevBuf d_grow_start;               // int [N + 1] -> pair range of each row atom j
+  DevBuf d_gblk_i;                   // int [nb]
+  DevBuf d_gblk_val;                 // double [nb][27], divided by sqrt(m_i m_j m_l)
 };
 
 }  // namespace kaldo
@@ -157,6 +164,7 @@ kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
 // stages ------------------------------------------------------------------------
 kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity);
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision);
+kaldo_status run_linewidths_gamma(kaldo_ctx ctx, double sigma_thz, int precision);
 kaldo_status run_kappa_rta(kaldo_ctx ctx);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 
