@@ -53,6 +53,154 @@ __global__ void k_dyn_assemble_real(double* __restrict__ D, const int2* __restri
   D[(size_t)b * n + a] = s * kEvUnit / sqrt(mass[i] * mass[j]);
 }
 
+// Batched FP64 Hermitian eigensolver for small n (<= kJacobiMaxN): cyclic
+// two-sided Jacobi with the round-robin ordering, one block per k, matrix in
+// LDS.  Each rotation first turns the (p, q) element real with a phase, then
+// applies the real symmetric Jacobi rotation; the n/2 rotations of a round act
+// on disjoint index pairs and are applied together.  On exit D[k] holds the
+// eigenvectors (column s = eta_s, contiguous) and lambda[k] the ascending
+// eigenvalues.  info[k] = 1 if the sweep limit was reached.
+constexpr int kJacobiMaxN = 32;
+
+template <int kJacobiMaxN>
+__global__ void __launch_bounds__(64) k_jacobi_hermitian(zc* __restrict__ D, double* __restrict__ lambda,
+                                                         int* __restrict__ info, int n) {
+  __shared__ zc A[kJacobiMaxN * kJacobiMaxN];
+  __shared__ zc V[kJacobiMaxN * kJacobiMaxN];
+  __shared__ double rc[kJacobiMaxN / 2], rs[kJacobiMaxN / 2];
+  __shared__ zc ru[kJacobiMaxN / 2];
+  __shared__ int rp[kJacobiMaxN / 2], rq[kJacobiMaxN / 2];
+  __shared__ double red[64];
+  __shared__ int done;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int m = (n + 1) & ~1;  // even size for the round-robin schedule (index n is a dummy)
+  zc* Dk = D + (size_t)k * n * n;
+  for (int e = tid; e < n * n; e += 64) {
+    const int a = e % n, b = e / n;  // column major input, Hermitian part (D + D^H) / 2
+    const zc x = Dk[e], y = Dk[(size_t)a * n + b];
+    A[a * kJacobiMaxN + b] = {0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
+    V[a * kJacobiMaxN + b] = {a == b ? 1.0 : 0.0, 0.0};
+  }
+  if (tid == 0) done = 0;
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
+    // convergence test on the off-diagonal norm
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += 64) {
+      const int a = e / n, b = e % n;
+      const zc v = A[a * kJacobiMaxN + b];
+      const double x = v.re * v.re + v.im * v.im;
+      tot += x;
+      if (a != b) off += x;
+    }
+    red[tid] = off;
+    __syncthreads();
+    if (tid == 0) {
+      double so = 0.0;
+      for (int t = 0; t < 64; ++t) so += red[t];
+      red[0] = so;
+    }
+    __syncthreads();
+    const double soff = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    if (tid == 0) {
+      double st = 0.0;
+      for (int t = 0; t < 64; ++t) st += red[t];
+      const double eps = 4.0 * n * 2.220446049250313e-16;  // relative off-diagonal norm target
+      done = soff <= eps * eps * st;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < m - 1; ++round) {
+      // round-robin pairs: position 0 fixed, the others rotate
+      if (tid < m / 2) {
+        auto slot = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
+        int p = slot(tid), q = slot(m - 1 - tid);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        rp[tid] = p;
+        rq[tid] = q;
+        double c = 1.0, s = 0.0;
+        zc u = {1.0, 0.0};
+        if (q < n) {
+          const zc apq = A[p * kJacobiMaxN + q];
+          const double mag = sqrt(apq.re * apq.re + apq.im * apq.im);
+          if (mag > 0.0) {
+            u = {apq.re / mag, apq.im / mag};
+            const double app = A[p * kJacobiMaxN + p].re, aqq = A[q * kJacobiMaxN + q].re;
+            const double theta = (aqq - app) / (2.0 * mag);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        rc[tid] = c;
+        rs[tid] = s;
+        ru[tid] = u;
+      }
+      __syncthreads();
+      // columns: col_p <- c col_p - s conj(u) col_q ; col_q <- s col_p + c conj(u) col_q  (A and V)
+      for (int e = tid; e < (m / 2) * n; e += 64) {
+        const int pr = e / n, r = e % n;
+        const int p = rp[pr], q = rq[pr];
+        if (q >= n) continue;
+        const double c = rc[pr], s = rs[pr];
+        const zc ub = {ru[pr].re, -ru[pr].im};
+        for (int w = 0; w < 2; ++w) {
+          zc* M = w == 0 ? A : V;
+          const zc xp = M[r * kJacobiMaxN + p], xq = M[r * kJacobiMaxN + q];
+          const zc uq = cmul(ub, xq);
+          M[r * kJacobiMaxN + p] = {c * xp.re - s * uq.re, c * xp.im - s * uq.im};
+          M[r * kJacobiMaxN + q] = {s * xp.re + c * uq.re, s * xp.im + c * uq.im};
+        }
+      }
+      __syncthreads();
+      // rows of A: row_p <- c row_p - s u row_q ; row_q <- s row_p + c u row_q
+      for (int e = tid; e < (m / 2) * n; e += 64) {
+        const int pr = e / n, col = e % n;
+        const int p = rp[pr], q = rq[pr];
+        if (q >= n) continue;
+        const double c = rc[pr], s = rs[pr];
+        const zc u = ru[pr];
+        const zc xp = A[p * kJacobiMaxN + col], xq = A[q * kJacobiMaxN + col];
+        const zc uq = cmul(u, xq);
+        A[p * kJacobiMaxN + col] = {c * xp.re - s * uq.re, c * xp.im - s * uq.im};
+        A[q * kJacobiMaxN + col] = {s * xp.re + c * uq.re, s * xp.im + c * uq.im};
+      }
+      __syncthreads();
+      // keep A exactly Hermitian: lower triangle from the upper one, real diagonal
+      for (int e = tid; e < n * n; e += 64) {
+        const int r = e / n, col = e % n;
+        if (r > col) {
+          const zc u = A[col * kJacobiMaxN + r];
+          A[r * kJacobiMaxN + col] = {u.re, -u.im};
+        } else if (r == col) {
+          A[r * kJacobiMaxN + r].im = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order by rank (ties broken by index), eigenvector s contiguous
+  for (int s = tid; s < n; s += 64) {
+    const double ls = A[s * kJacobiMaxN + s].re;
+    int rank = 0;
+    for (int t = 0; t < n; ++t) {
+      const double lt = A[t * kJacobiMaxN + t].re;
+      rank += (lt < ls) || (lt == ls && t < s);
+    }
+    lambda[(size_t)k * n + rank] = ls;
+    for (int a = 0; a < n; ++a) Dk[(size_t)rank * n + a] = V[a * kJacobiMaxN + s];
+  }
+  if (tid == 0) info[k] = done ? 0 : 1;
+}
+
 __global__ void k_real_to_complex(zc* __restrict__ out, const double* __restrict__ in, long long count) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) out[idx] = {in[idx], 0.0};
@@ -219,11 +367,21 @@ kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity) {
     prof_end(ctx, "dyn_assemble");
     KALDO_HIP(ctx, ctx->d_dyn.ensure((size_t)nk * n * sizeof(double)));
     prof_begin(ctx);
-    rocblas_status rs = rocsolver_zheevd_strided_batched(
-        ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, reinterpret_cast<rocblas_double_complex*>(D), n,
-        (rocblas_stride)nn, ctx->d_lambda.as<double>(), (rocblas_stride)n, ctx->d_dyn.as<double>(),
-        (rocblas_stride)n, info, nk);
-    if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_zheevd_strided_batched failed");
+    if (n <= kJacobiMaxN) {
+      if (n <= 8)
+        hipLaunchKernelGGL(k_jacobi_hermitian<8>, dim3(nk), dim3(64), 0, st, D, ctx->d_lambda.as<double>(), info, n);
+      else if (n <= 16)
+        hipLaunchKernelGGL(k_jacobi_hermitian<16>, dim3(nk), dim3(64), 0, st, D, ctx->d_lambda.as<double>(), info, n);
+      else
+        hipLaunchKernelGGL(k_jacobi_hermitian<32>, dim3(nk), dim3(64), 0, st, D, ctx->d_lambda.as<double>(), info, n);
+      KALDO_HIP(ctx, hipGetLastError());
+    } else {
+      rocblas_status rs = rocsolver_zheevd_strided_batched(
+          ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, reinterpret_cast<rocblas_double_complex*>(D), n,
+          (rocblas_stride)nn, ctx->d_lambda.as<double>(), (rocblas_stride)n, ctx->d_dyn.as<double>(),
+          (rocblas_stride)n, info, nk);
+      if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_zheevd_strided_batched failed");
+    }
     prof_end(ctx, "eigensolve");
   }
   hipLaunchKernelGGL(k_modes, dim3(blocks_for(nk, T)), dim3(T), 0, st, ctx->d_lambda.as<double>(), info,

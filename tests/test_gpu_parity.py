@@ -60,6 +60,21 @@ def test_phonon_frequencies_and_velocities(small_diamond):
                 assert d < 1e-9 * max(1.0, np.abs(ph.velocity).max()), (kk, S[0], d)
 
 
+def test_two_species_eigenvalues_all_k():
+    """Exact degeneracies at zone-boundary points with two masses (the batched
+    Jacobi eigensolver must keep its matrix Hermitian to resolve them)."""
+    c = diamond_si(grid=(4, 4, 4), rc3=2.6, masses=(M_SI, M_GE), seed=7)
+    _say("case: two-species diamond 4x4x4 eigenvalues")
+    ph = P.phonons(c, velocities=False)
+    with _ctx() as ctx:
+        nu = ctx.phonons(c)
+    lam = np.sign(nu) * nu ** 2
+    lam_ref = np.sign(ph.nu) * ph.nu ** 2
+    err = float(np.max(np.abs(lam - lam_ref)) / np.abs(lam_ref).max())
+    print(f"  eigenvalue error {err:.3e}", flush=True)
+    assert err < 1e-12, err
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_linewidths_and_kappa_small_diamond(small_diamond, precision):
     c, w, ph, g, k = small_diamond
