@@ -112,9 +112,13 @@ def projection(crystal, ph, k, sign, kps=None):
     Ek = ph.eigvec[k]
     Ep = ph.eigvec[kps] if sign > 0 else ph.eigvec[kps].conj()
     Epp = ph.eigvec[kpps].conj()
-    X = np.einsum('kabc,as->ksbc', F, Ek, optimize=True)
-    Y = np.einsum('ksbc,kbt->kstc', X, Ep, optimize=True)
-    V = np.einsum('kstc,kcu->kstu', Y, Epp, optimize=True)
+    # the three contractions (over a, then a', then a''), each as a (batched) matmul
+    nkp, n = F.shape[0], F.shape[1]
+    X = np.tensordot(F, Ek, axes=([1], [0]))                       # [k', a', a'', s]
+    Y = np.matmul(np.swapaxes(Ep, 1, 2), X.reshape(nkp, n, n * n))  # [k', s', (a'', s)]
+    Y = Y.reshape(nkp, n, n, n).transpose(0, 1, 3, 2)               # [k', s', s, a'']
+    V = np.matmul(Y.reshape(nkp, n * n, n), Epp)                   # [k', (s', s), s'']
+    V = V.reshape(nkp, n, n, n).transpose(0, 2, 1, 3)               # [k', s, s', s'']
     return V, kpps
 
 
@@ -135,23 +139,27 @@ def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, averag
     sig = units.TWO_PI * sigma_thz
     pref = rate_prefactor()
     out = np.zeros((len(T), len(ks), n))
+    # partners k' are processed in chunks that bound the dense tensor to ~256 MB
+    chunk = max(1, int(2 ** 28 // (16 * n ** 3)))
     for ik, k in enumerate(ks):
         w = ph.omega[k]
         mk = ph.mask[k]
         acc = np.zeros((len(T), n))
         for sign in (+1, -1):
-            V, kpps = projection(crystal, ph, k, sign)
-            V2 = np.abs(V) ** 2                                 # (nk', s, s', s'')
+          for c0 in range(0, ph.n_k, chunk):
+            kps = np.arange(c0, min(ph.n_k, c0 + chunk))
+            V, kpps = projection(crystal, ph, k, sign, kps=kps)
+            V2 = np.abs(V) ** 2                                 # (k' chunk, s, s', s'')
             w1 = w[None, :, None, None]
-            w2 = ph.omega[:, None, :, None]                     # k' = all, in order
+            w2 = ph.omega[kps][:, None, :, None]
             w3 = ph.omega[kpps][:, None, None, :]
-            m3 = (mk[None, :, None, None] & ph.mask[:, None, :, None]
+            m3 = (mk[None, :, None, None] & ph.mask[kps][:, None, :, None]
                   & ph.mask[kpps][:, None, None, :])
             with np.errstate(divide='ignore', invalid='ignore'):
                 inv = np.where(m3, 1.0 / (w1 * w2 * w3), 0.0)
             delta = gaussian_delta(w1 + sign * w2 - w3, sig)
             for it, t in enumerate(T):
-                n2 = np.where(ph.mask[:, None, :, None], occupation(w2, t, stats), 0.0)
+                n2 = np.where(ph.mask[kps][:, None, :, None], occupation(w2, t, stats), 0.0)
                 n3 = np.where(ph.mask[kpps][:, None, None, :], occupation(w3, t, stats), 0.0)
                 if sign > 0:
                     g = (n2 - n3) * delta

@@ -383,9 +383,33 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   return KALDO_OK;
 }
 
+// Mode tables and the Delta phase table (FP64) for the many-branch crystal path.
+kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double** OCC, cplx<double>** PH) {
+  const int n = ctx->nm, nk = ctx->nk, nT = ctx->nT, nd = ctx->fc3.n_delta;
+  hipStream_t st = ctx->stream;
+  const int TB = 256;
+  const size_t nmode = (size_t)nk * n;
+  KALDO_HIP(ctx, ctx->d_tabs.ensure((2 + (size_t)nT) * nmode * sizeof(double) +
+                                    (size_t)nd * nk * sizeof(cplx<double>)));
+  *OM = ctx->d_tabs.as<double>();
+  *IW = *OM + nmode;
+  *OCC = *IW + nmode;
+  *PH = reinterpret_cast<cplx<double>*>(*OCC + (size_t)nT * nmode);
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  hipLaunchKernelGGL(k_tables, dim3(blocks_for((long long)nmode, TB)), dim3(TB), 0, st, *OM, *IW, *OCC,
+                     ctx->d_omega.as<double>(), nk, n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL((k_delta_phase<double>), dim3(blocks_for((long long)nd * nk, TB)), dim3(TB), 0, st, *PH,
+                     ctx->fc3.d_delta.as<int>(), nd, ctx->grid[0], ctx->grid[1], ctx->grid[2]);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision) {
   const int n = ctx->nm;
   if (ctx->nk == 1) return run_linewidths_gamma(ctx, sigma_thz, precision);
+  if (n > 6 || precision == KALDO_BF16X3) return run_linewidths_crystal(ctx, sigma_thz, precision);
   if (n == 3 || n == 6) {
     if (precision == KALDO_FP64) return linewidths_small<double>(ctx, sigma_thz);
     if (precision == KALDO_FP32) return linewidths_small<float>(ctx, sigma_thz);

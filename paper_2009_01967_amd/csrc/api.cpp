@@ -224,6 +224,42 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
     L.delta.assign(3, 0);
     nd = 1;
   }
+  // crystal layout: non-empty (Delta, j, l) groups and their per-pair lists
+  std::vector<int> cg_block, cg_delta, cg_j, cg_l;
+  for (int d = 0; d < nd; ++d)
+    for (int j = 0; j < N; ++j)
+      for (int l = 0; l < N; ++l) {
+        const size_t g = ((size_t)d * N + j) * N + l;
+        if (group[2 * g + 1] > group[2 * g]) {
+          cg_block.push_back(group[2 * g]);
+          cg_block.push_back(group[2 * g + 1]);
+          cg_delta.push_back(d);
+          cg_j.push_back(j);
+          cg_l.push_back(l);
+        }
+      }
+  const int ng = (int)cg_delta.size();
+  std::vector<int> cg_order(ng);
+  std::iota(cg_order.begin(), cg_order.end(), 0);
+  std::stable_sort(cg_order.begin(), cg_order.end(), [&](int x, int y) {
+    return std::make_tuple(cg_j[x], cg_l[x], cg_delta[x]) < std::make_tuple(cg_j[y], cg_l[y], cg_delta[y]);
+  });
+  std::vector<int> cpair;  // (j, l, first, last+1)
+  for (int q = 0; q < ng; ++q) {
+    const int g = cg_order[q];
+    if (q == 0 || cg_j[g] != cg_j[cg_order[q - 1]] || cg_l[g] != cg_l[cg_order[q - 1]]) {
+      cpair.insert(cpair.end(), {cg_j[g], cg_l[g], q, q + 1});
+    } else {
+      cpair.back() = q + 1;
+    }
+  }
+  const int ncp = (int)cpair.size() / 4;
+  if (ng == 0) {
+    cg_block.assign(2, 0);
+    cg_delta.assign(1, 0);
+    cg_order.assign(1, 0);
+  }
+  if (ncp == 0) cpair.assign(4, 0);
   // Gamma-point layout: blocks grouped by atom pair (j, l), all cells merged
   std::vector<int64_t> gorder(nb);
   std::iota(gorder.begin(), gorder.end(), 0);
@@ -261,6 +297,12 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
   if ((st = upload(ctx, L.d_grow_start, grow.data(), grow.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_gblk_i, gbi.data(), gbi.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_gblk_val, gval.data(), gval.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_cg_block, cg_block.data(), cg_block.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_cg_delta, cg_delta.data(), cg_delta.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_cg_order, cg_order.data(), cg_order.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_cpair, cpair.data(), cpair.size())) != KALDO_OK) return st;
+  L.n_cgroups = ng;
+  L.n_cpairs = ncp;
   L.n_pairs = npairs;
   L.n_blocks = nb;
   L.n_delta = nd;

@@ -17,12 +17,9 @@
 
 #include "common.h"
 #include "internal.h"
+#include "mfma.h"
 
 namespace kaldo {
-
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
 constexpr int kTile = 64;  // output tile (rows s', columns s'') per block
 
@@ -50,34 +47,6 @@ __global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E
 }
 
 // ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] in the GEMM operand format ---------
-template <int P>
-struct Operand;
-template <>
-struct Operand<KALDO_FP64> {
-  using T = double;
-};
-template <>
-struct Operand<KALDO_FP32> {
-  using T = float;
-};
-template <>
-struct Operand<KALDO_BF16X3> {
-  using T = __bf16;
-};
-
-template <int P>
-__device__ __forceinline__ void store_operand(typename Operand<P>::T* hi, typename Operand<P>::T* lo, size_t o,
-                                              double v) {
-  if constexpr (P == KALDO_BF16X3) {
-    const float f = (float)v;
-    const __bf16 h = (__bf16)f;
-    hi[o] = h;
-    lo[o] = (__bf16)(f - (float)h);
-  } else {
-    hi[o] = (typename Operand<P>::T)v;
-  }
-}
-
 template <int P>
 __global__ void k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
                           const double* __restrict__ Xs, const double* __restrict__ E,

@@ -376,11 +376,11 @@ kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity) {
         hipLaunchKernelGGL(k_jacobi_hermitian<32>, dim3(nk), dim3(64), 0, st, D, ctx->d_lambda.as<double>(), info, n);
       KALDO_HIP(ctx, hipGetLastError());
     } else {
-      rocblas_status rs = rocsolver_zheevd_strided_batched(
+      rocblas_status rs = rocsolver_zheev_strided_batched(
           ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, reinterpret_cast<rocblas_double_complex*>(D), n,
           (rocblas_stride)nn, ctx->d_lambda.as<double>(), (rocblas_stride)n, ctx->d_dyn.as<double>(),
           (rocblas_stride)n, info, nk);
-      if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_zheevd_strided_batched failed");
+      if (rs != rocblas_status_success) return fail(ctx, KALDO_EDEVICE, "rocsolver_zheev_strided_batched failed");
     }
     prof_end(ctx, "eigensolve");
   }

@@ -67,6 +67,13 @@ struct Fc3Layout {
   DevBuf d_delta;                    // int  [nD][3]
   // Raw block list (same order as above).
   DevBuf d_blk_j, d_blk_l;           // int [nb]
+  // Crystal layout for many branches: the non-empty (Delta, j, l) groups, and
+  // per atom pair (j, l) the list of its groups (sorted by Delta).
+  int n_cgroups = 0, n_cpairs = 0;
+  DevBuf d_cg_block;                 // int2 [ng] block range (in the (Delta, j, l) order)
+  DevBuf d_cg_delta;                 // int [ng] Delta index
+  DevBuf d_cg_order;                 // int [ng] group indices sorted by (j, l, Delta)
+  DevBuf d_cpair;                    // int4 [np] (j, l, first, last+1) into d_cg_order
   // Gamma-point layout: blocks sorted by the atom pair (j, l), all cells merged.
   int n_pairs = 0;
   DevBuf d_gpair_start;              // int [npairs + 1] -> block range of each pair
@@ -165,6 +172,7 @@ kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
 kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity);
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision);
 kaldo_status run_linewidths_gamma(kaldo_ctx ctx, double sigma_thz, int precision);
+kaldo_status run_linewidths_crystal(kaldo_ctx ctx, double sigma_thz, int precision);
 kaldo_status run_kappa_rta(kaldo_ctx ctx);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 

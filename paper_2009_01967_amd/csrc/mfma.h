@@ -1,0 +1,64 @@
+// Operand types and MFMA helpers shared by the GEMM-shaped projection kernels.
+//
+// Lane layouts of the gfx950 MFMA instructions used here (checked on the device):
+//   f32 16x16x4:   lane l supplies A[l%16][l/16] and B[l/16][l%16];
+//                  accumulator register r of lane l is C[4*(l/16) + r][l%16]
+//   f64 16x16x4:   same inputs; accumulator register r of lane l is C[l/16 + 4*r][l%16]
+//   bf16 16x16x32: lane l supplies A[l%16][8*(l/16) .. +7] and B[8*(l/16) .. +7][l%16];
+//                  accumulators as f32 16x16x4
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "../../include/kaldo.h"
+
+namespace kaldo {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+
+template <int P>
+struct Operand;
+template <>
+struct Operand<KALDO_FP64> {
+  using T = double;
+  using Acc = f64x4;
+  static constexpr int split = 1;
+};
+template <>
+struct Operand<KALDO_FP32> {
+  using T = float;
+  using Acc = f32x4;
+  static constexpr int split = 1;
+};
+template <>
+struct Operand<KALDO_BF16X3> {
+  using T = __bf16;
+  using Acc = f32x4;
+  static constexpr int split = 2;  // hi and lo planes
+};
+
+// Store v into an operand plane; for BF16X3 as hi = bf16(v), lo = bf16(v - hi).
+template <int P>
+__device__ __forceinline__ void store_operand(typename Operand<P>::T* hi, typename Operand<P>::T* lo, size_t o,
+                                              double v) {
+  if constexpr (P == KALDO_BF16X3) {
+    const float f = (float)v;
+    const __bf16 h = (__bf16)f;
+    hi[o] = h;
+    lo[o] = (__bf16)(f - (float)h);
+  } else {
+    hi[o] = (typename Operand<P>::T)v;
+  }
+}
+
+// accumulator row of register r in lane l for a 16x16 tile
+template <int P>
+__device__ __forceinline__ int acc_row(int lane, int r) {
+  return P == KALDO_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+}
+
+}  // namespace kaldo
