@@ -87,6 +87,11 @@ typedef enum {
   KALDO_CLASSICAL = 1   /* n = k_B T / (hbar omega) (Sec. II.D) */
 } kaldo_stats;
 
+typedef enum {
+  KALDO_TUNE_AUTO = 0,  /* time the candidate tile shapes of each GEMM problem once, keep the fastest */
+  KALDO_TUNE_FIXED = 1  /* fixed tile shapes: results bitwise reproducible across contexts */
+} kaldo_tuning;
+
 /* At most this many temperatures per kaldo_linewidths call. */
 #define KALDO_MAX_T 8
 
@@ -144,7 +149,9 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
  *   sigma_thz  Gaussian width (standard deviation) in THz, > 0
  *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
  *              resident for kaldo_kappa_*)
- * KALDO_BF16X3 is accepted only for grids {1,1,1} (the Gamma-point path). */
+ * Every precision is accepted on every grid.  Cells with n = 3 or 6 branches
+ * and grid != {1,1,1} use a few-branch VALU kernel for FP64 and FP32; all
+ * other cases run the projection as MFMA GEMMs (Gamma: real, else complex). */
 kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
                               double sigma_thz, kaldo_delta delta, kaldo_stats stats,
                               kaldo_precision precision, double* gamma_out);
@@ -161,6 +168,14 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
  * (hbar w w'/T)(n' - n)/(w - w'); generalised velocity summed over fc2 blocks
  * with the displacement x_i - (x_j + R.cell). */
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
+
+/* Tile-shape selection for the MFMA GEMMs (not a step of the method).  With
+ * KALDO_TUNE_AUTO (the default) the first call that meets a GEMM shape times
+ * each candidate tile shape once and keeps the fastest for the context; the
+ * results of different tile shapes agree to rounding, not bitwise.
+ * KALDO_TUNE_FIXED uses one fixed shape per problem.  Returns KALDO_EINVAL for
+ * an unknown mode. */
+kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
 
 /* Kernel timing instrumentation (not a step of the method).  While enabled,
  * the library records a pair of HIP events on the context's stream around

@@ -9,6 +9,7 @@
 #include <tuple>
 
 #include "internal.h"
+#include "tune.h"
 
 namespace kaldo {
 
@@ -60,6 +61,35 @@ void prof_clear(kaldo_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   prof_collect(ctx);
   ctx->prof_tab.clear();
+}
+
+int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const std::function<void(int)>& launch) {
+  if (ctx->tuning != KALDO_TUNE_AUTO || nv <= 1) return fallback;
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) return it->second;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fallback;
+  }
+  int best = fallback;
+  float best_ms = 0.0f;
+  for (int v = 0; v < nv; ++v) {
+    launch(v);
+    (void)hipEventRecord(e0, ctx->stream);
+    launch(v);
+    (void)hipEventRecord(e1, ctx->stream);
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+    if (v == 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tuned[key] = best;
+  return best;
 }
 
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {
@@ -259,6 +289,8 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
     cg_delta.assign(1, 0);
     cg_order.assign(1, 0);
   }
+  std::vector<int> cpairmap((size_t)N * N, -1);
+  for (int c = 0; c < ncp; ++c) cpairmap[(size_t)cpair[4 * c] * N + cpair[4 * c + 1]] = c;
   if (ncp == 0) cpair.assign(4, 0);
   // Gamma-point layout: blocks grouped by atom pair (j, l), all cells merged
   std::vector<int64_t> gorder(nb);
@@ -301,6 +333,7 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
   if ((st = upload(ctx, L.d_cg_delta, cg_delta.data(), cg_delta.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_cg_order, cg_order.data(), cg_order.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_cpair, cpair.data(), cpair.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, L.d_cpairmap, cpairmap.data(), cpairmap.size())) != KALDO_OK) return st;
   L.n_cgroups = ng;
   L.n_cpairs = ncp;
   L.n_pairs = npairs;
@@ -464,6 +497,15 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
   kaldo_status st;
   if ((st = run_kappa_qhgk(ctx)) != KALDO_OK) return st;
   if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode) {
+  if (!ctx) return KALDO_EINVAL;
+  if (mode != KALDO_TUNE_AUTO && mode != KALDO_TUNE_FIXED)
+    return fail(ctx, KALDO_EINVAL, "kaldo_set_tuning: unknown mode");
+  ctx->tuning = mode;
+  ctx->tuned.clear();
   return KALDO_OK;
 }
 

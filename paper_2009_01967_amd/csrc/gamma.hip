@@ -7,32 +7,36 @@
 //   X_s[a'][a''] = sum_a eta_s[a] phi[a,a',a''] / sqrt(m m' m'')     (sparse, symmetric)
 //   Y_s = X_s E                                                    (sparse x dense)
 //   V_s = E^T Y_s                                                  (dense GEMM, MFMA)
-// and the epilogue of the crystal path is fused into the GEMM: V never leaves
-// registers; each tile is reduced to one partial linewidth per temperature.
+// The GEMM runs on the shared MFMA core with the linewidth epilogue fused in:
+// V never leaves registers; each block tile is reduced to one partial sum per
+// output column and temperature.
 //
 // Precisions of the GEMM: FP64 (f64 MFMA), FP32 (f32 MFMA), BF16X3 (each
 // operand split into bf16 hi + lo, three bf16 MFMAs hi*hi + hi*lo + lo*hi with
-// FP32 accumulation).  Mode tables, occupations and all sums stay FP64.
+// FP32 accumulation).  X_s and Y_s are formed in FP64; mode tables,
+// occupations and every sum past the tile stay FP64.
 #include <algorithm>
+#include <string>
 
 #include "common.h"
+#include "gemm.h"
 #include "internal.h"
 #include "mfma.h"
+#include "tune.h"
 
 namespace kaldo {
 
-constexpr int kTile = 64;  // output tile (rows s', columns s'') per block
-
 // ---- X_s: contract fc3 with eta_s over the home atom ---------------------------------
-// Xs[sl][pair][beta][gamma]; pairs are the distinct (j, l) atom pairs.
+// Xs[pair][sl][beta][gamma] for sl < sbp (zero where s0 + sl >= n); pairs are the
+// distinct (j, l) atom pairs.  E is column major: eta_s[a] = E[s * n + a].
 __global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E, const int* __restrict__ pstart,
                            const int* __restrict__ gi, const double* __restrict__ gval, int n, int npairs, int s0,
-                           int sb) {
+                           int sbp) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)sb * npairs * 9) return;
+  if (idx >= (long long)sbp * npairs * 9) return;
   const int e9 = (int)(idx % 9);
-  const int pr = (int)((idx / 9) % npairs);
-  const int sl = (int)(idx / (9LL * npairs));
+  const int sl = (int)((idx / 9) % sbp);
+  const int pr = (int)(idx / (9LL * sbp));
   const int s = s0 + sl;
   double v = 0.0;
   if (s < n) {
@@ -46,231 +50,162 @@ __global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E
   Xs[idx] = v;
 }
 
-// ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] in the GEMM operand format ---------
-template <int P>
-__global__ void k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
-                          const double* __restrict__ Xs, const double* __restrict__ E,
-                          const int* __restrict__ rstart, const int* __restrict__ pl, int n, int N, int npairs,
-                          int npad, int s0, int sb) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)sb * n * N) return;
-  const int j = (int)(idx % N);
-  const int s2 = (int)((idx / N) % n);
-  const int sl = (int)(idx / ((long long)N * n));
-  double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-  if (s0 + sl < n) {
-    const double* e = E + (size_t)s2 * n;
-    const double* xs = Xs + (size_t)sl * npairs * 9;
-    for (int p = rstart[j]; p < rstart[j + 1]; ++p) {
-      const double* x = xs + 9 * (size_t)p;
-      const int l3 = 3 * pl[p];
-      const double e0 = e[l3], e1 = e[l3 + 1], e2 = e[l3 + 2];
-      y0 += x[0] * e0 + x[1] * e1 + x[2] * e2;
-      y1 += x[3] * e0 + x[4] * e1 + x[5] * e2;
-      y2 += x[6] * e0 + x[7] * e1 + x[8] * e2;
-    }
-  }
-  const size_t o = ((size_t)sl * npad + s2) * npad + 3 * j;
-  store_operand<P>(Yhi, Ylo, o, y0);
-  store_operand<P>(Yhi, Ylo, o + 1, y1);
-  store_operand<P>(Yhi, Ylo, o + 2, y2);
-}
-
-// Et[s'][a] = E[a][s'] (the solver's column-major output), zero padded to npad x npad.
-template <int P>
-__global__ void k_gamma_et(typename Operand<P>::T* __restrict__ Ehi, typename Operand<P>::T* __restrict__ Elo,
-                           const double* __restrict__ E, int n, int npad) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)npad * npad) return;
-  const int a = (int)(idx % npad), s = (int)(idx / npad);
-  const double v = (a < n && s < n) ? E[(size_t)s * n + a] : 0.0;
-  store_operand<P>(Ehi, Elo, idx, v);
-}
-
-// ---- GEMM V_s = E^T Y_s with the fused epilogue ----------------------------------------
-struct GammaArgs {
-  int n, npad, nT, s0;
-  double c;  // 1 / (2 sigma^2)
-};
-
-template <int P>
-struct Kc;
-template <>
-struct Kc<KALDO_FP64> {
-  static constexpr int v = 16;
-};
-template <>
-struct Kc<KALDO_FP32> {
-  static constexpr int v = 32;
-};
-template <>
-struct Kc<KALDO_BF16X3> {
-  static constexpr int v = 64;
-};
-
-template <int P, int NT>
-__global__ void __launch_bounds__(256)
-    k_gamma_gemm(const typename Operand<P>::T* __restrict__ Ehi, const typename Operand<P>::T* __restrict__ Elo,
-                 const typename Operand<P>::T* __restrict__ Yhi, const typename Operand<P>::T* __restrict__ Ylo,
-                 const double* __restrict__ OM, const double* __restrict__ IW, const double* __restrict__ OCC,
-                 GammaArgs G, double* __restrict__ partial) {
-  using T = typename Operand<P>::T;
-  constexpr int KC = Kc<P>::v;
-  constexpr bool kSplit = P == KALDO_BF16X3;
-  // row stride in elements: keeps the per-lane MFMA operand reads on distinct banks
-  constexpr int LD = KC + (sizeof(T) == 8 ? 2 : (sizeof(T) == 4 ? 4 : 8));
-  __shared__ __attribute__((aligned(16))) T As[kSplit ? 2 : 1][kTile * LD];
-  __shared__ __attribute__((aligned(16))) T Bs[kSplit ? 2 : 1][kTile * LD];
-  __shared__ double red[4][NT];
-
-  const int ntile = G.npad / kTile;
-  const int ti = blockIdx.x / ntile, tj = blockIdx.x % ntile;
-  const int sl = blockIdx.y;
-  const int s = G.s0 + sl;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wi = wave >> 1, wj = wave & 1;
-  const size_t nn = (size_t)G.npad * G.npad;
-  const T* Ah = Ehi + (size_t)ti * kTile * G.npad;
-  const T* Al = kSplit ? Elo + (size_t)ti * kTile * G.npad : nullptr;
-  const T* Bh = Yhi + (size_t)sl * nn + (size_t)tj * kTile * G.npad;
-  const T* Bl = kSplit ? Ylo + (size_t)sl * nn + (size_t)tj * kTile * G.npad : nullptr;
-
-  using Acc = typename std::conditional<P == KALDO_FP64, f64x4, f32x4>::type;
-  Acc acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
-
-  // cooperative tile loads: 64 rows x KC elements per operand
-  constexpr int kElemsPerThread = kTile * KC / 256;
-  for (int k0 = 0; k0 < G.npad; k0 += KC) {
-#pragma unroll
-    for (int e = 0; e < kElemsPerThread; ++e) {
-      const int q = threadIdx.x * kElemsPerThread + e;
-      const int row = q / KC, col = q % KC;
-      As[0][row * LD + col] = Ah[(size_t)row * G.npad + k0 + col];
-      Bs[0][row * LD + col] = Bh[(size_t)row * G.npad + k0 + col];
-      if constexpr (kSplit) {
-        As[1][row * LD + col] = Al[(size_t)row * G.npad + k0 + col];
-        Bs[1][row * LD + col] = Bl[(size_t)row * G.npad + k0 + col];
-      }
-    }
-    __syncthreads();
-    if constexpr (P == KALDO_BF16X3) {
-#pragma unroll
-      for (int kk = 0; kk < KC; kk += 32) {
-        bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int r = wi * 32 + a * 16 + (lane & 15);
-          const int c = wj * 32 + a * 16 + (lane & 15);
-          const int k = kk + 8 * (lane >> 4);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            ah[a][e] = As[0][r * LD + k + e];
-            al[a][e] = As[1][r * LD + k + e];
-            bh[a][e] = Bs[0][c * LD + k + e];
-            bl[a][e] = Bs[1][c * LD + k + e];
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-          }
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
-        T av[2], bv[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          av[a] = As[0][(wi * 32 + a * 16 + (lane & 15)) * LD + kk + (lane >> 4)];
-          bv[a] = Bs[0][(wj * 32 + a * 16 + (lane & 15)) * LD + kk + (lane >> 4)];
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            if constexpr (P == KALDO_FP64)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-          }
-      }
-    }
-    __syncthreads();
-  }
-
-  // epilogue: weights of both processes at every temperature, reduced over the tile
-  double out[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) out[t] = 0.0;
-  const double ws = OM[s < G.n ? s : 0];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // accumulator rows: f32 MFMA lane l holds rows 4(l/16)+r, f64 MFMA rows l/16+4r
-        const int i = ti * kTile + wi * 32 + a * 16 + (P == KALDO_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
-        const int j = tj * kTile + wj * 32 + b * 16 + (lane & 15);         // s''
-        if (i < G.n && j < G.n) {
-          const double v = (double)acc[a][b][r];
-          const double v2 = v * v * IW[i] * IW[j];
-          if (v2 != 0.0) {
-            const double w1 = OM[i], w2 = OM[j];
-            const double xp = ws + w1 - w2, xm = ws - w1 - w2;
-            double gp, gm;
-            if constexpr (P == KALDO_FP64) {
-              gp = exp(-xp * xp * G.c);
-              gm = exp(-xm * xm * G.c);
-            } else {
-              gp = (double)__expf((float)(-xp * xp * G.c));
-              gm = (double)__expf((float)(-xm * xm * G.c));
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              if (t < G.nT) {
-                const double n1 = OCC[(size_t)t * G.n + i], n2 = OCC[(size_t)t * G.n + j];
-                out[t] += v2 * (gp * (n1 - n2) + 0.5 * gm * (1.0 + n1 + n2));
-              }
-            }
-          }
-        }
-      }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    double v = out[t];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wave][t] = v;
+// Et[a][s] = eta_s[a]: 32 x 32 tiles through LDS, both sides coalesced.
+__global__ void k_transpose(double* __restrict__ Et, const double* __restrict__ E, int n) {
+  __shared__ double t[32][33];
+  const int s0 = blockIdx.x * 32, a0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+  for (int r = ty; r < 32; r += 8) {
+    const int s = s0 + r, a = a0 + tx;
+    t[r][tx] = (s < n && a < n) ? E[(size_t)s * n + a] : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < G.nT) {
-    const int t = threadIdx.x;
-    partial[((size_t)sl * gridDim.x + blockIdx.x) * G.nT + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  for (int r = ty; r < 32; r += 8) {
+    const int a = a0 + r, s = s0 + tx;
+    if (a < n && s < n) Et[(size_t)a * n + s] = t[tx][r];
   }
 }
 
-// g[t][s] = C / w_s * sum over tiles (before set averaging)
+// ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] as the GEMM's B operand ---------
+// Rows (sl, s'') of ldy elements, columns a'.  Lanes run over s'' (coalesced reads
+// of Et); the SB modes of a block share every Et load; X_s is wave uniform and
+// read through the scalar cache.  Each block walks a run of jc atoms j.
+template <int P, int SB>
+__global__ void __launch_bounds__(256)
+    k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
+              const double* __restrict__ Xs, const double* __restrict__ Et, const int* __restrict__ rstart,
+              const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc) {
+  const int s2 = blockIdx.x * 256 + threadIdx.x;
+  const int slb = blockIdx.y * SB;
+  const int j0 = blockIdx.z * jc;
+  const int j1 = min(N, j0 + jc);
+  const bool live = s2 < n;
+  const int s2c = live ? s2 : n - 1;
+  for (int j = j0; j < j1; ++j) {
+    double y[SB][3];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) y[u][0] = y[u][1] = y[u][2] = 0.0;
+    const int p1 = rstart[j + 1];
+    for (int p = rstart[j]; p < p1; ++p) {
+      const size_t l3 = 3 * (size_t)pl[p];
+      const double e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
+      const double* x = Xs + ((size_t)p * sbp + slb) * 9;
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        y[u][0] += x[9 * u + 0] * e0 + x[9 * u + 1] * e1 + x[9 * u + 2] * e2;
+        y[u][1] += x[9 * u + 3] * e0 + x[9 * u + 4] * e1 + x[9 * u + 5] * e2;
+        y[u][2] += x[9 * u + 6] * e0 + x[9 * u + 7] * e1 + x[9 * u + 8] * e2;
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        if (slb + u < cnt) {
+          const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)j;
+          store_operand<P>(Yhi, Ylo, o, y[u][0]);
+          store_operand<P>(Yhi, Ylo, o + 1, y[u][1]);
+          store_operand<P>(Yhi, Ylo, o + 2, y[u][2]);
+        }
+      }
+    }
+  }
+}
+
+// A operand: row s' = eta_{s'} (K = a' contiguous), zero in the K padding.
+template <int P>
+__global__ void k_gamma_a(typename Operand<P>::T* __restrict__ Ahi, typename Operand<P>::T* __restrict__ Alo,
+                          const double* __restrict__ E, int n, int ld) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * ld) return;
+  const int a = (int)(idx % ld), s = (int)(idx / ld);
+  store_operand<P>(Ahi, Alo, idx, a < n ? E[(size_t)s * n + a] : 0.0);
+}
+
+// ---- fused linewidth epilogue of V_s = E^T Y_s ---------------------------------------
+// Output row i = s' and column c = sl * n + s''.  For every element, both
+// processes at every temperature:
+//   |V|^2 / (w' w'') * [ g+ (n' - n'') + 1/2 g- (1 + n' + n'') ]
+// with g+- = exp(-(w +- w' - w'')^2 / 2 sigma^2); the 1/w of the first mode,
+// the Gaussian normalisation and the prefactor are applied when collecting.
+template <int NT>
+struct EpiGamma {
+  const double *OM, *IW, *OCC;
+  double* partial;     // [m_tiles][ncol][nT]
+  long long ncol;      // cnt * n
+  int n, nT, s0;
+  double c;            // 1 / (2 sigma^2)
+
+  template <int P, int FM, int FN>
+  __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
+                                        char* lds) const {
+    using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
+#pragma unroll
+    for (int q = 0; q < FN; ++q) {
+      const long long col = at.c0 + 16 * q + (at.lane & 15);
+      const bool cv = col < ncol;
+      const int sl = cv ? (int)(col / n) : 0;
+      const int s2 = cv ? (int)(col - (long long)sl * n) : 0;
+      const double ws = OM[s0 + sl], w2 = OM[s2];
+      const R iw2 = cv ? (R)IW[s2] : (R)0;
+      R n2[NT], o[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        n2[t] = t < nT ? (R)OCC[(size_t)t * n + s2] : (R)0;
+        o[t] = 0;
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = at.m0 + 16 * a + acc_row<P>(at.lane, r);
+          const int ic = i < n ? i : n - 1;
+          const R iw1 = i < n ? (R)IW[ic] : (R)0;
+          const R v = (R)acc[a][q][r];
+          const R v2 = v * v * iw1 * iw2;
+          const double w1 = OM[ic];
+          const double xp = ws + w1 - w2, xm = ws - w1 - w2;
+          R gp, gm;
+          if constexpr (P == KALDO_FP64) {
+            gp = exp(-xp * xp * c);
+            gm = exp(-xm * xm * c);
+          } else {
+            gp = __expf((float)(-xp * xp * c));
+            gm = __expf((float)(-xm * xm * c));
+          }
+          const R h = (R)0.5 * gm, a1 = gp + h, a2 = h - gp;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const R n1 = t < nT ? (R)OCC[(size_t)t * n + ic] : (R)0;
+            o[t] += v2 * (h + n1 * a1 + n2[t] * a2);
+          }
+        }
+      double od[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) od[t] = (double)o[t];
+      column_put<FN, NT>(od, q, at, lds);
+    }
+    const long long first = (long long)at.nt * 32 * FN;
+    column_flush<FN, NT>(lds, partial + ((size_t)at.mt * ncol + first) * nT, ncol - first, nT);
+  }
+};
+
+// g[t][s] = C / w_s * sum over row tiles and the n columns of s (one block per (sl, t))
 __global__ void k_gamma_collect(double* __restrict__ graw, const double* __restrict__ partial,
-                                const double* __restrict__ IW, int n, int nT, int ntiles, int s0, int sb, double C) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= sb * nT) return;
-  const int sl = idx % sb, t = idx / sb;
-  const int s = s0 + sl;
-  if (s >= n) return;
+                                const double* __restrict__ IW, int n, int nT, int m_tiles, long long ncol, int s0,
+                                double C) {
+  __shared__ double red[256];
+  const int sl = blockIdx.x, t = blockIdx.y;
   double v = 0.0;
-  for (int b = 0; b < ntiles; ++b) v += partial[((size_t)sl * ntiles + b) * nT + t];
-  graw[(size_t)t * n + s] = C * IW[s] * v;
+  for (int mt = 0; mt < m_tiles; ++mt)
+    for (int s2 = threadIdx.x; s2 < n; s2 += 256)
+      v += partial[((size_t)mt * ncol + (size_t)sl * n + s2) * nT + t];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) graw[(size_t)t * n + s0 + sl] = C * IW[s0 + sl] * red[0];
 }
 
 __global__ void k_set_average_gamma(double* __restrict__ gamma, const double* __restrict__ graw,
@@ -307,94 +242,113 @@ __global__ void k_tables_gamma(double* __restrict__ OM, double* __restrict__ IW,
 }
 
 template <int P, int NT>
-static void launch_gemm(dim3 grid, hipStream_t st, const void* Eh, const void* El, const void* Yh, const void* Yl,
-                        const double* OM, const double* IW, const double* OCC, const GammaArgs& A,
-                        double* partial) {
-  using T = typename Operand<P>::T;
-  hipLaunchKernelGGL((k_gamma_gemm<P, NT>), grid, dim3(256), 0, st, (const T*)Eh, (const T*)El, (const T*)Yh,
-                     (const T*)Yl, OM, IW, OCC, A, partial);
-}
-
-template <int P>
-static void launch_gemm_nt(int nT, dim3 grid, hipStream_t st, const void* Eh, const void* El, const void* Yh,
-                           const void* Yl, const double* OM, const double* IW, const double* OCC, const GammaArgs& A,
-                           double* partial) {
-  if (nT <= 1) launch_gemm<P, 1>(grid, st, Eh, El, Yh, Yl, OM, IW, OCC, A, partial);
-  else if (nT <= 2) launch_gemm<P, 2>(grid, st, Eh, El, Yh, Yl, OM, IW, OCC, A, partial);
-  else if (nT <= 4) launch_gemm<P, 4>(grid, st, Eh, El, Yh, Yl, OM, IW, OCC, A, partial);
-  else launch_gemm<P, 8>(grid, st, Eh, El, Yh, Yl, OM, IW, OCC, A, partial);
+static int gemm_lw(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const EpiGamma<NT>& e) {
+  hipStream_t st = ctx->stream;
+  const int v = autotune(ctx, key, kGemmVariants, 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
+  gemm_launch<P>(v, g, e, st);
+  return v;
 }
 
 template <int P>
 static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   using T = typename Operand<P>::T;
+  constexpr int S = Operand<P>::split;
+  constexpr int SB = 8;
   const int N = ctx->n_atoms, n = ctx->nm, nT = ctx->nT;
-  const int npad = (n + kTile - 1) / kTile * kTile;
-  const int ntile = npad / kTile;
+  const int KC = GemmChunk<P>::KC;
+  const int ld = (n + KC - 1) / KC * KC;  // K padded to whole chunks
   const Fc3Layout& L = ctx->fc3;
-  const int npairs = L.n_pairs;
+  const int npairs = std::max(L.n_pairs, 1);
   hipStream_t st = ctx->stream;
   const double* E = ctx->d_dyn.as<double>();  // real eigenvectors, column s contiguous
-  const int nsplit = P == KALDO_BF16X3 ? 2 : 1;
-  const size_t op_bytes = (size_t)npad * npad * sizeof(T);
+  const size_t y_item = (size_t)n * ld * sizeof(T) * S;
   // first-mode batch bounded by the Y buffer size
-  int sb = (int)std::max<size_t>(1, std::min<size_t>((size_t)n, ((size_t)768 << 20) / (op_bytes * nsplit)));
-  sb = std::min(sb, 64);
+  int sb = (int)std::max<size_t>(1, std::min<size_t>((size_t)n, ((size_t)2 << 30) / y_item));
+  sb = std::min(sb, 256);
+  const int sbp = (sb + SB - 1) / SB * SB;
   const int nbatch = (n + sb - 1) / sb;
-  // buffers: tables | graw | partial | Xs ; operands in d_A
+  const long long ncol_max = (long long)sb * n;
+  const int mt_max = (n + 63) / 64;  // the smallest candidate block tile has 64 rows
+  // d_tabs: tables | graw | partial | Xs | Et
   const size_t tab = (2 + (size_t)nT) * n;
   const size_t graw = (size_t)nT * n;
-  const size_t part = (size_t)sb * ntile * ntile * nT;
-  const size_t xs = (size_t)sb * std::max(npairs, 1) * 9;
-  KALDO_HIP(ctx, ctx->d_tabs.ensure((tab + graw + part + xs) * sizeof(double)));
+  const size_t part = (size_t)mt_max * ncol_max * nT;
+  const size_t xs = (size_t)sbp * npairs * 9;
+  const size_t et = (size_t)n * n;
+  KALDO_HIP(ctx, ctx->d_tabs.ensure((tab + graw + part + xs + et) * sizeof(double)));
   double* OM = ctx->d_tabs.as<double>();
   double* IW = OM + n;
   double* OCC = IW + n;
   double* gr = OCC + (size_t)nT * n;
   double* partial = gr + graw;
   double* Xs = partial + part;
-  KALDO_HIP(ctx, ctx->d_A.ensure(op_bytes * nsplit * (1 + (size_t)sb)));
-  T* Eh = ctx->d_A.as<T>();
-  T* El = P == KALDO_BF16X3 ? Eh + (size_t)npad * npad : nullptr;
-  T* Yh = Eh + (size_t)nsplit * npad * npad;
-  T* Yl = P == KALDO_BF16X3 ? Yh + (size_t)sb * npad * npad : nullptr;
+  double* Et = Xs + xs;
+  // operands: A [n][ld] planes, Y [sb * n][ld] planes
+  const size_t a_elems = (size_t)n * ld, y_elems = (size_t)sb * n * ld;
+  KALDO_HIP(ctx, ctx->d_A.ensure((a_elems + y_elems) * S * sizeof(T)));
+  T* Ah = ctx->d_A.as<T>();
+  T* Al = S == 2 ? Ah + a_elems : nullptr;
+  T* Yh = Ah + a_elems * S;
+  T* Yl = S == 2 ? Yh + y_elems : nullptr;
   KALDO_HIP(ctx, ctx->d_gamma.ensure((size_t)nT * n * sizeof(double)));
-  // Y pads (rows >= n, columns >= n) stay zero
-  KALDO_HIP(ctx, hipMemsetAsync(Yh, 0, op_bytes * nsplit * sb, st));
+  // the K padding of Y (columns a' >= n) stays zero; the rest is rewritten per batch
+  if (ld > n) KALDO_HIP(ctx, hipMemsetAsync(Yh, 0, y_elems * S * sizeof(T), st));
   double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
   const int TB = 256;
   hipLaunchKernelGGL(k_tables_gamma, dim3(blocks_for(n, TB)), dim3(TB), 0, st, OM, IW, OCC,
                      ctx->d_omega.as<double>(), n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
-  hipLaunchKernelGGL((k_gamma_et<P>), dim3(blocks_for((long long)npad * npad, TB)), dim3(TB), 0, st, Eh, El, E, n,
-                     npad);
+  hipLaunchKernelGGL((k_gamma_a<P>), dim3(blocks_for((long long)n * ld, TB)), dim3(TB), 0, st, Ah, Al, E, n, ld);
+  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et, E, n);
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
-  GammaArgs A;
-  A.n = n;
-  A.npad = npad;
-  A.nT = nT;
-  A.c = 1.0 / (2.0 * sig * sig);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / (sqrt(kTwoPi) * sig);
+  const int jc = 4;
   for (int b = 0; b < nbatch; ++b) {
     const int s0 = b * sb;
     const int cnt = std::min(sb, n - s0);
-    A.s0 = s0;
+    const int cntp = (cnt + SB - 1) / SB * SB;
     prof_begin(ctx);
-    hipLaunchKernelGGL(k_gamma_xs, dim3(blocks_for((long long)cnt * npairs * 9, TB)), dim3(TB), 0, st, Xs, E,
-                       L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
-                       cnt);
-    KALDO_HIP(ctx, hipGetLastError());
-    hipLaunchKernelGGL((k_gamma_y<P>), dim3(blocks_for((long long)cnt * n * N, TB)), dim3(TB), 0, st, Yh, Yl, Xs,
-                       E, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, npairs, npad, s0, cnt);
+    if (L.n_pairs > 0) {
+      hipLaunchKernelGGL(k_gamma_xs, dim3(blocks_for((long long)cntp * npairs * 9, TB)), dim3(TB), 0, st, Xs, E,
+                         L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
+                         cntp);
+      KALDO_HIP(ctx, hipGetLastError());
+      hipLaunchKernelGGL((k_gamma_y<P, SB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256), 0, st,
+                         Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
+                         cnt, jc);
+    } else {
+      KALDO_HIP(ctx, hipMemsetAsync(Yh, 0, y_elems * S * sizeof(T), st));
+    }
     KALDO_HIP(ctx, hipGetLastError());
     prof_end(ctx, "gamma_sparse");
+    GemmOps g{};
+    g.a_hi = Ah;
+    g.a_lo = Al;
+    g.b_hi = Yh;
+    g.b_lo = Yl;
+    g.lda = g.ldb = ld;
+    g.K = ld;
+    g.nz = 1;
+    g.m_valid = n;
+    g.c_valid = (long long)cnt * n;
+    const std::string key = "gamma/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt) +
+                            "/" + std::to_string(nT);
+    int v = 0;
     prof_begin(ctx);
-    launch_gemm_nt<P>(nT, dim3(ntile * ntile, cnt), st, Eh, El, Yh, Yl, OM, IW, OCC, A, partial);
+#define KALDO_EPI(NTV)                                                                                      \
+  {                                                                                                         \
+    EpiGamma<NTV> e{OM, IW, OCC, partial, (long long)cnt * n, n, nT, s0, 1.0 / (2.0 * sig * sig)};          \
+    v = gemm_lw<P, NTV>(ctx, key, g, e);                                                                    \
+  }
+    if (nT <= 1) KALDO_EPI(1)
+    else if (nT <= 4) KALDO_EPI(4)
+    else KALDO_EPI(8)
+#undef KALDO_EPI
     KALDO_HIP(ctx, hipGetLastError());
     prof_end(ctx, "project");
-    hipLaunchKernelGGL(k_gamma_collect, dim3(blocks_for(cnt * nT, TB)), dim3(TB), 0, st, gr, partial, IW, n, nT,
-                       ntile * ntile, s0, cnt, C);
+    hipLaunchKernelGGL(k_gamma_collect, dim3(cnt, nT), dim3(256), 0, st, gr, partial, IW, n, nT, gemm_m_tiles<P>(v, n),
+                       (long long)cnt * n, s0, C);
     KALDO_HIP(ctx, hipGetLastError());
   }
   hipLaunchKernelGGL(k_set_average_gamma, dim3(blocks_for(n * nT, TB)), dim3(TB), 0, st, ctx->d_gamma.as<double>(),

@@ -1,0 +1,318 @@
+// A real MFMA GEMM core shared by the projection paths:
+//
+//   C[m][c] = sum_k A[m][k] * B[c][k]          (both operands K-contiguous rows)
+//
+// with a caller-supplied epilogue that consumes the accumulator tile in
+// registers (so C never reaches memory unless the epilogue stores it).
+//
+// Tiling for gfx950: 256 threads = 4 wavefronts in a 2 x 2 grid; a wavefront
+// owns (16 FM) x (16 FN) outputs as FM x FN 16x16 MFMA tiles; the block tile
+// is (32 FM) x (32 FN).  K is consumed in chunks of 128 bytes per row (64 bf16,
+// 32 fp32 or 16 fp64), staged through a double-buffered LDS tile by 16-byte
+// vector loads (one global_load_dwordx4 + one ds_write_b128 per slot), so the
+// next chunk is in flight while the current one feeds the matrix cores.  LDS
+// rows are padded to 144 bytes, which keeps both the b128 stores and the
+// fragment reads of 16 consecutive rows on distinct banks.
+//
+// Fragment reads: the MFMA sums over k, so any bijection between (lane group
+// g = lane / 16, step j) and the k index of a chunk gives the same result as
+// long as A and B use the same one.  FP32 and FP64 take k = 4 g + j within each
+// 16-wide group, so a lane fetches the four k it needs for four consecutive
+// 16x16x4 steps with one contiguous read; BF16 16x16x32 reads 8 consecutive k
+// per lane as the instruction defines.
+//
+// Block order: workgroups are dealt round-robin to the 8 XCDs, each with its
+// own L2.  The flat block id is remapped so that every XCD receives a
+// contiguous run of logical tiles with M fastest: tiles that share a B panel
+// run on the same XCD and read it from that XCD's L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mfma.h"
+
+namespace kaldo {
+
+struct GemmOps {
+  const void* a_hi;
+  const void* a_lo;   // lo planes: BF16X3 only
+  const void* b_hi;
+  const void* b_lo;
+  long long lda, ldb; // row strides in elements
+  long long a_z, b_z; // element offsets between batch items (blockIdx -> z)
+  const int* a_map;   // if set, batch item z takes A item a_map[z] (else z)
+  int K;              // multiple of the chunk (128 bytes of one row)
+  int m_tiles, n_tiles, nz; // filled in by the launcher from the tile shape
+  int m_valid;        // rows of A (= output rows); loads beyond are clamped
+  long long c_valid;  // rows of B (= output columns) per batch item
+};
+
+template <int P>
+struct GemmChunk {
+  static constexpr int KC = 128 / (int)sizeof(typename Operand<P>::T);
+};
+
+// Coordinates of one block tile, handed to the epilogue.
+struct TileAt {
+  int mt, nt, z;      // tile indices and batch item
+  int m0;             // first row of this wavefront's 16 FM rows
+  long long c0;       // first column of this wavefront's 16 FN columns
+  int lane, wm, wn;   // lane and wavefront position in the 2 x 2 grid
+};
+
+__device__ __forceinline__ uint4 lds_read16(const char* p) { return *reinterpret_cast<const uint4*>(p); }
+
+template <int P, int FM, int FN, class Epi>
+__global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
+  using T = typename Operand<P>::T;
+  using Acc = typename Operand<P>::Acc;
+  constexpr int S = Operand<P>::split;
+  constexpr int BM = 32 * FM, BN = 32 * FN;
+  constexpr int RB = 144;                     // LDS row bytes
+  constexpr int ROWS = BM + BN;
+  constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
+  constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
+  __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
+
+  // XCD-aware order: logical tile = start of this XCD's run + position in it
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = nb >> 3, r8 = nb & 7, x = b & 7;
+  const int tile = x * q + (x < r8 ? x : r8) + (b >> 3);
+  const int mt = tile % g.m_tiles;
+  const int rest = tile / g.m_tiles;
+  const int nt = rest % g.n_tiles;
+  const int z = rest / g.n_tiles;
+
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int slot = tid & 7;  // 16-byte slot of the 128-byte row chunk
+
+  // global row offsets of this thread's load slots (clamped to existing rows)
+  long long aoff[FM], boff[FN];
+#pragma unroll
+  for (int u = 0; u < FM; ++u) {
+    int row = mt * BM + (tid >> 3) + 32 * u;
+    row = row < g.m_valid ? row : g.m_valid - 1;
+    aoff[u] = (long long)(g.a_map ? g.a_map[z] : z) * g.a_z + (long long)row * g.lda + slot * EPT;
+  }
+#pragma unroll
+  for (int u = 0; u < FN; ++u) {
+    long long row = (long long)nt * BN + (tid >> 3) + 32 * u;
+    row = row < g.c_valid ? row : g.c_valid - 1;
+    boff[u] = (long long)z * g.b_z + row * g.ldb + slot * EPT;
+  }
+  const T* ap[S];
+  const T* bp[S];
+  ap[0] = static_cast<const T*>(g.a_hi);
+  bp[0] = static_cast<const T*>(g.b_hi);
+  if constexpr (S == 2) {
+    ap[S - 1] = static_cast<const T*>(g.a_lo);
+    bp[S - 1] = static_cast<const T*>(g.b_lo);
+  }
+
+  // staging registers of the next chunk: rg[s][u], u < FM for A rows, then FN for B rows
+  uint4 rg[S][FM + FN];
+#define KALDO_GLOAD(K0)                                                                                   \
+  _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
+    _Pragma("unroll") for (int u = 0; u < FM; ++u) rg[s][u] =                                          \
+        *reinterpret_cast<const uint4*>(ap[s] + aoff[u] + (K0));                                         \
+    _Pragma("unroll") for (int u = 0; u < FN; ++u) rg[s][FM + u] =                                     \
+        *reinterpret_cast<const uint4*>(bp[s] + boff[u] + (K0));                                         \
+  }
+#define KALDO_SSTORE(BUFI)                                                                                \
+  _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
+    _Pragma("unroll") for (int u = 0; u < FM + FN; ++u) {                                              \
+      const int row = (u < FM ? 0 : BM - 32 * FM) + (tid >> 3) + 32 * u;                                \
+      *reinterpret_cast<uint4*>(lds + (BUFI) * BUF + (s * ROWS + row) * RB + slot * 16) = rg[s][u];     \
+    }                                                                                                   \
+  }
+
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int c = 0; c < FN; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][c][r] = 0;
+
+  const int arow = wm * 16 * FM + (lane & 15);
+  const int brow = BM + wn * 16 * FN + (lane & 15);
+  const int grp = lane >> 4;
+
+  const int nchunk = g.K / GemmChunk<P>::KC;
+  KALDO_GLOAD(0)
+  KALDO_SSTORE(0)
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    // the next chunk (the last one again on the final pass: a harmless reload
+    // into the buffer nobody reads any more keeps the loop free of branches)
+    const int nxt = (ch + 1 < nchunk ? ch + 1 : ch) * GemmChunk<P>::KC;
+    KALDO_GLOAD(nxt)
+    const char* base = lds + (ch & 1) * BUF;
+    if constexpr (P == KALDO_BF16X3) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        bf16x8 af[FM][2], bf[FN][2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+          for (int a = 0; a < FM; ++a) {
+            const uint4 v = lds_read16(base + (s * ROWS + arow + 16 * a) * RB + j * 64 + grp * 16);
+            af[a][s] = __builtin_bit_cast(bf16x8, v);
+          }
+#pragma unroll
+          for (int c = 0; c < FN; ++c) {
+            const uint4 v = lds_read16(base + (s * ROWS + brow + 16 * c) * RB + j * 64 + grp * 16);
+            bf[c][s] = __builtin_bit_cast(bf16x8, v);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int c = 0; c < FN; ++c) {
+            acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][0], bf[c][0], acc[a][c], 0, 0, 0);
+            acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][0], bf[c][1], acc[a][c], 0, 0, 0);
+            acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][1], bf[c][0], acc[a][c], 0, 0, 0);
+          }
+      }
+    } else if constexpr (P == KALDO_FP32) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        f32x4 af[FM], bf[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+          af[a] = __builtin_bit_cast(f32x4, lds_read16(base + (arow + 16 * a) * RB + h * 64 + grp * 16));
+#pragma unroll
+        for (int c = 0; c < FN; ++c)
+          bf[c] = __builtin_bit_cast(f32x4, lds_read16(base + (brow + 16 * c) * RB + h * 64 + grp * 16));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int c = 0; c < FN; ++c)
+              acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][j], bf[c][j], acc[a][c], 0, 0, 0);
+      }
+    } else {
+      double af[FM][4], bf[FN][4];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const char* p = base + (arow + 16 * a) * RB + grp * 32;
+        const uint4 v0 = lds_read16(p), v1 = lds_read16(p + 16);
+        const double2 d0 = __builtin_bit_cast(double2, v0), d1 = __builtin_bit_cast(double2, v1);
+        af[a][0] = d0.x;
+        af[a][1] = d0.y;
+        af[a][2] = d1.x;
+        af[a][3] = d1.y;
+      }
+#pragma unroll
+      for (int c = 0; c < FN; ++c) {
+        const char* p = base + (brow + 16 * c) * RB + grp * 32;
+        const uint4 v0 = lds_read16(p), v1 = lds_read16(p + 16);
+        const double2 d0 = __builtin_bit_cast(double2, v0), d1 = __builtin_bit_cast(double2, v1);
+        bf[c][0] = d0.x;
+        bf[c][1] = d0.y;
+        bf[c][2] = d1.x;
+        bf[c][3] = d1.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int c = 0; c < FN; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][j], bf[c][j], acc[a][c], 0, 0, 0);
+    }
+    KALDO_SSTORE((ch + 1) & 1)
+    __syncthreads();
+  }
+
+#undef KALDO_GLOAD
+#undef KALDO_SSTORE
+
+  TileAt at;
+  at.mt = mt;
+  at.nt = nt;
+  at.z = z;
+  at.m0 = mt * BM + wm * 16 * FM;
+  at.c0 = (long long)nt * BN + wn * 16 * FN;
+  at.lane = lane;
+  at.wm = wm;
+  at.wn = wn;
+  // the operand buffers are free after the last barrier: the epilogue may use them
+  epi.template apply<P, FM, FN>(acc, at, lds);
+}
+
+// Per-column partial sums of a linewidth epilogue, in two steps.  column_put
+// reduces o[t] (this lane's sum over its rows of column 16 q + lane % 16 of the
+// wavefront tile) over the 4 lane groups and parks it in LDS; column_flush
+// adds the 2 wavefront rows and writes dst[col * nT + t] for the block's valid
+// columns (dst already offset to the block's first column).
+template <int FN, int NT>
+__device__ __forceinline__ void column_put(double (&o)[NT], int q, const TileAt& at, char* lds) {
+  double* red = reinterpret_cast<double*>(lds);  // [2 wm][32 FN columns][NT]
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double v = o[t];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    o[t] = v;
+  }
+  if (at.lane < 16) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) red[(at.wm * 32 * FN + at.wn * 16 * FN + 16 * q + at.lane) * NT + t] = o[t];
+  }
+}
+
+template <int FN, int NT>
+__device__ __forceinline__ void column_flush(char* lds, double* dst, long long ncols_left, int nT) {
+  const double* red = reinterpret_cast<const double*>(lds);
+  __syncthreads();
+  for (int i = (int)threadIdx.x; i < 32 * FN * NT; i += 256) {
+    const int col = i / NT, t = i % NT;
+    if (t < nT && col < ncols_left) dst[(long long)col * nT + t] = red[i] + red[32 * FN * NT + i];
+  }
+}
+
+// ---- tile variants and launch ----------------------------------------------------------
+// Candidate (FM, FN) shapes, block tile 32 FM x 32 FN.  FP64 accumulators take
+// twice the registers of FP32 ones, so its candidates are one size smaller.
+constexpr int kGemmVariants = 4;
+
+template <int P>
+inline int gemm_fm(int v) {
+  if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
+  return v == 1 ? 2 : (v == 3 ? 3 : 4);
+}
+
+template <int P>
+inline int gemm_m_tiles(int v, int m) {
+  const int bm = 32 * gemm_fm<P>(v);
+  return (m + bm - 1) / bm;
+}
+
+template <int P, int FM, int FN, class Epi>
+inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
+  g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
+  g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
+  const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
+  hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
+}
+
+template <int P, class Epi>
+inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
+  if constexpr (P == KALDO_FP64) {
+    if (v == 0) gemm_launch_tile<P, 2, 4>(g, e, st);
+    else if (v == 1) gemm_launch_tile<P, 4, 2>(g, e, st);
+    else if (v == 2) gemm_launch_tile<P, 2, 2>(g, e, st);
+    else gemm_launch_tile<P, 3, 2>(g, e, st);
+  } else {
+    if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
+    else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
+    else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
+    else gemm_launch_tile<P, 3, 4>(g, e, st);
+  }
+}
+
+}  // namespace kaldo

@@ -74,6 +74,7 @@ struct Fc3Layout {
   DevBuf d_cg_delta;                 // int [ng] Delta index
   DevBuf d_cg_order;                 // int [ng] group indices sorted by (j, l, Delta)
   DevBuf d_cpair;                    // int4 [np] (j, l, first, last+1) into d_cg_order
+  DevBuf d_cpairmap;                 // int [N * N] pair (j, l) -> index into d_cpair, or -1
   // Gamma-point layout: blocks sorted by the atom pair (j, l), all cells merged.
   int n_pairs = 0;
   DevBuf d_gpair_start;              // int [npairs + 1] -> block range of each pair
@@ -95,6 +96,10 @@ struct kaldo_ctx_s {
   };
   std::map<std::string, ProfEntry> prof_tab;
   hipEvent_t prof_open = nullptr;
+
+  // tile shapes chosen by the autotuner, per problem key
+  int tuning = KALDO_TUNE_AUTO;
+  std::map<std::string, int> tuned;
 
   int device = 0;
   hipStream_t stream = nullptr;

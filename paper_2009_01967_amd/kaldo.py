@@ -33,13 +33,15 @@ KALDO_DELTA_GAUSS = 0
 KALDO_QUANTUM = 0
 KALDO_CLASSICAL = 1
 KALDO_MAX_T = 8
+KALDO_TUNE_AUTO = 0
+KALDO_TUNE_FIXED = 1
 
 STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALDO_EDEVICE",
                 -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
 
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
-            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_profile_enable",
-            "kaldo_profile_read"]
+            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_set_tuning",
+            "kaldo_profile_enable", "kaldo_profile_read"]
 
 
 class kaldo_structure(C.Structure):
@@ -91,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
+    lib.kaldo_set_tuning.argtypes = [C.c_void_p, C.c_int]
+    lib.kaldo_set_tuning.restype = C.c_int
     lib.kaldo_profile_enable.argtypes = [C.c_void_p, C.c_int]
     lib.kaldo_profile_enable.restype = C.c_int
     lib.kaldo_profile_read.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -206,6 +210,11 @@ def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
 
 def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_qhgk(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_set_tuning(ctx, mode: int) -> int:
+    """KALDO_TUNE_AUTO (0) or KALDO_TUNE_FIXED (1)."""
+    return load_library().kaldo_set_tuning(ctx, int(mode))
 
 
 def kaldo_profile_enable(ctx, enable: bool = True) -> int:
