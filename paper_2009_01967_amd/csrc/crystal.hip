@@ -141,9 +141,7 @@ __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand
       }
     }
   }
-  const size_t o = (size_t)row * ldk + 2 * (size_t)a2;
-  store_operand<P>(Xh, Xl, o, re);
-  store_operand<P>(Xh, Xl, o + 1, im);
+  store_operand2<P>(Xh, Xl, (size_t)row * ldk + 2 * (size_t)a2, re, im);
 }
 
 // the realified pair h (0, 1) of a lane's 4 accumulator rows inside a 16-row tile at row m
@@ -176,8 +174,7 @@ struct EpiStoreY {
           const int i = cr_pair_mode<Q>(at.m0 + 16 * a, at.lane, h);
           if (i < n) {
             const size_t o = (size_t)at.z * yz + ((size_t)s * n + i) * ldk + 2 * (size_t)a1;
-            store_operand<Q>(yh, yl, o, (double)acc[a][q][2 * h]);
-            store_operand<Q>(yh, yl, o + 1, (double)acc[a][q][2 * h + 1]);
+            store_operand2<Q>(yh, yl, o, (double)acc[a][q][2 * h], (double)acc[a][q][2 * h + 1]);
           }
         }
     }
@@ -200,33 +197,55 @@ struct EpiCrystal {
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
                                         char* lds) const {
     using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
+    constexpr double cut = gauss_cut<P>();
     const int p = p0 + at.z;
     const int kk = kmap[at.z];
+    // column data: w - w'' (first mode minus k+p mode), 1/w'', n''
+    double dcol[FN];
+    R iw2[FN], n2[FN][NT], o[FN][NT];
 #pragma unroll
     for (int q = 0; q < FN; ++q) {
       const long long col = at.c0 + 16 * q + (at.lane & 15);
       const bool cv = col < ncol;
       const int s = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)s * n) : 0;
-      const double ws = OM[(size_t)s * nk + k], w2 = OM[(size_t)s2 * nk + kk];
-      const R iw2 = cv ? (R)IW[(size_t)s2 * nk + kk] : (R)0;
-      R n2[NT], o[NT];
+      dcol[q] = OM[(size_t)s * nk + k] - OM[(size_t)s2 * nk + kk];
+      iw2[q] = cv ? (R)IW[(size_t)s2 * nk + kk] : (R)0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        n2[t] = t < nT ? (R)OCC[((size_t)t * n + s2) * nk + kk] : (R)0;
-        o[t] = 0;
+        n2[q][t] = t < nT ? (R)OCC[((size_t)t * n + s2) * nk + kk] : (R)0;
+        o[q][t] = 0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      // row data of the lane's two (Re, Im) pairs: w', 1/w', n'
+      double w1[2];
+      R iw1[2], n1[2][NT];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
+        const int ic = i < n ? i : n - 1;
+        w1[h] = OM[(size_t)ic * nk + p];
+        iw1[h] = i < n ? (R)IW[(size_t)ic * nk + p] : (R)0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)OCC[((size_t)t * n + ic) * nk + p] : (R)0;
       }
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int q = 0; q < FN; ++q) {
+        // a 16 x 16 sub-tile with every element outside the Gaussian cutoff adds nothing
+        bool need = false;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
-          const int ic = i < n ? i : n - 1;
-          const R iw1 = i < n ? (R)IW[(size_t)ic * nk + p] : (R)0;
+          const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
+          need = need || fmin(xp * xp, xm * xm) * c < cut;
+        }
+        if (__ballot(need) == 0) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
           const R vr = (R)acc[a][q][2 * h], vi = (R)acc[a][q][2 * h + 1];
-          const R v2 = (vr * vr + vi * vi) * iw1 * iw2;
-          const double w1 = OM[(size_t)ic * nk + p];
-          const double xp = ws + w1 - w2, xm = ws - w1 - w2;
+          const R v2 = (vr * vr + vi * vi) * iw1[h] * iw2[q];
+          const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
           R gp, gm;
           if constexpr (P == KALDO_FP64) {
             gp = exp(-xp * xp * c);
@@ -237,14 +256,15 @@ struct EpiCrystal {
           }
           const R hh = (R)0.5 * gm, a1 = gp + hh, a2 = hh - gp;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const R n1 = t < nT ? (R)OCC[((size_t)t * n + ic) * nk + p] : (R)0;
-            o[t] += v2 * (hh + n1 * a1 + n2[t] * a2);
-          }
+          for (int t = 0; t < NT; ++t) o[q][t] += v2 * (hh + n1[h][t] * a1 + n2[q][t] * a2);
         }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < FN; ++q) {
       double od[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) od[t] = (double)o[t];
+      for (int t = 0; t < NT; ++t) od[t] = (double)o[q][t];
       column_put<FN, NT>(od, q, at, lds);
     }
     const long long first = (long long)at.nt * 32 * FN;

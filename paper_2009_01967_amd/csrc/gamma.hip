@@ -139,31 +139,53 @@ struct EpiGamma {
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
                                         char* lds) const {
     using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
+    constexpr double cut = gauss_cut<P>();
+    // column data: w - w'' (first mode minus s''), 1/w'', n''
+    double dcol[FN];
+    R iw2[FN], n2[FN][NT], o[FN][NT];
 #pragma unroll
     for (int q = 0; q < FN; ++q) {
       const long long col = at.c0 + 16 * q + (at.lane & 15);
       const bool cv = col < ncol;
       const int sl = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)sl * n) : 0;
-      const double ws = OM[s0 + sl], w2 = OM[s2];
-      const R iw2 = cv ? (R)IW[s2] : (R)0;
-      R n2[NT], o[NT];
+      dcol[q] = OM[s0 + sl] - OM[s2];
+      iw2[q] = cv ? (R)IW[s2] : (R)0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        n2[t] = t < nT ? (R)OCC[(size_t)t * n + s2] : (R)0;
-        o[t] = 0;
+        n2[q][t] = t < nT ? (R)OCC[(size_t)t * n + s2] : (R)0;
+        o[q][t] = 0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      // row data of the lane's four rows s': w', 1/w', n'
+      double w1[4];
+      R iw1[4], n1[4][NT];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = at.m0 + 16 * a + acc_row<P>(at.lane, r);
+        const int ic = i < n ? i : n - 1;
+        w1[r] = OM[ic];
+        iw1[r] = i < n ? (R)IW[ic] : (R)0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) n1[r][t] = t < nT ? (R)OCC[(size_t)t * n + ic] : (R)0;
       }
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int q = 0; q < FN; ++q) {
+        // a 16 x 16 sub-tile with every element outside the Gaussian cutoff adds nothing
+        bool need = false;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = at.m0 + 16 * a + acc_row<P>(at.lane, r);
-          const int ic = i < n ? i : n - 1;
-          const R iw1 = i < n ? (R)IW[ic] : (R)0;
+          const double xp = dcol[q] + w1[r], xm = dcol[q] - w1[r];
+          need = need || fmin(xp * xp, xm * xm) * c < cut;
+        }
+        if (__ballot(need) == 0) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
           const R v = (R)acc[a][q][r];
-          const R v2 = v * v * iw1 * iw2;
-          const double w1 = OM[ic];
-          const double xp = ws + w1 - w2, xm = ws - w1 - w2;
+          const R v2 = v * v * iw1[r] * iw2[q];
+          const double xp = dcol[q] + w1[r], xm = dcol[q] - w1[r];
           R gp, gm;
           if constexpr (P == KALDO_FP64) {
             gp = exp(-xp * xp * c);
@@ -174,14 +196,15 @@ struct EpiGamma {
           }
           const R h = (R)0.5 * gm, a1 = gp + h, a2 = h - gp;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const R n1 = t < nT ? (R)OCC[(size_t)t * n + ic] : (R)0;
-            o[t] += v2 * (h + n1 * a1 + n2[t] * a2);
-          }
+          for (int t = 0; t < NT; ++t) o[q][t] += v2 * (h + n1[r][t] * a1 + n2[q][t] * a2);
         }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < FN; ++q) {
       double od[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) od[t] = (double)o[t];
+      for (int t = 0; t < NT; ++t) od[t] = (double)o[q][t];
       column_put<FN, NT>(od, q, at, lds);
     }
     const long long first = (long long)at.nt * 32 * FN;

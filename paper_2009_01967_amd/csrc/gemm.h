@@ -7,12 +7,15 @@
 //
 // Tiling for gfx950: 256 threads = 4 wavefronts in a 2 x 2 grid; a wavefront
 // owns (16 FM) x (16 FN) outputs as FM x FN 16x16 MFMA tiles; the block tile
-// is (32 FM) x (32 FN).  K is consumed in chunks of 128 bytes per row (64 bf16,
-// 32 fp32 or 16 fp64), staged through a double-buffered LDS tile by 16-byte
-// vector loads (one global_load_dwordx4 + one ds_write_b128 per slot), so the
-// next chunk is in flight while the current one feeds the matrix cores.  LDS
-// rows are padded to 144 bytes, which keeps both the b128 stores and the
-// fragment reads of 16 consecutive rows on distinct banks.
+// is (32 FM) x (32 FN).  K is consumed in chunks of CB bytes per row (64 for
+// BF16 and FP32: 32 bf16 or 16 fp32; 128 for FP64: 16 fp64), staged through a
+// double-buffered LDS tile by 16-byte vector loads (one global_load_dwordx4 +
+// one ds_write_b128 per slot); the next chunk is in flight in registers while
+// the current one feeds the matrix cores.  The short chunk keeps the staging
+// registers and the LDS tile small enough for two blocks per CU, so one
+// block's loads and epilogue overlap the other's matrix work, and it keeps the
+// K padding of short contractions small.  LDS rows are padded by 16 bytes,
+// which keeps the fragment reads of 16 consecutive rows on distinct banks.
 //
 // Fragment reads: the MFMA sums over k, so any bijection between (lane group
 // g = lane / 16, step j) and the k index of a chunk gives the same result as
@@ -47,9 +50,11 @@ struct GemmOps {
   long long c_valid;  // rows of B (= output columns) per batch item
 };
 
+// Bytes of one row per K chunk, and the chunk in elements.
 template <int P>
 struct GemmChunk {
-  static constexpr int KC = 128 / (int)sizeof(typename Operand<P>::T);
+  static constexpr int CB = P == KALDO_FP64 ? 128 : 64;
+  static constexpr int KC = CB / (int)sizeof(typename Operand<P>::T);
 };
 
 // Coordinates of one block tile, handed to the epilogue.
@@ -68,7 +73,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   using Acc = typename Operand<P>::Acc;
   constexpr int S = Operand<P>::split;
   constexpr int BM = 32 * FM, BN = 32 * FN;
-  constexpr int RB = 144;                     // LDS row bytes
+  constexpr int CB = GemmChunk<P>::CB;
+  constexpr int RB = CB + 16;                 // LDS row bytes
+  constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
+  constexpr int RPP = 256 / SLOTS;            // rows loaded per pass of the block
+  constexpr int NA = BM / RPP, NB = BN / RPP; // passes for A and B
+  static_assert(NA * RPP == BM && NB * RPP == BN, "tile rows must be whole load passes");
   constexpr int ROWS = BM + BN;
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
@@ -86,19 +96,20 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int slot = tid & 7;  // 16-byte slot of the 128-byte row chunk
+  const int slot = tid % SLOTS;   // 16-byte slot of the row chunk
+  const int row0 = tid / SLOTS;   // first row of this thread's slots
 
-  // global row offsets of this thread's load slots (clamped to existing rows)
-  long long aoff[FM], boff[FN];
+  // global element offsets of this thread's load slots (rows clamped to existing ones)
+  long long aoff[NA], boff[NB];
 #pragma unroll
-  for (int u = 0; u < FM; ++u) {
-    int row = mt * BM + (tid >> 3) + 32 * u;
+  for (int u = 0; u < NA; ++u) {
+    int row = mt * BM + row0 + RPP * u;
     row = row < g.m_valid ? row : g.m_valid - 1;
     aoff[u] = (long long)(g.a_map ? g.a_map[z] : z) * g.a_z + (long long)row * g.lda + slot * EPT;
   }
 #pragma unroll
-  for (int u = 0; u < FN; ++u) {
-    long long row = (long long)nt * BN + (tid >> 3) + 32 * u;
+  for (int u = 0; u < NB; ++u) {
+    long long row = (long long)nt * BN + row0 + RPP * u;
     row = row < g.c_valid ? row : g.c_valid - 1;
     boff[u] = (long long)z * g.b_z + row * g.ldb + slot * EPT;
   }
@@ -111,19 +122,19 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     bp[S - 1] = static_cast<const T*>(g.b_lo);
   }
 
-  // staging registers of the next chunk: rg[s][u], u < FM for A rows, then FN for B rows
-  uint4 rg[S][FM + FN];
+  // staging registers of the next chunk: rg[s][u], u < NA for A rows, then NB for B rows
+  uint4 rg[S][NA + NB];
 #define KALDO_GLOAD(K0)                                                                                   \
   _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
-    _Pragma("unroll") for (int u = 0; u < FM; ++u) rg[s][u] =                                          \
+    _Pragma("unroll") for (int u = 0; u < NA; ++u) rg[s][u] =                                          \
         *reinterpret_cast<const uint4*>(ap[s] + aoff[u] + (K0));                                         \
-    _Pragma("unroll") for (int u = 0; u < FN; ++u) rg[s][FM + u] =                                     \
+    _Pragma("unroll") for (int u = 0; u < NB; ++u) rg[s][NA + u] =                                     \
         *reinterpret_cast<const uint4*>(bp[s] + boff[u] + (K0));                                         \
   }
 #define KALDO_SSTORE(BUFI)                                                                                \
   _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
-    _Pragma("unroll") for (int u = 0; u < FM + FN; ++u) {                                              \
-      const int row = (u < FM ? 0 : BM - 32 * FM) + (tid >> 3) + 32 * u;                                \
+    _Pragma("unroll") for (int u = 0; u < NA + NB; ++u) {                                              \
+      const int row = (u < NA ? 0 : BM - RPP * NA) + row0 + RPP * u;                                    \
       *reinterpret_cast<uint4*>(lds + (BUFI) * BUF + (s * ROWS + row) * RB + slot * 16) = rg[s][u];     \
     }                                                                                                   \
   }
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     const char* base = lds + (ch & 1) * BUF;
     if constexpr (P == KALDO_BF16X3) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < CB / 64; ++j) {
         bf16x8 af[FM][2], bf[FN][2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -178,7 +189,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
       }
     } else if constexpr (P == KALDO_FP32) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < CB / 64; ++h) {
         f32x4 af[FM], bf[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
@@ -195,6 +206,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
               acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][j], bf[c][j], acc[a][c], 0, 0, 0);
       }
     } else {
+      static_assert(P != KALDO_FP64 || CB == 128, "FP64 reads 32 bytes per lane group");
       double af[FM][4], bf[FN][4];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
@@ -227,7 +239,6 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     KALDO_SSTORE((ch + 1) & 1)
     __syncthreads();
   }
-
 #undef KALDO_GLOAD
 #undef KALDO_SSTORE
 
@@ -277,13 +288,14 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
 
 // ---- tile variants and launch ----------------------------------------------------------
 // Candidate (FM, FN) shapes, block tile 32 FM x 32 FN.  FP64 accumulators take
-// twice the registers of FP32 ones, so its candidates are one size smaller.
+// twice the registers of FP32 ones, so its candidates are one size smaller;
+// the 64-byte chunks of BF16 and FP32 load 64 rows per pass (FM, FN even).
 constexpr int kGemmVariants = 4;
 
 template <int P>
 inline int gemm_fm(int v) {
   if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
-  return v == 1 ? 2 : (v == 3 ? 3 : 4);
+  return v == 1 || v == 3 ? 2 : 4;
 }
 
 template <int P>
@@ -311,7 +323,7 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
     else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
     else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
-    else gemm_launch_tile<P, 3, 4>(g, e, st);
+    else gemm_launch_tile<P, 2, 2>(g, e, st);
   }
 }
 

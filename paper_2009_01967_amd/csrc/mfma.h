@@ -55,6 +55,32 @@ __device__ __forceinline__ void store_operand(typename Operand<P>::T* hi, typena
   }
 }
 
+// Store the adjacent pair (v0, v1) at o, o + 1 (o even) with one write per plane.
+template <int P>
+__device__ __forceinline__ void store_operand2(typename Operand<P>::T* hi, typename Operand<P>::T* lo, size_t o,
+                                               double v0, double v1) {
+  if constexpr (P == KALDO_BF16X3) {
+    const float f0 = (float)v0, f1 = (float)v1;
+    const __bf16 h0 = (__bf16)f0, h1 = (__bf16)f1;
+    const __bf16 l0 = (__bf16)(f0 - (float)h0), l1 = (__bf16)(f1 - (float)h1);
+    typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+    *reinterpret_cast<bf16x2*>(hi + o) = bf16x2{h0, h1};
+    *reinterpret_cast<bf16x2*>(lo + o) = bf16x2{l0, l1};
+  } else if constexpr (P == KALDO_FP32) {
+    *reinterpret_cast<float2*>(hi + o) = make_float2((float)v0, (float)v1);
+  } else {
+    *reinterpret_cast<double2*>(hi + o) = make_double2(v0, v1);
+  }
+}
+
+// Arguments x^2 / (2 sigma^2) of the Gaussian beyond which an element's weight
+// is dropped: 6 sigma for the mixed precisions (relative weight < 2e-8), 8.9
+// sigma for FP64 (< 5e-18, below its rounding).
+template <int P>
+__host__ __device__ constexpr double gauss_cut() {
+  return P == KALDO_FP64 ? 40.0 : 18.0;
+}
+
 // accumulator row of register r in lane l for a 16x16 tile
 template <int P>
 __device__ __forceinline__ int acc_row(int lane, int r) {
