@@ -7,7 +7,12 @@ conductivity.  Inputs (structure, fc2, fc3) are uploaded once before timing;
 outputs stay in device memory.  The mixed-precision (FP32 projection) path
 gives ``value``; the FP64 path is timed beside it.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+The many-branch workloads that run the projection as MFMA GEMMs (the 46-atom
+cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed after it,
+BF16X3 beside FP64, and reported under ``mfma_paths`` with the roofline of
+their GEMMs (``--no-mfma`` skips them).
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: one GPU only.
 """
 
 from __future__ import annotations
@@ -26,8 +31,12 @@ if ROOT not in sys.path:
 
 WORKLOAD = "diamond-2at-16x16x16-shell3"
 METRIC = "phonon linewidths/s + projection TFLOP/s, mixed vs FP64, at rel err ≤1e-4"
-FP32_VECTOR_PEAK = 157.3e12     # MI355X published vector FP32 (TFLOP/s)
+FP32_VECTOR_PEAK = 157.3e12     # MI355X published vector FP32 (FLOP/s)
 FP64_VECTOR_PEAK = 78.6e12
+BF16_MFMA_PEAK = 2.5e15         # dense bf16 MFMA
+FP32_MFMA_PEAK = 157.3e12
+FP64_MFMA_PEAK = 78.6e12
+MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 
 
 def log(*a):
@@ -104,6 +113,92 @@ def run_gpu(args):
                 wall64=wall64, kern32=kern32, kern64=kern64, g32=g32, g64=g64, k32=k32, k64=k64)
 
 
+def run_mfma(name, steps, warmup):
+    """Linewidths and kappa of a many-branch workload on resident phonons, BF16X3
+    then FP64, with the projection GEMMs timed through the library's hooks; one
+    phonon pass is timed on its own."""
+    import torch
+    from gen import workload, WORKLOADS
+    from paper_2009_01967_amd import kaldo
+
+    w = WORKLOADS[name]
+    t0 = time.perf_counter()
+    c = workload(name)
+    log(f"{name}: generated in {time.perf_counter() - t0:.1f} s")
+    T, sigma = list(w["T"]), w["sigma_thz"]
+    nk, n = c.n_k, c.n_modes
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = kaldo.Context(0, stream.cuda_stream)
+    ctx.phonons(c)
+    ctx.linewidths(c, T=T, sigma_thz=sigma, precision="bf16x3")
+    g_d = torch.empty((len(T), nk, n), dtype=torch.float64, device=dev)
+    k_d = torch.empty((len(T), 3, 3), dtype=torch.float64, device=dev)
+    kappa = kaldo.kaldo_kappa_qhgk if nk == 1 else kaldo.kaldo_kappa_rta
+
+    def step(prec):
+        h = ctx.h
+        kaldo._check(h, kaldo.kaldo_linewidths(h, None, T, sigma, kaldo.KALDO_QUANTUM, prec, g_d))
+        kaldo._check(h, kappa(h, k_d))
+
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    kaldo._check(ctx.h, kaldo.kaldo_phonons(ctx.h, None, None, c.grid, None, None))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    phonon_ms = e0.elapsed_time(e1)
+    res = {}
+    for label, prec in (("bf16x3", kaldo.KALDO_BF16X3), ("fp64", kaldo.KALDO_FP64)):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        kaldo.kaldo_profile_enable(ctx.h, True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step(prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kern = {}
+        for kname in ("eigensolve", "step_a", "step_b", "gamma_sparse", "project"):
+            tot, cnt = kaldo.kaldo_profile_read(ctx.h, kname)
+            if cnt:
+                kern[kname] = {"ms_per_step": tot / steps, "launches_per_step": cnt / steps}
+        kaldo.kaldo_profile_enable(ctx.h, False)
+        res[label] = dict(ms=ms, kern=kern, g=g_d.cpu().numpy().copy(), k=k_d.cpu().numpy().copy())
+        log(f"{name} {label}: {ms:.2f} ms/step, kernels {kern}")
+    ctx.close()
+    lw = nk * n * len(T)
+    f_c = 16.0 * nk * nk * n ** 4 if nk > 1 else 2.0 * n ** 4  # algorithmic GEMM flops, one V for both signs
+    g64 = res["fp64"]["g"]
+    floor = 1e-6 * np.abs(g64).max()
+    err = float(np.max(np.abs(res["bf16x3"]["g"] - g64) / np.maximum(np.abs(g64), floor)))
+    kerr = float(np.max(np.abs(res["bf16x3"]["k"] - res["fp64"]["k"])) / np.abs(res["fp64"]["k"]).max())
+    out = {"workload": name, "n_k": nk, "n_modes": n, "T_K": T, "sigma_thz": sigma,
+           "step": "kaldo_linewidths + kaldo_kappa on resident phonons", "phonons_ms": phonon_ms,
+           "gemm_flops_per_step": f_c, "gamma_rel_err_bf16x3_vs_fp64": err,
+           "kappa_rel_err_bf16x3_vs_fp64": kerr}
+    for label, peak in (("bf16x3", BF16_MFMA_PEAK), ("fp64", FP64_MFMA_PEAK)):
+        ms = res[label]["ms"]
+        proj = res[label]["kern"].get("project", {}).get("ms_per_step")
+        ent = {"ms_per_step": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
+               "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in res[label]["kern"].items()}}
+        if proj:
+            # BF16X3 executes three bf16 products per real product
+            executed = f_c * (3.0 if label == "bf16x3" else 1.0)
+            ent["roofline"] = {"bound": "mfma", "kernel": "k_gemm (projection GEMMs, fused epilogue)",
+                               "achieved": f_c / (proj * 1e-3) / 1e12, "executed": executed / (proj * 1e-3) / 1e12,
+                               "peak": peak / 1e12, "unit": "TFLOP/s",
+                               "frac": executed / (proj * 1e-3) / peak, "traffic": None}
+        out[label] = ent
+    out["speedup_bf16x3_vs_fp64"] = res["fp64"]["ms"] / res["bf16x3"]["ms"]
+    return out
+
+
 def cpu_baseline(r, budget_s=20.0):
     """The FP64 oracle on the host, on a bounded sample of first-mode k points."""
     from oracle import phonons as P, anharmonic as A
@@ -147,6 +242,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part "
@@ -190,6 +286,8 @@ def main():
             "flops_per_launch": f_b + f_c,
         },
     }
+    if not args.no_mfma:
+        out["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
     if not args.no_cpu:
         base, err = cpu_baseline(r)
         out["cpu_baseline"] = base
