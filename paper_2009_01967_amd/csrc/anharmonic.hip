@@ -174,8 +174,8 @@ __global__ void __launch_bounds__(256)
       const int kk = (q0 * P.G1 + q1) * P.G2 + q2;
       // p-side mode data stays in registers for all first modes s
       cplx<R> Ep[NM][NM];
-      double wp[NM], np_[NT][NM];
-      R iwp[NM];
+      double wp[NM];
+      R np_[NT][NM], iwp[NM];
 #pragma unroll
       for (int s1 = 0; s1 < NM; ++s1) {
 #pragma unroll
@@ -183,16 +183,16 @@ __global__ void __launch_bounds__(256)
         wp[s1] = OM[(size_t)s1 * nk + p];
         iwp[s1] = (R)IW[(size_t)s1 * nk + p];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) np_[t][s1] = t < P.nT ? OCC[((size_t)t * NM + s1) * nk + p] : 0.0;
+        for (int t = 0; t < NT; ++t) np_[t][s1] = t < P.nT ? (R)OCC[((size_t)t * NM + s1) * nk + p] : (R)0;
       }
 #pragma unroll 1
       for (int s = 0; s < NM; ++s) {
         const double iws = IW[(size_t)s * nk + k];
         if (iws == 0.0) continue;  // masked first mode: uniform across the block
         const double ws = OM[(size_t)s * nk + k];
-        double acc[NT];
+        R acc[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+        for (int t = 0; t < NT; ++t) acc[t] = (R)0;
         // step B: Phi = sum_Delta e^{2 pi i p.Delta} A_k[s][Delta]
         cplx<R> F[NM][NM];
 #pragma unroll
@@ -200,13 +200,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int b = 0; b < NM; ++b) F[a][b] = {(R)0, (R)0};
         const cplx<R>* As = A + ((size_t)kl * NM + s) * (size_t)P.nd * NM * NM;
+        // the phase of the next Delta is in flight while this one is applied
+        cplx<R> ph = PH[p];
         for (int d = 0; d < P.nd; ++d) {
-          const cplx<R> ph = PH[(size_t)d * nk + p];
+          const cplx<R> cur = ph;
+          if (d + 1 < P.nd) ph = PH[(size_t)(d + 1) * nk + p];
           const cplx<R>* Ad = As + (size_t)d * NM * NM;
 #pragma unroll
           for (int a = 0; a < NM; ++a)
 #pragma unroll
-            for (int b = 0; b < NM; ++b) cfma(F[a][b], ph, Ad[a * NM + b]);
+            for (int b = 0; b < NM; ++b) cfma(F[a][b], cur, Ad[a * NM + b]);
         }
         // step C + epilogue, one column s'' at a time; k''-side data is
         // re-read per column instead of being held for all s.
@@ -223,29 +226,29 @@ __global__ void __launch_bounds__(256)
           }
           const double w2 = OM[(size_t)s2 * nk + kk + z];
           const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
-          double n2[NT];
+          R n2[NT];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) n2[t] = t < P.nT ? OCC[((size_t)t * NM + s2) * nk + kk + z] : 0.0;
+          for (int t = 0; t < NT; ++t) n2[t] = t < P.nT ? (R)OCC[((size_t)t * NM + s2) * nk + kk + z] : (R)0;
 #pragma unroll
           for (int s1 = 0; s1 < NM; ++s1) {
             cplx<R> V = {(R)0, (R)0};
 #pragma unroll
             for (int a = 0; a < NM; ++a) cfma(V, Ep[a][s1], Tc[a]);
-            const double v2 = (double)((V.re * V.re + V.im * V.im) * (iwp[s1] * iw2));
+            const R v2 = (V.re * V.re + V.im * V.im) * (iwp[s1] * iw2);
             const double xp = ws + wp[s1] - w2;
             const double xm = ws - wp[s1] - w2;
-            const double gp = gauss<R>(xp, P.c) * v2;
-            const double gm = 0.5 * gauss<R>(xm, P.c) * v2;
+            const R gp = (R)gauss<R>(xp, P.c) * v2;
+            const R gm = (R)0.5 * (R)gauss<R>(xm, P.c) * v2;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-              const double n1 = np_[t][s1];
-              acc[t] += gp * (n1 - n2[t]) + gm * (1.0 + n1 + n2[t]);
+              const R n1 = np_[t][s1];
+              acc[t] += gp * (n1 - n2[t]) + gm * ((R)1 + n1 + n2[t]);
             }
           }
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          double v = acc[t];
+          double v = (double)acc[t];
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
           if (lane == 0) red[wave][s * NT + t] += v;

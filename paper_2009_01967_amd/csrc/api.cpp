@@ -327,6 +327,7 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
   if ((st = upload(ctx, L.d_gpair_start, gpstart.data(), gpstart.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_gpair_l, gpl.data(), gpl.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_grow_start, grow.data(), grow.size())) != KALDO_OK) return st;
+  L.grow_start = grow;
   if ((st = upload(ctx, L.d_gblk_i, gbi.data(), gbi.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_gblk_val, gval.data(), gval.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, L.d_cg_block, cg_block.data(), cg_block.size())) != KALDO_OK) return st;

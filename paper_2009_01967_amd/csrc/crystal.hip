@@ -108,8 +108,9 @@ __global__ void k_cr_realify(typename Operand<P>::T* __restrict__ Ach, typename 
 
 // Step B into the realified B operand of GEMM 1, every element written (zeros
 // outside the fc3 pairs and in the K padding): X[z][(s, a')][2 a'' + d] for
-// partners p = p0 + z.
-template <int P>
+// partners p = p0 + z.  One thread serves up to ZT partners of the same
+// element, so each Z value is read once per ZT partners.
+template <int P, int ZT>
 __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand<P>::T* __restrict__ Xl,
                        const cplx<double>* __restrict__ Z, const cplx<double>* __restrict__ PH,
                        const int* __restrict__ cg_delta, const int* __restrict__ cg_order,
@@ -118,30 +119,38 @@ __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand
   const int half = ldk / 2;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nn = (long long)n * n;
-  if (idx >= (long long)zb * nn * half) return;
+  if (idx >= nn * half) return;
   const int a2 = (int)(idx % half);
-  const long long row = idx / half;  // z * n^2 + s * n + a'
+  const long long row = idx / half;  // s * n + a'
   const int a1 = (int)(row % n);
-  const int s = (int)((row / n) % n);
-  const int z = (int)(row / nn);
-  const int p = p0 + z;
-  double re = 0.0, im = 0.0;
-  if (a2 < n) {
-    const int j = a1 / 3, l = a2 / 3;
-    const int cp = pairmap[(size_t)j * N + l];
+  const int s = (int)(row / n);
+  int cp = -1;
+  if (a2 < n) cp = pairmap[(size_t)(a1 / 3) * N + a2 / 3];
+  const int e9 = 3 * (a1 % 3) + a2 % 3;
+  for (int z0 = 0; z0 < zb; z0 += ZT) {
+    double re[ZT], im[ZT];
+#pragma unroll
+    for (int u = 0; u < ZT; ++u) re[u] = im[u] = 0.0;
     if (cp >= 0) {
       const int4 pr = cpair[cp];
-      const int e9 = 3 * (a1 % 3) + a2 % 3;
       for (int q = pr.z; q < pr.w; ++q) {
         const int g = cg_order[q];
-        const cplx<double> ph = PH[(size_t)cg_delta[g] * nk + p];
         const cplx<double> zz = Z[((size_t)s * ng + g) * 9 + e9];
-        re += ph.re * zz.re - ph.im * zz.im;
-        im += ph.re * zz.im + ph.im * zz.re;
+        const cplx<double>* ph = PH + (size_t)cg_delta[g] * nk + p0 + z0;
+#pragma unroll
+        for (int u = 0; u < ZT; ++u) {
+          if (z0 + u < zb) {
+            const cplx<double> f = ph[u];
+            re[u] += f.re * zz.re - f.im * zz.im;
+            im[u] += f.re * zz.im + f.im * zz.re;
+          }
+        }
       }
     }
+#pragma unroll
+    for (int u = 0; u < ZT; ++u)
+      if (z0 + u < zb) store_operand2<P>(Xh, Xl, ((size_t)(z0 + u) * nn + row) * ldk + 2 * (size_t)a2, re[u], im[u]);
   }
-  store_operand2<P>(Xh, Xl, (size_t)row * ldk + 2 * (size_t)a2, re, im);
 }
 
 // the realified pair h (0, 1) of a lane's 4 accumulator rows inside a 16-row tile at row m
@@ -406,7 +415,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
     for (int p0 = 0; p0 < nk; p0 += zb) {
       const int cnt = std::min(zb, nk - p0);
       prof_begin(ctx);
-      hipLaunchKernelGGL((k_cr_x<P>), dim3(blocks_for((long long)cnt * nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
+      hipLaunchKernelGGL((k_cr_x<P, 8>), dim3(blocks_for(nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
                          Z, PH, L.d_cg_delta.as<int>(), L.d_cg_order.as<int>(), L.d_cpair.as<int4>(),
                          L.d_cpairmap.as<int>(), n, N, nk, ng, ldk, p0, cnt);
       KALDO_HIP(ctx, hipGetLastError());

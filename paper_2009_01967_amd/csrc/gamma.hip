@@ -68,43 +68,65 @@ __global__ void k_transpose(double* __restrict__ Et, const double* __restrict__ 
 
 // ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] as the GEMM's B operand ---------
 // Rows (sl, s'') of ldy elements, columns a'.  Lanes run over s'' (coalesced reads
-// of Et); the SB modes of a block share every Et load; X_s is wave uniform and
-// read through the scalar cache.  Each block walks a run of jc atoms j.
-template <int P, int SB>
+// of Et); the SB modes of a block share every Et load.  A block walks a run of
+// jc atoms j; the X_s blocks of its pairs are staged in LDS first and read as
+// wave-wide broadcasts.  Rows of JB atoms are accumulated together so each lane
+// writes 3 JB contiguous elements.
+template <int P, int SB, int JB>
 __global__ void __launch_bounds__(256)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
               const double* __restrict__ Xs, const double* __restrict__ Et, const int* __restrict__ rstart,
               const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc) {
+  extern __shared__ double xl[];  // [block pairs][SB][9]
   const int s2 = blockIdx.x * 256 + threadIdx.x;
   const int slb = blockIdx.y * SB;
   const int j0 = blockIdx.z * jc;
   const int j1 = min(N, j0 + jc);
+  const int pb0 = rstart[j0], pb1 = rstart[j1];
+  for (int i = threadIdx.x; i < (pb1 - pb0) * SB * 9; i += 256) {
+    const int pp = i / (SB * 9), r = i % (SB * 9);
+    xl[i] = Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
+  }
+  __syncthreads();
   const bool live = s2 < n;
   const int s2c = live ? s2 : n - 1;
-  for (int j = j0; j < j1; ++j) {
-    double y[SB][3];
+  for (int jb = j0; jb < j1; jb += JB) {
+    double y[SB][3 * JB];
 #pragma unroll
-    for (int u = 0; u < SB; ++u) y[u][0] = y[u][1] = y[u][2] = 0.0;
-    const int p1 = rstart[j + 1];
-    for (int p = rstart[j]; p < p1; ++p) {
-      const size_t l3 = 3 * (size_t)pl[p];
-      const double e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
-      const double* x = Xs + ((size_t)p * sbp + slb) * 9;
+    for (int u = 0; u < SB; ++u)
 #pragma unroll
-      for (int u = 0; u < SB; ++u) {
-        y[u][0] += x[9 * u + 0] * e0 + x[9 * u + 1] * e1 + x[9 * u + 2] * e2;
-        y[u][1] += x[9 * u + 3] * e0 + x[9 * u + 4] * e1 + x[9 * u + 5] * e2;
-        y[u][2] += x[9 * u + 6] * e0 + x[9 * u + 7] * e1 + x[9 * u + 8] * e2;
+      for (int e = 0; e < 3 * JB; ++e) y[u][e] = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      const int j = jb + jj;
+      if (j >= j1) break;
+      const int p1 = rstart[j + 1];
+      for (int p = rstart[j]; p < p1; ++p) {
+        const size_t l3 = 3 * (size_t)pl[p];
+        const double e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
+        const double* x = xl + (size_t)(p - pb0) * SB * 9;
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          y[u][3 * jj + 0] += x[9 * u + 0] * e0 + x[9 * u + 1] * e1 + x[9 * u + 2] * e2;
+          y[u][3 * jj + 1] += x[9 * u + 3] * e0 + x[9 * u + 4] * e1 + x[9 * u + 5] * e2;
+          y[u][3 * jj + 2] += x[9 * u + 6] * e0 + x[9 * u + 7] * e1 + x[9 * u + 8] * e2;
+        }
       }
     }
     if (live) {
+      const int ne = 3 * min(JB, j1 - jb);  // elements of this run
 #pragma unroll
       for (int u = 0; u < SB; ++u) {
         if (slb + u < cnt) {
-          const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)j;
-          store_operand<P>(Yhi, Ylo, o, y[u][0]);
-          store_operand<P>(Yhi, Ylo, o + 1, y[u][1]);
-          store_operand<P>(Yhi, Ylo, o + 2, y[u][2]);
+          const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)jb;
+          if (ne == 3 * JB) {
+#pragma unroll
+            for (int e = 0; e < 3 * JB; e += 2) store_operand2<P>(Yhi, Ylo, o + e, y[u][e], y[u][e + 1]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 3 * JB; ++e)
+              if (e < ne) store_operand<P>(Yhi, Ylo, o + e, y[u][e]);
+          }
         }
       }
     }
@@ -326,7 +348,18 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / (sqrt(kTwoPi) * sig);
-  const int jc = 4;
+  // atoms per block (a multiple of JB): the X_s blocks of their pairs must fit in 64 KB of LDS
+  constexpr int JB = 2;
+  int jc = 4;
+  size_t y_lds = 0;
+  for (;; jc -= JB) {
+    int max_pairs = 1;
+    for (int j0 = 0; j0 < N; j0 += jc)
+      max_pairs = std::max(max_pairs, L.grow_start[std::min(N, j0 + jc)] - L.grow_start[j0]);
+    y_lds = (size_t)max_pairs * SB * 9 * sizeof(double);
+    if (y_lds <= 64 * 1024) break;
+    if (jc == JB) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
+  }
   for (int b = 0; b < nbatch; ++b) {
     const int s0 = b * sb;
     const int cnt = std::min(sb, n - s0);
@@ -337,8 +370,8 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
                          L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
                          cntp);
       KALDO_HIP(ctx, hipGetLastError());
-      hipLaunchKernelGGL((k_gamma_y<P, SB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256), 0, st,
-                         Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
+      hipLaunchKernelGGL((k_gamma_y<P, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
+                         y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
                          cnt, jc);
     } else {
       KALDO_HIP(ctx, hipMemsetAsync(Yh, 0, y_elems * S * sizeof(T), st));

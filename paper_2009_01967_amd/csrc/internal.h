@@ -80,6 +80,7 @@ struct Fc3Layout {
   DevBuf d_gpair_start;              // int [npairs + 1] -> block range of each pair
   DevBuf d_gpair_l;                  // int [npairs] atom l of each pair
   DevBuf d_grow_start;               // int [N + 1] -> pair range of each row atom j
+  std::vector<int> grow_start;       // host copy of the above
   DevBuf d_gblk_i;                   // int [nb]
   DevBuf d_gblk_val;                 // double [nb][27], divided by sqrt(m_i m_j m_l)
 };
