@@ -169,6 +169,36 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
  * with the displacement x_i - (x_j + R.cell). */
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
 
+/* Batches: the linewidths of many crystals (uneven cell sizes and grids) in
+ * one HIP graph launch.
+ *
+ * kaldo_batch_add computes the harmonic modes of one crystal on its grid
+ * (paper Sec. II.A-B, as kaldo_phonons) and keeps them with its fc3 (as
+ * kaldo_linewidths would) in a crystal context owned by ctx; *handle receives
+ * the crystal's index in the batch (0, 1, ...).  All four inputs are required
+ * host data, copied and not retained.  Errors as kaldo_phonons; adding a
+ * crystal drops a captured graph.
+ *
+ * kaldo_batch_run computes the linewidths (paper Sec. II.B, as
+ * kaldo_linewidths with the Gaussian delta) of every mode of every crystal for
+ * nT temperatures.  The first call with a given (T, sigma, statistics,
+ * precision) plans the batch (sizes every device buffer, settles the tile shape
+ * of each GEMM problem, shared by all crystals of the context), then captures
+ * the linewidth kernels of all crystals on the context's stream into one HIP
+ * graph; that and later calls with the same arguments launch the graph once.
+ * The context's stream must not be the null stream (pass NULL to kaldo_create
+ * to get an owned one).  gamma_out, if not NULL, holds one pointer per crystal
+ * in handle order, each to [nT][Nk_i][n_i] doubles (host or device memory) or
+ * NULL to skip that crystal.  Returns KALDO_ESTATE for an empty batch and the
+ * first failing crystal's status otherwise.
+ *
+ * kaldo_batch_clear releases every crystal of the batch and the graph. */
+kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
+                             const kaldo_fc3* fc3, const int32_t grid[3], int32_t* handle);
+kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                             kaldo_precision precision, double* const* gamma_out);
+kaldo_status kaldo_batch_clear(kaldo_ctx ctx);
+
 /* Tile-shape selection for the MFMA GEMMs (not a step of the method).  With
  * KALDO_TUNE_AUTO (the default) the first call that meets a GEMM shape times
  * each candidate tile shape once and keeps the fastest for the context; the

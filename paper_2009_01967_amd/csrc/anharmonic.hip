@@ -32,6 +32,24 @@ struct ProjArgs {
   double c;      // 1 / (2 sigma_omega^2)
 };
 
+// ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
+__global__ void k_fill_zero(uint4* __restrict__ p16, unsigned char* __restrict__ tail, size_t n16, size_t ntail) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) p16[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (i < ntail) tail[i] = 0;
+}
+
+kaldo_status fill_zero(kaldo_ctx ctx, void* p, size_t bytes) {
+  if (bytes == 0) return KALDO_OK;
+  // device allocations are 256-byte aligned; sub-buffers passed here are 16-byte aligned
+  const size_t n16 = bytes / 16, ntail = bytes % 16;
+  const size_t work = std::max(n16, ntail);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, ctx->stream,
+                     static_cast<uint4*>(p), static_cast<unsigned char*>(p) + n16 * 16, n16, ntail);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
 // ---- mode tables ---------------------------------------------------------------
 // OM[s][k], IW[s][k] (1/omega or 0 if masked), OCC[t][s][k]
 __global__ void k_tables(double* __restrict__ OM, double* __restrict__ IW, double* __restrict__ OCC,
@@ -360,7 +378,7 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
-  for (int k0 = 0; k0 < nk; k0 += kchunk) {
+  for (int k0 = 0; k0 < nk && !planning(ctx); k0 += kchunk) {
     const int kc = std::min(kchunk, nk - k0);
     P.k0 = k0;
     prof_begin(ctx);

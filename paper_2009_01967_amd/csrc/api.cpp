@@ -25,7 +25,7 @@ kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what) {
 }
 
 void prof_begin(kaldo_ctx ctx) {
-  if (!ctx->prof) return;
+  if (!ctx->prof || ctx->mode != kRun) return;
   if (hipEventCreate(&ctx->prof_open) != hipSuccess) {
     ctx->prof_open = nullptr;
     return;
@@ -34,7 +34,7 @@ void prof_begin(kaldo_ctx ctx) {
 }
 
 void prof_end(kaldo_ctx ctx, const char* name) {
-  if (!ctx->prof || !ctx->prof_open) return;
+  if (!ctx->prof || !ctx->prof_open || ctx->mode != kRun) return;
   hipEvent_t stop;
   if (hipEventCreate(&stop) != hipSuccess) return;
   (void)hipEventRecord(stop, ctx->stream);
@@ -64,9 +64,11 @@ void prof_clear(kaldo_ctx ctx) {
 }
 
 int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const std::function<void(int)>& launch) {
-  if (ctx->tuning != KALDO_TUNE_AUTO || nv <= 1) return fallback;
-  auto it = ctx->tuned.find(key);
-  if (it != ctx->tuned.end()) return it->second;
+  kaldo_ctx owner = ctx->tune_owner ? ctx->tune_owner : ctx;
+  if (owner->tuning != KALDO_TUNE_AUTO || nv <= 1) return fallback;
+  auto it = owner->tuned.find(key);
+  if (it != owner->tuned.end()) return it->second;
+  if (ctx->mode == kCapture) return fallback;  // no timing inside a capture
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -88,7 +90,7 @@ int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const 
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->tuned[key] = best;
+  owner->tuned[key] = best;
   return best;
 }
 
@@ -383,10 +385,19 @@ kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream) {
   return KALDO_OK;
 }
 
+static void batch_release(kaldo_ctx ctx) {
+  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+  ctx->batch_exec = nullptr;
+  ctx->batch_key.clear();
+  for (kaldo_ctx sub : ctx->batch) kaldo_destroy(sub);
+  ctx->batch.clear();
+}
+
 void kaldo_destroy(kaldo_ctx ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  batch_release(ctx);
   prof_clear(ctx);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -441,13 +452,8 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
   return KALDO_OK;
 }
 
-kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
-                              double sigma_thz, kaldo_delta delta, kaldo_stats stats,
-                              kaldo_precision precision, double* gamma_out) {
-  if (!ctx) return KALDO_EINVAL;
-  ctx->err.clear();
-  KALDO_HIP(ctx, hipSetDevice(ctx->device));
-  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_linewidths before kaldo_phonons");
+static kaldo_status check_linewidth_args(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz,
+                                         kaldo_delta delta, kaldo_stats stats, kaldo_precision precision) {
   if (!T || nT < 1 || nT > KALDO_MAX_T) return fail(ctx, KALDO_EINVAL, "need 1 <= nT <= KALDO_MAX_T temperatures");
   if (delta != KALDO_DELTA_GAUSS) return fail(ctx, KALDO_EINVAL, "only the Gaussian delta is available");
   if (stats != KALDO_QUANTUM && stats != KALDO_CLASSICAL) return fail(ctx, KALDO_EINVAL, "bad statistics");
@@ -458,7 +464,18 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
     if (!std::isfinite(T[t]) || T[t] < 0.0 || (T[t] == 0.0 && stats == KALDO_CLASSICAL))
       return fail(ctx, KALDO_EINVAL, "temperatures must be finite, >= 0 (> 0 for classical)");
   }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
+                              double sigma_thz, kaldo_delta delta, kaldo_stats stats,
+                              kaldo_precision precision, double* gamma_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_linewidths before kaldo_phonons");
   kaldo_status st;
+  if ((st = check_linewidth_args(ctx, T, nT, sigma_thz, delta, stats, precision)) != KALDO_OK) return st;
   if (fc3) {
     if ((st = load_fc3(ctx, fc3)) != KALDO_OK) return st;
   } else if (!ctx->have_fc3) {
@@ -498,6 +515,113 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
   kaldo_status st;
   if ((st = run_kappa_qhgk(ctx)) != KALDO_OK) return st;
   if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
+                             const kaldo_fc3* fc3, const int32_t grid[3], int32_t* handle) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!structure || !fc2 || !fc3 || !grid || !handle)
+    return fail(ctx, KALDO_EINVAL, "kaldo_batch_add: structure, fc2, fc3, grid and handle are required");
+  if (ctx->batch.size() >= 4096) return fail(ctx, KALDO_EINVAL, "kaldo_batch_add: at most 4096 crystals");
+  kaldo_ctx sub = nullptr;
+  kaldo_status st = kaldo_create(&sub, ctx->device, ctx->stream);
+  if (st != KALDO_OK) return fail(ctx, st, "kaldo_batch_add: cannot create a crystal context");
+  sub->tune_owner = ctx;
+  if ((st = kaldo_phonons(sub, structure, fc2, grid, nullptr, nullptr)) != KALDO_OK ||
+      (st = load_fc3(sub, fc3)) != KALDO_OK) {
+    const std::string msg = "kaldo_batch_add: " + sub->err;
+    kaldo_destroy(sub);
+    return fail(ctx, st, msg);
+  }
+  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+  ctx->batch_exec = nullptr;
+  ctx->batch_key.clear();
+  ctx->batch.push_back(sub);
+  *handle = (int32_t)ctx->batch.size() - 1;
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_batch_clear(kaldo_ctx ctx) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  batch_release(ctx);
+  return KALDO_OK;
+}
+
+// Capture the linewidth kernels of every crystal of the batch into one graph.
+static kaldo_status batch_capture(kaldo_ctx ctx, double sigma_thz, int precision) {
+  kaldo_status st = KALDO_OK;
+  // plan: size every buffer and settle every tile shape outside the capture
+  for (kaldo_ctx sub : ctx->batch) {
+    sub->mode = kPlan;
+    st = run_linewidths(sub, sigma_thz, precision);
+    sub->mode = kRun;
+    if (st != KALDO_OK) return fail(ctx, st, "kaldo_batch_run (plan): " + sub->err);
+  }
+  KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  KALDO_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  for (kaldo_ctx sub : ctx->batch) {
+    sub->mode = kCapture;
+    st = run_linewidths(sub, sigma_thz, precision);
+    sub->mode = kRun;
+    if (st != KALDO_OK) {
+      st = fail(ctx, st, "kaldo_batch_run (capture): " + sub->err);
+      break;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  if (st == KALDO_OK && e != hipSuccess) st = hip_fail(ctx, e, "hipStreamEndCapture");
+  if (st == KALDO_OK) {
+    const hipError_t ei = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      ctx->batch_exec = nullptr;
+      st = hip_fail(ctx, ei, "hipGraphInstantiate");
+    }
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  return st;
+}
+
+kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                             kaldo_precision precision, double* const* gamma_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (ctx->batch.empty()) return fail(ctx, KALDO_ESTATE, "kaldo_batch_run: the batch is empty");
+  kaldo_status st;
+  if ((st = check_linewidth_args(ctx, T, nT, sigma_thz, KALDO_DELTA_GAUSS, stats, precision)) != KALDO_OK) return st;
+  std::vector<double> key = {sigma_thz, (double)stats, (double)precision, (double)nT};
+  for (int t = 0; t < nT; ++t) key.push_back(T[t]);
+  for (kaldo_ctx sub : ctx->batch) {
+    sub->nT = nT;
+    for (int t = 0; t < nT; ++t) sub->T[t] = T[t];
+    sub->stats = stats;
+    sub->have_gamma = false;
+  }
+  if (!ctx->batch_exec || key != ctx->batch_key) {
+    if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+    ctx->batch_exec = nullptr;
+    ctx->batch_key.clear();
+    if ((st = batch_capture(ctx, sigma_thz, precision)) != KALDO_OK) return st;
+    ctx->batch_key = key;
+  }
+  prof_begin(ctx);
+  KALDO_HIP(ctx, hipGraphLaunch(ctx->batch_exec, ctx->stream));
+  prof_end(ctx, "batch_graph");
+  for (size_t i = 0; i < ctx->batch.size(); ++i) {
+    kaldo_ctx sub = ctx->batch[i];
+    sub->have_gamma = true;
+    if (gamma_out && gamma_out[i]) {
+      const size_t bytes = (size_t)nT * sub->nk * sub->nm * sizeof(double);
+      if ((st = copy_out(ctx, gamma_out[i], sub->d_gamma.p, bytes)) != KALDO_OK) return st;
+    }
+  }
   return KALDO_OK;
 }
 

@@ -343,7 +343,7 @@ template <int P, class Epi>
 static int cr_gemm(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
   const int v = autotune(ctx, key, kGemmVariants, 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
-  gemm_launch<P>(v, g, e, st);
+  if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
   return v;
 }
 
@@ -394,7 +394,10 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   int* kmap = reinterpret_cast<int*>(gr + graw_n);
   KALDO_HIP(ctx, ctx->d_gamma.ensure((size_t)nT * nk * n * sizeof(double)));
   // the K padding of Y (columns >= 2n) is never written by GEMM 1: clear once
-  if (ldk > 2 * n) KALDO_HIP(ctx, hipMemsetAsync(Yh, 0, xy_elems * S * sizeof(T), st));
+  if (ldk > 2 * n) {
+    const kaldo_status fs = fill_zero(ctx, Yh, xy_elems * S * sizeof(T));
+    if (fs != KALDO_OK) return fs;
+  }
   hipLaunchKernelGGL((k_cr_realify<P>), dim3(blocks_for((long long)nk * mrows * (ldk / 2), TB)), dim3(TB), 0, st,
                      Ach, Acl, Aph, Apl, ctx->d_evec.as<cplx<double>>(), nk, n, mrows, ldk);
   hipLaunchKernelGGL(k_cr_kmap, dim3(blocks_for((long long)nk * nk, TB)), dim3(TB), 0, st, kmap, nk, ctx->grid[0],
@@ -404,9 +407,12 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   const double cexp = 1.0 / (2.0 * sig * sig);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
-  for (int k = 0; k < nk; ++k) {
+  // planning visits one first-mode point and the batches whose GEMM shapes differ
+  const bool plan = planning(ctx);
+  for (int k = 0; k < (plan ? 1 : nk); ++k) {
     prof_begin(ctx);
-    hipLaunchKernelGGL(k_cr_zg, dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,
+    if (!plan)
+      hipLaunchKernelGGL(k_cr_zg, dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,
                        ctx->d_evec.as<cplx<double>>(), L.d_cg_block.as<int2>(), L.d_blk_i.as<int>(),
                        L.d_blk_R2.as<int>(), L.d_blk_val.as<double>(), n, ng, ctx->grid[0], ctx->grid[1],
                        ctx->grid[2], k);
@@ -414,8 +420,10 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
     prof_end(ctx, "step_a");
     for (int p0 = 0; p0 < nk; p0 += zb) {
       const int cnt = std::min(zb, nk - p0);
+      if (plan && p0 != 0 && p0 + zb < nk) continue;
       prof_begin(ctx);
-      hipLaunchKernelGGL((k_cr_x<P, 8>), dim3(blocks_for(nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
+      if (!plan)
+        hipLaunchKernelGGL((k_cr_x<P, 8>), dim3(blocks_for(nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
                          Z, PH, L.d_cg_delta.as<int>(), L.d_cg_order.as<int>(), L.d_cpair.as<int4>(),
                          L.d_cpairmap.as<int>(), n, N, nk, ng, ldk, p0, cnt);
       KALDO_HIP(ctx, hipGetLastError());
@@ -456,7 +464,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       gemm_launch<P>(w, g2, e2, st);                                                                            \
     });                                                                                                         \
     e2.m_tiles = gemm_m_tiles<P>(vt, mrows);                                                                    \
-    gemm_launch<P>(vt, g2, e2, st);                                                                             \
+    if (!plan) gemm_launch<P>(vt, g2, e2, st);                                                                  \
     v = vt;                                                                                                     \
   }
       if (nT <= 1) KALDO_EPI(1)
@@ -465,13 +473,16 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
 #undef KALDO_EPI
       KALDO_HIP(ctx, hipGetLastError());
       prof_end(ctx, "project");
+      if (plan) continue;
       hipLaunchKernelGGL(k_cr_collect, dim3(n, nT), dim3(256), 0, st, gacc, partial, n, nT,
                          gemm_m_tiles<P>(v, mrows), cnt, p0 == 0 ? 1 : 0);
       KALDO_HIP(ctx, hipGetLastError());
     }
+    if (plan) continue;
     hipLaunchKernelGGL(k_cr_finish, dim3(blocks_for(n * nT, TB)), dim3(TB), 0, st, gr, gacc, IW, n, nk, nT, k, C);
     KALDO_HIP(ctx, hipGetLastError());
   }
+  if (plan) return KALDO_OK;
   hipLaunchKernelGGL(k_cr_set_average, dim3(blocks_for((long long)n * nk * nT, TB)), dim3(TB), 0, st,
                      ctx->d_gamma.as<double>(), gr, ctx->d_setid.as<int>(), n, nk, nT);
   KALDO_HIP(ctx, hipGetLastError());

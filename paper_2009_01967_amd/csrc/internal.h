@@ -87,7 +87,17 @@ struct Fc3Layout {
 
 }  // namespace kaldo
 
+namespace kaldo {
+// How a stage runs: kRun launches everything; kPlan sizes every buffer, builds
+// the mode tables and settles the tile shape of each GEMM problem, but skips
+// the heavy launches; kCapture launches everything with no allocation, no
+// memset node, no timing and no host synchronisation (stream capture).
+enum RunMode { kRun = 0, kPlan = 1, kCapture = 2 };
+}  // namespace kaldo
+
 struct kaldo_ctx_s {
+  int mode = kaldo::kRun;
+
   // kernel timing instrumentation
   bool prof = false;
   struct ProfEntry {
@@ -98,9 +108,16 @@ struct kaldo_ctx_s {
   std::map<std::string, ProfEntry> prof_tab;
   hipEvent_t prof_open = nullptr;
 
-  // tile shapes chosen by the autotuner, per problem key
+  // tile shapes chosen by the autotuner, per problem key (kept by tune_owner
+  // when set: the crystals of a batch share their parent's choices)
   int tuning = KALDO_TUNE_AUTO;
   std::map<std::string, int> tuned;
+  kaldo_ctx_s* tune_owner = nullptr;
+
+  // batch of crystals: resident sub-contexts and the captured linewidth graph
+  std::vector<kaldo_ctx_s*> batch;
+  hipGraphExec_t batch_exec = nullptr;
+  std::vector<double> batch_key;     // parameters the graph was captured with
 
   int device = 0;
   hipStream_t stream = nullptr;
@@ -170,6 +187,11 @@ kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what);
 void prof_begin(kaldo_ctx ctx);
 void prof_end(kaldo_ctx ctx, const char* name);
 void prof_clear(kaldo_ctx ctx);
+
+// zero device memory with a fill kernel (capturable, unlike a memset node)
+kaldo_status fill_zero(kaldo_ctx ctx, void* p, size_t bytes);
+
+inline bool planning(kaldo_ctx ctx) { return ctx->mode == kPlan; }
 
 // copy a device result into a caller pointer that may be host or device memory
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);

@@ -40,8 +40,9 @@ STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALD
                 -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
 
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
-            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_set_tuning",
-            "kaldo_profile_enable", "kaldo_profile_read"]
+            "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
+            "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
+            "kaldo_profile_read"]
 
 
 class kaldo_structure(C.Structure):
@@ -93,6 +94,14 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
+    lib.kaldo_batch_add.argtypes = [C.c_void_p, C.POINTER(kaldo_structure), C.POINTER(kaldo_fc2),
+                                    C.POINTER(kaldo_fc3), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.kaldo_batch_add.restype = C.c_int
+    lib.kaldo_batch_run.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int, C.c_int,
+                                    C.POINTER(C.c_void_p)]
+    lib.kaldo_batch_run.restype = C.c_int
+    lib.kaldo_batch_clear.argtypes = [C.c_void_p]
+    lib.kaldo_batch_clear.restype = C.c_int
     lib.kaldo_set_tuning.argtypes = [C.c_void_p, C.c_int]
     lib.kaldo_set_tuning.restype = C.c_int
     lib.kaldo_profile_enable.argtypes = [C.c_void_p, C.c_int]
@@ -212,6 +221,30 @@ def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_qhgk(ctx, _out_ptr(kappa_out))
 
 
+def kaldo_batch_add(ctx, structure, fc2, fc3, grid):
+    """Add one crystal to the context's batch; returns (status, handle)."""
+    g = (C.c_int32 * 3)(*[int(x) for x in grid])
+    h = C.c_int32(-1)
+    st = load_library().kaldo_batch_add(ctx, C.byref(structure), C.byref(fc2), C.byref(fc3), g, C.byref(h))
+    return st, h.value
+
+
+def kaldo_batch_run(ctx, T: Sequence[float], sigma_thz: float, stats: int, precision: int, gamma_outs) -> int:
+    """gamma_outs: one output (numpy array, device tensor or None) per crystal, or None."""
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    arr = None
+    if gamma_outs is not None:
+        arr = (C.c_void_p * max(1, len(gamma_outs)))()
+        for i, o in enumerate(gamma_outs):
+            p = _out_ptr(o)
+            arr[i] = p.value if p is not None else None
+    return load_library().kaldo_batch_run(ctx, Ts, len(T), float(sigma_thz), int(stats), int(precision), arr)
+
+
+def kaldo_batch_clear(ctx) -> int:
+    return load_library().kaldo_batch_clear(ctx)
+
+
 def kaldo_set_tuning(ctx, mode: int) -> int:
     """KALDO_TUNE_AUTO (0) or KALDO_TUNE_FIXED (1)."""
     return load_library().kaldo_set_tuning(ctx, int(mode))
@@ -290,6 +323,34 @@ class Context:
         _check(self.h, kaldo_linewidths(self.h, f3, T, sigma_thz,
                                         KALDO_CLASSICAL if classical else KALDO_QUANTUM, prec, gamma_out))
         return gamma_out
+
+    def batch_add(self, crystal) -> int:
+        """Add a crystal (its modes are computed now, on crystal.grid); returns its handle."""
+        keep = _Keep()
+        s = make_structure(crystal.cell, crystal.positions, crystal.masses, keep)
+        f2 = make_fc2(crystal.fc2_i, crystal.fc2_j, crystal.fc2_R, crystal.fc2_val, keep)
+        f3 = make_fc3(crystal.fc3_i, crystal.fc3_j, crystal.fc3_l, crystal.fc3_R1, crystal.fc3_R2,
+                      crystal.fc3_val, keep)
+        st, h = kaldo_batch_add(self.h, s, f2, f3, crystal.grid)
+        _check(self.h, st)
+        if not hasattr(self, "batch_shapes"):
+            self.batch_shapes = []
+        self.batch_shapes.append((int(np.prod(crystal.grid)), 3 * crystal.n_atoms))
+        return h
+
+    def batch_run(self, T=(300.0,), sigma_thz=0.1, precision="fp32", classical=False, outs=None):
+        """Linewidths of every crystal of the batch (one graph launch); returns
+        the list of per-crystal outputs ([nT][Nk][n] numpy arrays by default)."""
+        if outs is None:
+            outs = [np.zeros((len(T), nk, n)) for nk, n in getattr(self, "batch_shapes", [])]
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(self.h, kaldo_batch_run(self.h, T, sigma_thz, KALDO_CLASSICAL if classical else KALDO_QUANTUM,
+                                       prec, outs))
+        return outs
+
+    def batch_clear(self):
+        _check(self.h, kaldo_batch_clear(self.h))
+        self.batch_shapes = []
 
     def kappa_rta(self, out=None, want_host=True):
         if want_host and out is None:

@@ -1,0 +1,97 @@
+"""Batches: the linewidths of many crystals of uneven cell size and grid in one
+HIP graph launch (kaldo_batch_add / kaldo_batch_run), against the FP64 oracle
+and against eager per-crystal calls, with repeated replays of the graph.
+
+The crystals come from the seeded batch generator of the 32-crystal workload
+(cells of 2..54 atoms, grids 4^3..10^3); the test draws fewer, smaller ones
+(2..8 atoms, grids 2^3..4^3) so that the oracle covers every mode, plus a
+2-atom cell that takes the few-branch kernel inside the same graph."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from gen import batch_crystals
+from oracle import phonons as P, anharmonic as A
+from tests.parity import TOL, gamma_error
+
+pytestmark = pytest.mark.gpu
+
+T = [300.0, 700.0]
+SIGMA = 0.2
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    crystals = batch_crystals(count=6, n_range=(2, 8), g_range=(2, 4))
+    crystals.append(batch_crystals(count=1, n_range=(2, 2), g_range=(3, 3))[0])
+    refs = []
+    for c in crystals:
+        _say(f"oracle: {c.name} {c.n_atoms} atoms, grid {c.grid}")
+        ph = P.phonons(c, velocities=False)
+        refs.append((ph, A.linewidths(c, ph, T, SIGMA)))
+    return crystals, refs
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_graph_against_oracle_and_replays(batch, precision):
+    from paper_2009_01967_amd import kaldo
+    crystals, refs = batch
+    _say(f"case: batch of {len(crystals)} crystals, {precision}")
+    with kaldo.Context(0) as ctx:
+        for i, c in enumerate(crystals):
+            assert ctx.batch_add(c) == i
+        first = ctx.batch_run(T=T, sigma_thz=SIGMA, precision=precision)
+        for c, (ph, g_ref), g in zip(crystals, refs, first):
+            err = gamma_error(g, g_ref, ph.mask)
+            _say(f"  {c.n_atoms} atoms, grid {c.grid}: error {err:.3e}")
+            assert err < TOL[precision], (c.n_atoms, c.grid, err)
+        # replays of the captured graph, with other eager GPU work in between,
+        # give the first launch's results bit for bit
+        with kaldo.Context(0) as other:
+            for r in range(3):
+                other.phonons(crystals[r])
+                other.linewidths(crystals[r], T=T, sigma_thz=SIGMA, precision=precision)
+                again = ctx.batch_run(T=T, sigma_thz=SIGMA, precision=precision)
+                for g0, g1 in zip(first, again):
+                    assert np.array_equal(g0, g1), f"replay {r} differs"
+        _say("  3 replays identical")
+
+
+def test_batch_matches_eager_calls(batch):
+    """Each crystal of the batch equals its own eager kaldo_linewidths call with
+    the same fixed tile shapes."""
+    from paper_2009_01967_amd import kaldo
+    crystals, _ = batch
+    _say("case: batch vs eager, fixed tiles, fp32")
+    with kaldo.Context(0) as ctx:
+        kaldo._check(ctx.h, kaldo.kaldo_set_tuning(ctx.h, kaldo.KALDO_TUNE_FIXED))
+        for c in crystals:
+            ctx.batch_add(c)
+        got = ctx.batch_run(T=T, sigma_thz=SIGMA, precision="fp32")
+    for c, g in zip(crystals, got):
+        with kaldo.Context(0) as e:
+            kaldo._check(e.h, kaldo.kaldo_set_tuning(e.h, kaldo.KALDO_TUNE_FIXED))
+            e.phonons(c)
+            ge = e.linewidths(c, T=T, sigma_thz=SIGMA, precision="fp32")
+        assert np.array_equal(g, ge), (c.n_atoms, c.grid)
+
+
+def test_batch_errors():
+    from paper_2009_01967_amd import kaldo
+    with kaldo.Context(0) as ctx:
+        st = kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
+        assert st == kaldo.KALDO_ESTATE
+        c = batch_crystals(count=1, n_range=(2, 2), g_range=(2, 2))[0]
+        ctx.batch_add(c)
+        st = kaldo.kaldo_batch_run(ctx.h, T, -1.0, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
+        assert st == kaldo.KALDO_EINVAL
+        kaldo._check(ctx.h, kaldo.kaldo_batch_clear(ctx.h))
+        st = kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
+        assert st == kaldo.KALDO_ESTATE
