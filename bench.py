@@ -243,11 +243,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
+    ap.add_argument("--no-main", action="store_true",
+                    help="skip the headline workload (prints only the MFMA workloads; for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part "
               f"of this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}))
+        return
+    if args.no_main:
+        print(json.dumps({"mfma_paths": [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]}))
+        return
     r = run_gpu(args)
     nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
     lw = nk * n * nT

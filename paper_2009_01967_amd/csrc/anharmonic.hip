@@ -29,6 +29,7 @@ struct ProjArgs {
   int nk, nd, nT;
   int k0;
   int ppt;       // p points per thread
+  int k_local;   // XCD-aware order: the p tiles of one k on one XCD
   double c;      // 1 / (2 sigma_omega^2)
 };
 
@@ -171,7 +172,19 @@ __global__ void __launch_bounds__(256)
     k_project_small(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ PH, const cplx<R>* __restrict__ ET,
                     const double* __restrict__ OM, const double* __restrict__ IW, const double* __restrict__ OCC,
                     ProjArgs P, double* __restrict__ partial) {
-  const int kl = blockIdx.y;
+  // XCD-aware order.  Workgroups are dealt round-robin to the 8 XCDs, so in
+  // launch order each XCD sees a fixed subset of p tiles for every k: its L2
+  // holds 1/8 of the p-side tables but every XCD fetches every A_k.  When the
+  // p-side tables fit one L2 (P.k_local), the flat id is remapped instead so
+  // that the p tiles of one k run on one XCD and A_k is fetched once.
+  int pchunk = (int)blockIdx.x, kl = (int)blockIdx.y;
+  if (P.k_local) {
+    const int nb = (int)(gridDim.x * gridDim.y), b = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+    const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
+    const int tile = x8 * q8 + (x8 < r8 ? x8 : r8) + (b >> 3);
+    pchunk = tile % (int)gridDim.x;
+    kl = tile / (int)gridDim.x;
+  }
   const int k = P.k0 + kl;
   const int nk = P.nk;
   const int km0 = k / (P.G1 * P.G2), km1 = (k / P.G2) % P.G1, km2 = k % P.G2;
@@ -182,7 +195,7 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
 
   for (int it = 0; it < P.ppt; ++it) {
-    const int p = (blockIdx.x * P.ppt + it) * blockDim.x + threadIdx.x;
+    const int p = (pchunk * P.ppt + it) * blockDim.x + threadIdx.x;
     if (p < nk) {
       const int pm0 = p / (P.G1 * P.G2), pm1 = (p / P.G2) % P.G1, pm2 = p % P.G2;
       int q0 = km0 + pm0, q1 = km1 + pm1, q2 = km2 + pm2;
@@ -274,12 +287,12 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  // block reduction -> partial[kl][blockIdx.x][t][s]
+  // block reduction -> partial[kl][pchunk][t][s]
   __syncthreads();
   if (threadIdx.x < NM * NT) {
     const int s = threadIdx.x / NT, t = threadIdx.x % NT;
     const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-    if (t < P.nT) partial[(((size_t)kl * gridDim.x + blockIdx.x) * P.nT + t) * NM + s] = v;
+    if (t < P.nT) partial[(((size_t)kl * gridDim.x + pchunk) * P.nT + t) * NM + s] = v;
   }
 }
 
@@ -374,6 +387,9 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   P.nd = nd;
   P.nT = nT;
   P.ppt = ppt;
+  // p-side tables read by every block: eigenvectors, phases, mode tables
+  const size_t p_side = et_bytes + ph_bytes + tab_bytes;
+  P.k_local = p_side <= ((size_t)7 << 19) ? 1 : 0;  // 3.5 MB of a 4 MB L2
   P.c = 1.0 / (2.0 * sig * sig);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
