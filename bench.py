@@ -37,6 +37,13 @@ BF16_MFMA_PEAK = 2.5e15         # dense bf16 MFMA
 FP32_MFMA_PEAK = 157.3e12
 FP64_MFMA_PEAK = 78.6e12
 MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
+# HBM bytes per launch of the headline kernel: rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE over this benchmark (--steps 2 --warmup 1 --no-cpu --no-mfma), each
+# scaled by what the counter reads for a plain 1 GiB device copy
+# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Taken on the
+# current k_project_small; set to None when that kernel changes.
+HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3>", "fetch_kib": 184510.9, "write_kib": 9218.9,
+                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def log(*a):
@@ -48,6 +55,17 @@ def algorithmic_flops(nk, n, nd):
     f_b = 8.0 * nk * nk * nd * n ** 3
     f_c = 16.0 * nk * nk * n ** 4
     return f_b, f_c
+
+
+def algorithmic_bytes(nk, n, nd, nT):
+    """Unique bytes the projection kernel must read and write once (FP32 path):
+    the step-A tensor, eigenvectors, Delta phases, mode tables and the partial sums."""
+    a = nk * n * nd * n * n * 8          # A_k[s][Delta][a'][a''] complex float
+    et = n * n * nk * 8                  # eigenvectors, complex float
+    ph = nd * nk * 8                     # phases, complex float
+    tab = (2 + nT) * n * nk * 8          # omega, 1/omega, occupations (double)
+    part = nk * (nk // 256) * nT * n * 8  # per-tile partial sums (double)
+    return float(a + et + ph + tab + part)
 
 
 def run_gpu(args):
@@ -299,7 +317,10 @@ def main():
             "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
-            "traffic": None,
+            "traffic": (HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
+                        HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0,
+            "traffic_unit": "HBM bytes per launch (scaled rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+            "algorithmic_bytes": algorithmic_bytes(nk, n, nd, nT),
             "flops_per_launch": f_b + f_c,
         },
     }
