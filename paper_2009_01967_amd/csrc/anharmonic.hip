@@ -167,11 +167,15 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
-template <typename R, int NM, int NT>
+// LDS_A: the block's A_k (all s and Delta) is staged in LDS once and read as
+// wave-wide broadcasts; otherwise it is read from global memory through the
+// scalar cache (cells whose A_k does not fit).
+template <typename R, int NM, int NT, bool LDS_A>
 __global__ void __launch_bounds__(256)
     k_project_small(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ PH, const cplx<R>* __restrict__ ET,
                     const double* __restrict__ OM, const double* __restrict__ IW, const double* __restrict__ OCC,
                     ProjArgs P, double* __restrict__ partial) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   // XCD-aware order.  Workgroups are dealt round-robin to the 8 XCDs, so in
   // launch order each XCD sees a fixed subset of p tiles for every k: its L2
   // holds 1/8 of the p-side tables but every XCD fetches every A_k.  When the
@@ -192,6 +196,13 @@ __global__ void __launch_bounds__(256)
   __shared__ double red[4][NM * NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x < 4 * NM * NT) (&red[0][0])[threadIdx.x] = 0.0;
+  const size_t a_per_k = (size_t)NM * P.nd * NM * NM;  // complex elements of A_k
+  const cplx<R>* Ablk = A + (size_t)kl * a_per_k;
+  if constexpr (LDS_A) {
+    cplx<R>* As = reinterpret_cast<cplx<R>*>(smem);
+    for (size_t i = threadIdx.x; i < a_per_k; i += blockDim.x) As[i] = Ablk[i];
+    Ablk = As;
+  }
   __syncthreads();
 
   for (int it = 0; it < P.ppt; ++it) {
@@ -230,7 +241,7 @@ __global__ void __launch_bounds__(256)
         for (int a = 0; a < NM; ++a)
 #pragma unroll
           for (int b = 0; b < NM; ++b) F[a][b] = {(R)0, (R)0};
-        const cplx<R>* As = A + ((size_t)kl * NM + s) * (size_t)P.nd * NM * NM;
+        const cplx<R>* As = Ablk + (size_t)s * P.nd * NM * NM;
         // the phase of the next Delta is in flight while this one is applied
         cplx<R> ph = PH[p];
         for (int d = 0; d < P.nd; ++d) {
@@ -323,20 +334,37 @@ __global__ void k_finalize(double* __restrict__ gamma, const double* __restrict_
   }
 }
 
+template <typename R, int NM, bool LDS_A>
+static void launch_project_t(dim3 grid, size_t lds, hipStream_t st, const cplx<R>* A, const cplx<R>* PH,
+                             const cplx<R>* ET, const double* OM, const double* IW, const double* OCC,
+                             const ProjArgs& P, double* partial) {
+#define KALDO_LAUNCH(NTV)                                                                                    \
+  {                                                                                                           \
+    if (lds > 64 * 1024)                                                                                      \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_small<R, NM, NTV, LDS_A>),          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
+    hipLaunchKernelGGL((k_project_small<R, NM, NTV, LDS_A>), grid, dim3(256), lds, st, A, PH, ET, OM, IW, OCC, \
+                       P, partial);                                                                           \
+  }
+  if (P.nT <= 1) KALDO_LAUNCH(1)
+  else if (P.nT <= 2) KALDO_LAUNCH(2)
+  else if (P.nT <= 3) KALDO_LAUNCH(3)
+  else if (P.nT <= 4) KALDO_LAUNCH(4)
+  else KALDO_LAUNCH(8)
+#undef KALDO_LAUNCH
+}
+
+// A_k goes to LDS when it fits: beside a second resident block for FP32 (two
+// waves per SIMD), alone for FP64 (whose registers allow one)
 template <typename R, int NM>
 static void launch_project(dim3 grid, hipStream_t st, const cplx<R>* A, const cplx<R>* PH, const cplx<R>* ET,
                            const double* OM, const double* IW, const double* OCC, const ProjArgs& P,
                            double* partial) {
-  if (P.nT <= 1)
-    hipLaunchKernelGGL((k_project_small<R, NM, 1>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
-  else if (P.nT <= 2)
-    hipLaunchKernelGGL((k_project_small<R, NM, 2>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
-  else if (P.nT <= 3)
-    hipLaunchKernelGGL((k_project_small<R, NM, 3>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
-  else if (P.nT <= 4)
-    hipLaunchKernelGGL((k_project_small<R, NM, 4>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  const size_t lds = (size_t)NM * P.nd * NM * NM * sizeof(cplx<R>);
+  if (lds <= (sizeof(R) == 4 ? 76 : 150) * 1024)
+    launch_project_t<R, NM, true>(grid, lds, st, A, PH, ET, OM, IW, OCC, P, partial);
   else
-    hipLaunchKernelGGL((k_project_small<R, NM, 8>), grid, dim3(256), 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+    launch_project_t<R, NM, false>(grid, 0, st, A, PH, ET, OM, IW, OCC, P, partial);
 }
 
 template <typename R>
