@@ -30,7 +30,7 @@ struct ProjArgs {
   int k0;
   int ppt;       // p points per thread
   int k_local;   // XCD-aware order: the p tiles of one k on one XCD
-  double c;      // 1 / (2 sigma_omega^2)
+  double rc;     // 1 / (sqrt(2) sigma_omega): frequencies are scaled by it
 };
 
 // ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
@@ -147,17 +147,18 @@ __global__ void k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict
 }
 
 // ---- fused step B + step C + epilogue ----------------------------------------------
+// exp(-x^2) with x the frequency mismatch in units of sqrt(2) sigma
 template <typename R>
-__device__ __forceinline__ double gauss(double x, double c);
+__device__ __forceinline__ R gauss(double x);
 
 template <>
-__device__ __forceinline__ double gauss<double>(double x, double c) {
-  return exp(-x * x * c);
+__device__ __forceinline__ double gauss<double>(double x) {
+  return exp(-x * x);
 }
 
 template <>
-__device__ __forceinline__ double gauss<float>(double x, double c) {
-  return (double)__expf((float)(-x * x * c));
+__device__ __forceinline__ float gauss<float>(double x) {
+  return __expf((float)(-x * x));
 }
 
 // Opaque zero: keeps loads inside a loop (bounds register pressure).
@@ -222,7 +223,7 @@ __global__ void __launch_bounds__(256)
       for (int s1 = 0; s1 < NM; ++s1) {
 #pragma unroll
         for (int a = 0; a < NM; ++a) Ep[a][s1] = ET[((size_t)s1 * NM + a) * nk + p];
-        wp[s1] = OM[(size_t)s1 * nk + p];
+        wp[s1] = OM[(size_t)s1 * nk + p] * P.rc;  // frequencies in units of sqrt(2) sigma
         iwp[s1] = (R)IW[(size_t)s1 * nk + p];
 #pragma unroll
         for (int t = 0; t < NT; ++t) np_[t][s1] = t < P.nT ? (R)OCC[((size_t)t * NM + s1) * nk + p] : (R)0;
@@ -231,7 +232,7 @@ __global__ void __launch_bounds__(256)
       for (int s = 0; s < NM; ++s) {
         const double iws = IW[(size_t)s * nk + k];
         if (iws == 0.0) continue;  // masked first mode: uniform across the block
-        const double ws = OM[(size_t)s * nk + k];
+        const double ws = OM[(size_t)s * nk + k] * P.rc;
         R acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = (R)0;
@@ -266,7 +267,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int b = 0; b < NM; ++b) cfma_conj(Tc[a], F[a][b], ET[col + (size_t)b * nk]);
           }
-          const double w2 = OM[(size_t)s2 * nk + kk + z];
+          const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / (sqrt(2) sigma)
           const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
           R n2[NT];
 #pragma unroll
@@ -277,15 +278,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int a = 0; a < NM; ++a) cfma(V, Ep[a][s1], Tc[a]);
             const R v2 = (V.re * V.re + V.im * V.im) * (iwp[s1] * iw2);
-            const double xp = ws + wp[s1] - w2;
-            const double xm = ws - wp[s1] - w2;
-            const R gp = (R)gauss<R>(xp, P.c) * v2;
-            const R gm = (R)0.5 * (R)gauss<R>(xm, P.c) * v2;
+            const R gp = (R)gauss<R>(d2 + wp[s1]) * v2;
+            const R gm = (R)0.5 * (R)gauss<R>(d2 - wp[s1]) * v2;
+            // gp (n' - n'') + gm (1 + n' + n'') = gm + n' (gp + gm) + n'' (gm - gp)
+            const R sp = gp + gm, sm = gm - gp;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const R n1 = np_[t][s1];
-              acc[t] += gp * (n1 - n2[t]) + gm * ((R)1 + n1 + n2[t]);
-            }
+            for (int t = 0; t < NT; ++t) acc[t] += gm + np_[t][s1] * sp + n2[t] * sm;
           }
         }
 #pragma unroll
@@ -418,7 +416,7 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   // p-side tables read by every block: eigenvectors, phases, mode tables
   const size_t p_side = et_bytes + ph_bytes + tab_bytes;
   P.k_local = p_side <= ((size_t)7 << 19) ? 1 : 0;  // 3.5 MB of a 4 MB L2
-  P.c = 1.0 / (2.0 * sig * sig);
+  P.rc = 1.0 / (sqrt(2.0) * sig);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
