@@ -342,7 +342,7 @@ kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double*
 template <int P, class Epi>
 static int cr_gemm(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
-  const int v = autotune(ctx, key, kGemmVariants, 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
+  const int v = autotune(ctx, key, gemm_variants<P>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
   if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
   return v;
 }
@@ -459,7 +459,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   {                                                                                                             \
     EpiCrystal<NTV> e2{OM, IW, OCC, kmap + (size_t)k * nk + p0, partial, nn, n, nk, nT, k, p0, 0, cexp};       \
     /* the partial layout depends on the row tiling of the variant that runs */                               \
-    const int vt = autotune(ctx, key2, kGemmVariants, 0, [&](int w) {                                           \
+    const int vt = autotune(ctx, key2, gemm_variants<P>(), 0, [&](int w) {                                           \
       e2.m_tiles = gemm_m_tiles<P>(w, mrows);                                                                   \
       gemm_launch<P>(w, g2, e2, st);                                                                            \
     });                                                                                                         \

@@ -289,7 +289,7 @@ __global__ void k_tables_gamma(double* __restrict__ OM, double* __restrict__ IW,
 template <int P, int NT>
 static int gemm_lw(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const EpiGamma<NT>& e) {
   hipStream_t st = ctx->stream;
-  const int v = autotune(ctx, key, kGemmVariants, 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
+  const int v = autotune(ctx, key, gemm_variants<P>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
   if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
   return v;
 }

@@ -14,8 +14,8 @@
 // the current one feeds the matrix cores.  The short chunk keeps the staging
 // registers and the LDS tile small enough for two blocks per CU, so one
 // block's loads and epilogue overlap the other's matrix work, and it keeps the
-// K padding of short contractions small.  LDS rows are padded by 16 bytes,
-// which keeps the fragment reads of 16 consecutive rows on distinct banks.
+// K padding of short contractions small.  The LDS layout (see lds_off) keeps
+// fragment reads and staging stores free of bank conflicts.
 //
 // Fragment reads: the MFMA sums over k, so any bijection between (lane group
 // g = lane / 16, step j) and the k index of a chunk gives the same result as
@@ -67,19 +67,38 @@ struct TileAt {
 
 __device__ __forceinline__ uint4 lds_read16(const char* p) { return *reinterpret_cast<const uint4*>(p); }
 
-template <int P, int FM, int FN, class Epi>
+// LDS byte offset of 16-byte slot `slot` of tile row `row`.  64-byte rows
+// (the BF16 and FP32 chunks) are unpadded and XOR-swizzled: the physical slot
+// is slot ^ f(row mod 16) with f = (0,0,1,1,3,3,2,2,1,1,0,0,2,2,3,3).  Of the
+// layouts measured (16-byte row padding, this swizzle, slot-major groups with
+// either staging order) it gave the fastest GEMMs: slot-major groups remove
+// every bank conflict of the fragment reads but move them to the staging
+// stores or cost coalescing of the staging loads.  128-byte rows (FP64) are
+// padded by 16 bytes.
+template <int CB>
+__device__ __forceinline__ int lds_off(int row, int slot) {
+  if constexpr (CB == 64) return row * 64 + ((slot ^ (int)((0xfa05af50u >> (2 * (row & 15))) & 3u)) << 4);
+  else return row * (CB + 16) + slot * 16;
+}
+
+// BD (BF16X3 only): B fragments go from global memory (L1/L2) straight to the
+// wavefront's registers one chunk ahead, and LDS stages A alone.  The split
+// operands make BF16X3 LDS-bound; this halves its LDS traffic.
+template <int P, int FM, int FN, class Epi, bool BD = false>
 __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   using T = typename Operand<P>::T;
   using Acc = typename Operand<P>::Acc;
   constexpr int S = Operand<P>::split;
+  static_assert(!BD || P == KALDO_BF16X3, "direct B fragments are a BF16X3 variant");
   constexpr int BM = 32 * FM, BN = 32 * FN;
   constexpr int CB = GemmChunk<P>::CB;
-  constexpr int RB = CB + 16;                 // LDS row bytes
+  constexpr int RB = CB == 64 ? 64 : CB + 16; // LDS bytes per tile row (see lds_off)
   constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
   constexpr int RPP = 256 / SLOTS;            // rows loaded per pass of the block
-  constexpr int NA = BM / RPP, NB = BN / RPP; // passes for A and B
-  static_assert(NA * RPP == BM && NB * RPP == BN, "tile rows must be whole load passes");
-  constexpr int ROWS = BM + BN;
+  constexpr int NA = BM / RPP;                // passes for A
+  constexpr int NB = BD ? 0 : BN / RPP;       // passes for B (none when B is direct)
+  static_assert(NA * RPP == BM && (BD || NB * RPP == BN), "tile rows must be whole load passes");
+  constexpr int ROWS = BM + (BD ? 0 : BN);
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
   __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
@@ -96,11 +115,13 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int slot = tid % SLOTS;   // 16-byte slot of the row chunk
-  const int row0 = tid / SLOTS;   // first row of this thread's slots
+  // 16-byte slot of the row chunk and first row of this thread's slots: each
+  // quad of lanes loads one contiguous row chunk (coalesced global reads)
+  const int slot = tid % SLOTS;
+  const int row0 = tid / SLOTS;
 
   // global element offsets of this thread's load slots (rows clamped to existing ones)
-  long long aoff[NA], boff[NB];
+  long long aoff[NA], boff[NB > 0 ? NB : 1];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
     int row = mt * BM + row0 + RPP * u;
@@ -135,7 +156,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
     _Pragma("unroll") for (int u = 0; u < NA + NB; ++u) {                                              \
       const int row = (u < NA ? 0 : BM - RPP * NA) + row0 + RPP * u;                                    \
-      *reinterpret_cast<uint4*>(lds + (BUFI) * BUF + (s * ROWS + row) * RB + slot * 16) = rg[s][u];     \
+      *reinterpret_cast<uint4*>(lds + (BUFI) * BUF + lds_off<CB>(s * ROWS + row, slot)) = rg[s][u];     \
     }                                                                                                   \
   }
 
@@ -151,8 +172,28 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int brow = BM + wn * 16 * FN + (lane & 15);
   const int grp = lane >> 4;
 
+  // direct B fragments: this lane's element offsets of its FN fragment rows
+  long long bfo[BD ? FN : 1];
+  bf16x8 bcur[BD ? FN : 1][2], bnx[BD ? FN : 1][2];
+  if constexpr (BD) {
+#pragma unroll
+    for (int c = 0; c < FN; ++c) {
+      long long row = (long long)nt * BN + wn * 16 * FN + 16 * c + (lane & 15);
+      row = row < g.c_valid ? row : g.c_valid - 1;
+      bfo[c] = (long long)z * g.b_z + row * g.ldb + 8 * grp;
+    }
+  }
+#define KALDO_BLOAD(K0, DST)                                                                              \
+  _Pragma("unroll") for (int c = 0; c < FN; ++c) {                                                      \
+    _Pragma("unroll") for (int s = 0; s < 2; ++s) DST[c][s] =                                           \
+        *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + (K0));                                         \
+  }
+
   const int nchunk = g.K / GemmChunk<P>::KC;
   KALDO_GLOAD(0)
+  if constexpr (BD) {
+    KALDO_BLOAD(0, bcur)
+  }
   KALDO_SSTORE(0)
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
@@ -160,6 +201,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     // into the buffer nobody reads any more keeps the loop free of branches)
     const int nxt = (ch + 1 < nchunk ? ch + 1 : ch) * GemmChunk<P>::KC;
     KALDO_GLOAD(nxt)
+    if constexpr (BD) {
+      KALDO_BLOAD(nxt, bnx)
+    }
     const char* base = lds + (ch & 1) * BUF;
     if constexpr (P == KALDO_BF16X3) {
 #pragma unroll
@@ -169,13 +213,17 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
         for (int s = 0; s < 2; ++s) {
 #pragma unroll
           for (int a = 0; a < FM; ++a) {
-            const uint4 v = lds_read16(base + (s * ROWS + arow + 16 * a) * RB + j * 64 + grp * 16);
+            const uint4 v = lds_read16(base + lds_off<CB>(s * ROWS + arow + 16 * a, 4 * j + grp));
             af[a][s] = __builtin_bit_cast(bf16x8, v);
           }
 #pragma unroll
           for (int c = 0; c < FN; ++c) {
-            const uint4 v = lds_read16(base + (s * ROWS + brow + 16 * c) * RB + j * 64 + grp * 16);
-            bf[c][s] = __builtin_bit_cast(bf16x8, v);
+            if constexpr (BD) {
+              bf[c][s] = bcur[c][s];
+            } else {
+              const uint4 v = lds_read16(base + lds_off<CB>(s * ROWS + brow + 16 * c, 4 * j + grp));
+              bf[c][s] = __builtin_bit_cast(bf16x8, v);
+            }
           }
         }
 #pragma unroll
@@ -193,10 +241,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
         f32x4 af[FM], bf[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
-          af[a] = __builtin_bit_cast(f32x4, lds_read16(base + (arow + 16 * a) * RB + h * 64 + grp * 16));
+          af[a] = __builtin_bit_cast(f32x4, lds_read16(base + lds_off<CB>(arow + 16 * a, 4 * h + grp)));
 #pragma unroll
         for (int c = 0; c < FN; ++c)
-          bf[c] = __builtin_bit_cast(f32x4, lds_read16(base + (brow + 16 * c) * RB + h * 64 + grp * 16));
+          bf[c] = __builtin_bit_cast(f32x4, lds_read16(base + lds_off<CB>(brow + 16 * c, 4 * h + grp)));
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -210,7 +258,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
       double af[FM][4], bf[FN][4];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
-        const char* p = base + (arow + 16 * a) * RB + grp * 32;
+        const char* p = base + lds_off<CB>(arow + 16 * a, 2 * grp);
         const uint4 v0 = lds_read16(p), v1 = lds_read16(p + 16);
         const double2 d0 = __builtin_bit_cast(double2, v0), d1 = __builtin_bit_cast(double2, v1);
         af[a][0] = d0.x;
@@ -220,7 +268,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
       }
 #pragma unroll
       for (int c = 0; c < FN; ++c) {
-        const char* p = base + (brow + 16 * c) * RB + grp * 32;
+        const char* p = base + lds_off<CB>(brow + 16 * c, 2 * grp);
         const uint4 v0 = lds_read16(p), v1 = lds_read16(p + 16);
         const double2 d0 = __builtin_bit_cast(double2, v0), d1 = __builtin_bit_cast(double2, v1);
         bf[c][0] = d0.x;
@@ -237,10 +285,18 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
             acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][j], bf[c][j], acc[a][c], 0, 0, 0);
     }
     KALDO_SSTORE((ch + 1) & 1)
+    if constexpr (BD) {
+#pragma unroll
+      for (int c = 0; c < FN; ++c) {
+        bcur[c][0] = bnx[c][0];
+        bcur[c][1] = bnx[c][1];
+      }
+    }
     __syncthreads();
   }
 #undef KALDO_GLOAD
 #undef KALDO_SSTORE
+#undef KALDO_BLOAD
 
   TileAt at;
   at.mt = mt;
@@ -290,12 +346,18 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
 // Candidate (FM, FN) shapes, block tile 32 FM x 32 FN.  FP64 accumulators take
 // twice the registers of FP32 ones, so its candidates are one size smaller;
 // the 64-byte chunks of BF16 and FP32 load 64 rows per pass (FM, FN even).
-constexpr int kGemmVariants = 4;
+// BF16X3 adds two candidates (4 and 5) whose B fragments bypass LDS.
+constexpr int kGemmVariantsMax = 6;
+
+template <int P>
+inline int gemm_variants() {
+  return P == KALDO_BF16X3 ? 6 : 4;
+}
 
 template <int P>
 inline int gemm_fm(int v) {
   if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
-  return v == 1 || v == 3 ? 2 : 4;
+  return v == 1 || v == 3 || v == 5 ? 2 : 4;
 }
 
 template <int P>
@@ -304,12 +366,12 @@ inline int gemm_m_tiles(int v, int m) {
   return (m + bm - 1) / bm;
 }
 
-template <int P, int FM, int FN, class Epi>
+template <int P, int FM, int FN, class Epi, bool BD = false>
 inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
   g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
   const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
-  hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
+  hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi, BD>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
 }
 
 template <int P, class Epi>
@@ -319,11 +381,18 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     else if (v == 1) gemm_launch_tile<P, 4, 2>(g, e, st);
     else if (v == 2) gemm_launch_tile<P, 2, 2>(g, e, st);
     else gemm_launch_tile<P, 3, 2>(g, e, st);
-  } else {
+  } else if constexpr (P == KALDO_FP32) {
     if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
     else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
     else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
     else gemm_launch_tile<P, 2, 2>(g, e, st);
+  } else {
+    if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
+    else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
+    else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
+    else if (v == 3) gemm_launch_tile<P, 2, 2>(g, e, st);
+    else if (v == 4) gemm_launch_tile<P, 4, 4, Epi, true>(g, e, st);
+    else gemm_launch_tile<P, 2, 4, Epi, true>(g, e, st);
   }
 }
 
