@@ -42,7 +42,7 @@ MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 # scaled by what the counter reads for a plain 1 GiB device copy
 # (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Taken on the
 # current k_project_small; set to None when that kernel changes.
-HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3>", "fetch_kib": 184510.9, "write_kib": 9218.9,
+HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3,true>", "fetch_kib": 98128.1, "write_kib": 9225.7,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -313,7 +313,7 @@ def main():
         "speedup_fp32_vs_fp64": r["ms64"] / r["ms32"],
         "kernels_ms": {k: v["avg_ms"] for k, v in r["kern32"].items()},
         "roofline": {
-            "bound": "alu", "kernel": "k_project_small<float,6,3>",
+            "bound": "alu", "kernel": HEADLINE_TRAFFIC["kernel"],
             "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
