@@ -43,8 +43,10 @@ __host__ __device__ __forceinline__ int cr_rows(int n) {
   return P == KALDO_FP64 ? 8 * ((n + 3) / 4) : 2 * n;
 }
 
-// Z[s][g][e9] for one first-mode k
-__global__ void k_cr_zg(cplx<double>* __restrict__ Z, const cplx<double>* __restrict__ E,
+// Z[s][g][e9] for one first-mode k (formed in FP64, stored as RZ: FP64 for the
+// FP64 path, FP32 for the mixed ones)
+template <typename RZ>
+__global__ void k_cr_zg(cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ E,
                         const int2* __restrict__ cgb, const int* __restrict__ bi, const int* __restrict__ bR2,
                         const double* __restrict__ bval, int n, int ng, int G0, int G1, int G2, int k) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -70,7 +72,7 @@ __global__ void k_cr_zg(cplx<double>* __restrict__ Z, const cplx<double>* __rest
     re += sr * c - si * sn;
     im += sr * sn + si * c;
   }
-  Z[idx] = {re, im};
+  Z[idx] = {(RZ)re, (RZ)im};
 }
 
 // Realified eigenvector operands for every grid point, rows cr_row(i, c), K = ldk:
@@ -110,9 +112,9 @@ __global__ void k_cr_realify(typename Operand<P>::T* __restrict__ Ach, typename 
 // outside the fc3 pairs and in the K padding): X[z][(s, a')][2 a'' + d] for
 // partners p = p0 + z.  One thread serves up to ZT partners of the same
 // element, so each Z value is read once per ZT partners.
-template <int P, int ZT>
+template <int P, int ZT, typename RZ>
 __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand<P>::T* __restrict__ Xl,
-                       const cplx<double>* __restrict__ Z, const cplx<double>* __restrict__ PH,
+                       const cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ PH,
                        const int* __restrict__ cg_delta, const int* __restrict__ cg_order,
                        const int4* __restrict__ cpair, const int* __restrict__ pairmap, int n, int N, int nk, int ng,
                        int ldk, int p0, int zb) {
@@ -128,28 +130,29 @@ __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand
   if (a2 < n) cp = pairmap[(size_t)(a1 / 3) * N + a2 / 3];
   const int e9 = 3 * (a1 % 3) + a2 % 3;
   for (int z0 = 0; z0 < zb; z0 += ZT) {
-    double re[ZT], im[ZT];
+    RZ re[ZT], im[ZT];
 #pragma unroll
-    for (int u = 0; u < ZT; ++u) re[u] = im[u] = 0.0;
+    for (int u = 0; u < ZT; ++u) re[u] = im[u] = (RZ)0;
     if (cp >= 0) {
       const int4 pr = cpair[cp];
       for (int q = pr.z; q < pr.w; ++q) {
         const int g = cg_order[q];
-        const cplx<double> zz = Z[((size_t)s * ng + g) * 9 + e9];
+        const cplx<RZ> zz = Z[((size_t)s * ng + g) * 9 + e9];
         const cplx<double>* ph = PH + (size_t)cg_delta[g] * nk + p0 + z0;
 #pragma unroll
         for (int u = 0; u < ZT; ++u) {
           if (z0 + u < zb) {
-            const cplx<double> f = ph[u];
-            re[u] += f.re * zz.re - f.im * zz.im;
-            im[u] += f.re * zz.im + f.im * zz.re;
+            const RZ fr = (RZ)ph[u].re, fi = (RZ)ph[u].im;
+            re[u] += fr * zz.re - fi * zz.im;
+            im[u] += fr * zz.im + fi * zz.re;
           }
         }
       }
     }
 #pragma unroll
     for (int u = 0; u < ZT; ++u)
-      if (z0 + u < zb) store_operand2<P>(Xh, Xl, ((size_t)(z0 + u) * nn + row) * ldk + 2 * (size_t)a2, re[u], im[u]);
+      if (z0 + u < zb)
+        store_operand2<P>(Xh, Xl, ((size_t)(z0 + u) * nn + row) * ldk + 2 * (size_t)a2, (double)re[u], (double)im[u]);
   }
 }
 
@@ -387,8 +390,10 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   const size_t graw_n = (size_t)nT * nk * n;
   KALDO_HIP(ctx, ctx->d_scratch2.ensure(z_elems * sizeof(cplx<double>) + (part + gacc_n + graw_n) * sizeof(double) +
                                         (size_t)nk * nk * sizeof(int)));
-  cplx<double>* Z = ctx->d_scratch2.as<cplx<double>>();
-  double* partial = reinterpret_cast<double*>(Z + z_elems);
+  // Z is stored in RZ (FP64 for the FP64 path, FP32 otherwise) in a slot sized for FP64
+  using RZ = typename std::conditional<P == KALDO_FP64, double, float>::type;
+  cplx<RZ>* Z = ctx->d_scratch2.as<cplx<RZ>>();
+  double* partial = reinterpret_cast<double*>(ctx->d_scratch2.as<cplx<double>>() + z_elems);
   double* gacc = partial + part;
   double* gr = gacc + gacc_n;
   int* kmap = reinterpret_cast<int*>(gr + graw_n);
@@ -412,7 +417,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   for (int k = 0; k < (plan ? 1 : nk); ++k) {
     prof_begin(ctx);
     if (!plan)
-      hipLaunchKernelGGL(k_cr_zg, dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,
+      hipLaunchKernelGGL((k_cr_zg<RZ>), dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,
                        ctx->d_evec.as<cplx<double>>(), L.d_cg_block.as<int2>(), L.d_blk_i.as<int>(),
                        L.d_blk_R2.as<int>(), L.d_blk_val.as<double>(), n, ng, ctx->grid[0], ctx->grid[1],
                        ctx->grid[2], k);
@@ -423,7 +428,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       if (plan && p0 != 0 && p0 + zb < nk) continue;
       prof_begin(ctx);
       if (!plan)
-        hipLaunchKernelGGL((k_cr_x<P, 8>), dim3(blocks_for(nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
+        hipLaunchKernelGGL((k_cr_x<P, 8, RZ>), dim3(blocks_for(nn * (ldk / 2), TB)), dim3(TB), 0, st, Xh, Xl,
                          Z, PH, L.d_cg_delta.as<int>(), L.d_cg_order.as<int>(), L.d_cpair.as<int4>(),
                          L.d_cpairmap.as<int>(), n, N, nk, ng, ldk, p0, cnt);
       KALDO_HIP(ctx, hipGetLastError());

@@ -51,7 +51,8 @@ __global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E
 }
 
 // Et[a][s] = eta_s[a]: 32 x 32 tiles through LDS, both sides coalesced.
-__global__ void k_transpose(double* __restrict__ Et, const double* __restrict__ E, int n) {
+template <typename R>
+__global__ void k_transpose(R* __restrict__ Et, const double* __restrict__ E, int n) {
   __shared__ double t[32][33];
   const int s0 = blockIdx.x * 32, a0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
@@ -62,22 +63,24 @@ __global__ void k_transpose(double* __restrict__ Et, const double* __restrict__ 
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int a = a0 + r, s = s0 + tx;
-    if (a < n && s < n) Et[(size_t)a * n + s] = t[tx][r];
+    if (a < n && s < n) Et[(size_t)a * n + s] = (R)t[tx][r];
   }
 }
 
 // ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] as the GEMM's B operand ---------
 // Rows (sl, s'') of ldy elements, columns a'.  Lanes run over s'' (coalesced reads
-// of Et); the SB modes of a block share every Et load.  A block walks a run of
+// of Et); the SB modes of a block share every Et load.  R is FP64 for the FP64
+// path and FP32 for the mixed ones (Y then enters FP32 or BF16 hi+lo operands).  A block walks a run of
 // jc atoms j; the X_s blocks of its pairs are staged in LDS first and read as
 // wave-wide broadcasts.  Rows of JB atoms are accumulated together so each lane
 // writes 3 JB contiguous elements.
-template <int P, int SB, int JB>
+template <int P, typename R, int SB, int JB>
 __global__ void __launch_bounds__(256)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
-              const double* __restrict__ Xs, const double* __restrict__ Et, const int* __restrict__ rstart,
+              const double* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
               const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc) {
-  extern __shared__ double xl[];  // [block pairs][SB][9]
+  extern __shared__ __attribute__((aligned(16))) char xlraw[];
+  R* xl = reinterpret_cast<R*>(xlraw);  // [block pairs][SB][9]
   const int s2 = blockIdx.x * 256 + threadIdx.x;
   const int slb = blockIdx.y * SB;
   const int j0 = blockIdx.z * jc;
@@ -85,17 +88,17 @@ __global__ void __launch_bounds__(256)
   const int pb0 = rstart[j0], pb1 = rstart[j1];
   for (int i = threadIdx.x; i < (pb1 - pb0) * SB * 9; i += 256) {
     const int pp = i / (SB * 9), r = i % (SB * 9);
-    xl[i] = Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
+    xl[i] = (R)Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
   }
   __syncthreads();
   const bool live = s2 < n;
   const int s2c = live ? s2 : n - 1;
   for (int jb = j0; jb < j1; jb += JB) {
-    double y[SB][3 * JB];
+    R y[SB][3 * JB];
 #pragma unroll
     for (int u = 0; u < SB; ++u)
 #pragma unroll
-      for (int e = 0; e < 3 * JB; ++e) y[u][e] = 0.0;
+      for (int e = 0; e < 3 * JB; ++e) y[u][e] = (R)0;
 #pragma unroll
     for (int jj = 0; jj < JB; ++jj) {
       const int j = jb + jj;
@@ -103,8 +106,8 @@ __global__ void __launch_bounds__(256)
       const int p1 = rstart[j + 1];
       for (int p = rstart[j]; p < p1; ++p) {
         const size_t l3 = 3 * (size_t)pl[p];
-        const double e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
-        const double* x = xl + (size_t)(p - pb0) * SB * 9;
+        const R e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
+        const R* x = xl + (size_t)(p - pb0) * SB * 9;
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
           y[u][3 * jj + 0] += x[9 * u + 0] * e0 + x[9 * u + 1] * e1 + x[9 * u + 2] * e2;
@@ -121,11 +124,12 @@ __global__ void __launch_bounds__(256)
           const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)jb;
           if (ne == 3 * JB) {
 #pragma unroll
-            for (int e = 0; e < 3 * JB; e += 2) store_operand2<P>(Yhi, Ylo, o + e, y[u][e], y[u][e + 1]);
+            for (int e = 0; e < 3 * JB; e += 2)
+              store_operand2<P>(Yhi, Ylo, o + e, (double)y[u][e], (double)y[u][e + 1]);
           } else {
 #pragma unroll
             for (int e = 0; e < 3 * JB; ++e)
-              if (e < ne) store_operand<P>(Yhi, Ylo, o + e, y[u][e]);
+              if (e < ne) store_operand<P>(Yhi, Ylo, o + e, (double)y[u][e]);
           }
         }
       }
@@ -298,7 +302,9 @@ template <int P>
 static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   using T = typename Operand<P>::T;
   constexpr int S = Operand<P>::split;
-  constexpr int SB = 8;
+  // sparse step: FP64 for the FP64 path, FP32 with 16 first modes per E load otherwise
+  using RY = typename std::conditional<P == KALDO_FP64, double, float>::type;
+  constexpr int SB = P == KALDO_FP64 ? 8 : 16;
   const int N = ctx->n_atoms, n = ctx->nm, nT = ctx->nT;
   const int KC = GemmChunk<P>::KC;
   const int ld = (n + KC - 1) / KC * KC;  // K padded to whole chunks
@@ -327,7 +333,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   double* gr = OCC + (size_t)nT * n;
   double* partial = gr + graw;
   double* Xs = partial + part;
-  double* Et = Xs + xs;
+  RY* Et = reinterpret_cast<RY*>(Xs + xs);
   // operands: A [n][ld] planes, Y [sb * n][ld] planes
   const size_t a_elems = (size_t)n * ld, y_elems = (size_t)sb * n * ld;
   KALDO_HIP(ctx, ctx->d_A.ensure((a_elems + y_elems) * S * sizeof(T)));
@@ -345,7 +351,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   hipLaunchKernelGGL(k_tables_gamma, dim3(blocks_for(n, TB)), dim3(TB), 0, st, OM, IW, OCC,
                      ctx->d_omega.as<double>(), n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
   hipLaunchKernelGGL((k_gamma_a<P>), dim3(blocks_for((long long)n * ld, TB)), dim3(TB), 0, st, Ah, Al, E, n, ld);
-  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et, E, n);
+  hipLaunchKernelGGL((k_transpose<RY>), dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et, E, n);
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / (sqrt(kTwoPi) * sig);
@@ -357,7 +363,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     int max_pairs = 1;
     for (int j0 = 0; j0 < N; j0 += jc)
       max_pairs = std::max(max_pairs, L.grow_start[std::min(N, j0 + jc)] - L.grow_start[j0]);
-    y_lds = (size_t)max_pairs * SB * 9 * sizeof(double);
+    y_lds = (size_t)max_pairs * SB * 9 * sizeof(RY);
     if (y_lds <= 64 * 1024) break;
     if (jc == JB) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
   }
@@ -374,7 +380,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
                          L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
                          cntp);
       KALDO_HIP(ctx, hipGetLastError());
-      hipLaunchKernelGGL((k_gamma_y<P, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
+      hipLaunchKernelGGL((k_gamma_y<P, RY, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
                          y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
                          cnt, jc);
     } else if ((fs = fill_zero(ctx, Yh, y_elems * S * sizeof(T))) != KALDO_OK) {

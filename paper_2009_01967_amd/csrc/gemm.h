@@ -346,12 +346,14 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
 // Candidate (FM, FN) shapes, block tile 32 FM x 32 FN.  FP64 accumulators take
 // twice the registers of FP32 ones, so its candidates are one size smaller;
 // the 64-byte chunks of BF16 and FP32 load 64 rows per pass (FM, FN even).
-// BF16X3 adds two candidates (4 and 5) whose B fragments bypass LDS.
-constexpr int kGemmVariantsMax = 6;
+// BF16X3 adds candidates 4 and 5, whose B fragments bypass LDS, and 6, a
+// 128 x 256 block tile (64 x 128 per wavefront: twice the MFMA work per LDS
+// fragment read and half the A-panel re-reads).
+constexpr int kGemmVariantsMax = 7;
 
 template <int P>
 inline int gemm_variants() {
-  return P == KALDO_BF16X3 ? 6 : 4;
+  return P == KALDO_BF16X3 ? 7 : 4;
 }
 
 template <int P>
@@ -392,7 +394,8 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
     else if (v == 3) gemm_launch_tile<P, 2, 2>(g, e, st);
     else if (v == 4) gemm_launch_tile<P, 4, 4, Epi, true>(g, e, st);
-    else gemm_launch_tile<P, 2, 4, Epi, true>(g, e, st);
+    else if (v == 5) gemm_launch_tile<P, 2, 4, Epi, true>(g, e, st);
+    else gemm_launch_tile<P, 4, 8>(g, e, st);
   }
 }
 
