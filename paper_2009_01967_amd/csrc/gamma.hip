@@ -78,58 +78,75 @@ template <int P, typename R, int SB, int JB>
 __global__ void __launch_bounds__(256)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
               const double* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
-              const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc) {
+              const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc, int js) {
   extern __shared__ __attribute__((aligned(16))) char xlraw[];
-  R* xl = reinterpret_cast<R*>(xlraw);  // [block pairs][SB][9]
+  // X_s blocks of the staged pairs, [pair][SB][XP]: each 3 x 3 block padded to
+  // XP values (16-byte multiple) so that it is read with wave-wide ds_read_b128
+  constexpr int XP = sizeof(R) == 4 ? 12 : 10;
+  R* xl = reinterpret_cast<R*>(xlraw);
   const int s2 = blockIdx.x * 256 + threadIdx.x;
   const int slb = blockIdx.y * SB;
-  const int j0 = blockIdx.z * jc;
-  const int j1 = min(N, j0 + jc);
-  const int pb0 = rstart[j0], pb1 = rstart[j1];
-  for (int i = threadIdx.x; i < (pb1 - pb0) * SB * 9; i += 256) {
-    const int pp = i / (SB * 9), r = i % (SB * 9);
-    xl[i] = (R)Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
-  }
-  __syncthreads();
+  const int jbeg = blockIdx.z * jc;
+  const int jend = min(N, jbeg + jc);
   const bool live = s2 < n;
   const int s2c = live ? s2 : n - 1;
-  for (int jb = j0; jb < j1; jb += JB) {
-    R y[SB][3 * JB];
+  // the block walks jc atoms in sub-runs of js, staging the X_s blocks of each
+  // sub-run in LDS; one lane writes a long contiguous run of its row
+  for (int j0 = jbeg; j0 < jend; j0 += js) {
+    const int j1 = min(jend, j0 + js);
+    const int pb0 = rstart[j0], pb1 = rstart[j1];
+    __syncthreads();  // the previous sub-run is done with the staged blocks
+    for (int i = threadIdx.x; i < (pb1 - pb0) * SB * 9; i += 256) {
+      const int pp = i / (SB * 9), r = i % (SB * 9), u = r / 9;
+      xl[((size_t)pp * SB + u) * XP + r % 9] = (R)Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
+    }
+    __syncthreads();
+    for (int jb = j0; jb < j1; jb += JB) {
+      R y[SB][3 * JB];
 #pragma unroll
-    for (int u = 0; u < SB; ++u)
+      for (int u = 0; u < SB; ++u)
 #pragma unroll
-      for (int e = 0; e < 3 * JB; ++e) y[u][e] = (R)0;
+        for (int e = 0; e < 3 * JB; ++e) y[u][e] = (R)0;
 #pragma unroll
-    for (int jj = 0; jj < JB; ++jj) {
-      const int j = jb + jj;
-      if (j >= j1) break;
-      const int p1 = rstart[j + 1];
-      for (int p = rstart[j]; p < p1; ++p) {
-        const size_t l3 = 3 * (size_t)pl[p];
-        const R e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
-        const R* x = xl + (size_t)(p - pb0) * SB * 9;
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = jb + jj;
+        if (j >= j1) break;
+        const int p1 = rstart[j + 1];
+        for (int p = rstart[j]; p < p1; ++p) {
+          const size_t l3 = 3 * (size_t)pl[p];
+          const R e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
+          const R* x = xl + (size_t)(p - pb0) * SB * XP;
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-          y[u][3 * jj + 0] += x[9 * u + 0] * e0 + x[9 * u + 1] * e1 + x[9 * u + 2] * e2;
-          y[u][3 * jj + 1] += x[9 * u + 3] * e0 + x[9 * u + 4] * e1 + x[9 * u + 5] * e2;
-          y[u][3 * jj + 2] += x[9 * u + 6] * e0 + x[9 * u + 7] * e1 + x[9 * u + 8] * e2;
+          for (int u = 0; u < SB; ++u) {
+            // the padded block as XP / (16 / sizeof(R)) 16-byte reads
+            R xu[XP];
+            const uint4* src = reinterpret_cast<const uint4*>(x + XP * u);
+#pragma unroll
+            for (int q = 0; q < XP * (int)sizeof(R) / 16; ++q) {
+              const uint4 v = src[q];
+              __builtin_memcpy(&xu[q * 16 / sizeof(R)], &v, 16);
+            }
+            y[u][3 * jj + 0] += xu[0] * e0 + xu[1] * e1 + xu[2] * e2;
+            y[u][3 * jj + 1] += xu[3] * e0 + xu[4] * e1 + xu[5] * e2;
+            y[u][3 * jj + 2] += xu[6] * e0 + xu[7] * e1 + xu[8] * e2;
+          }
         }
       }
-    }
-    if (live) {
-      const int ne = 3 * min(JB, j1 - jb);  // elements of this run
+      if (live) {
+        const int ne = 3 * min(JB, j1 - jb);  // elements of this run
 #pragma unroll
-      for (int u = 0; u < SB; ++u) {
-        if (slb + u < cnt) {
-          const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)jb;
-          if (ne == 3 * JB) {
+        for (int u = 0; u < SB; ++u) {
+          if (slb + u < cnt) {
+            const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)jb;
+            if (ne == 3 * JB) {
 #pragma unroll
-            for (int e = 0; e < 3 * JB; e += 2)
-              store_operand2<P>(Yhi, Ylo, o + e, (double)y[u][e], (double)y[u][e + 1]);
-          } else {
+              for (int e = 0; e < 3 * JB; e += 2)
+                store_operand2<P>(Yhi, Ylo, o + e, (double)y[u][e], (double)y[u][e + 1]);
+            } else {
 #pragma unroll
-            for (int e = 0; e < 3 * JB; ++e)
-              if (e < ne) store_operand<P>(Yhi, Ylo, o + e, (double)y[u][e]);
+              for (int e = 0; e < 3 * JB; ++e)
+                if (e < ne) store_operand<P>(Yhi, Ylo, o + e, (double)y[u][e]);
+            }
           }
         }
       }
@@ -355,18 +372,21 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / (sqrt(kTwoPi) * sig);
-  // atoms per block (a multiple of JB): the X_s blocks of their pairs must fit in 64 KB of LDS
+  // atoms per block jc, staged in sub-runs of js atoms (multiples of JB) whose
+  // X_s blocks must fit in 64 KB of LDS.  Short runs (one sub-run per block)
+  // measured fastest: runs of 32 atoms halved the speed (fewer blocks in flight).
   constexpr int JB = 2;
-  int jc = 4;
+  int js = 4;
   size_t y_lds = 0;
-  for (;; jc -= JB) {
+  for (;; js -= JB) {
     int max_pairs = 1;
-    for (int j0 = 0; j0 < N; j0 += jc)
-      max_pairs = std::max(max_pairs, L.grow_start[std::min(N, j0 + jc)] - L.grow_start[j0]);
-    y_lds = (size_t)max_pairs * SB * 9 * sizeof(RY);
+    for (int j0 = 0; j0 < N; j0 += js)
+      max_pairs = std::max(max_pairs, L.grow_start[std::min(N, j0 + js)] - L.grow_start[j0]);
+    y_lds = (size_t)max_pairs * SB * (sizeof(RY) == 4 ? 12 : 10) * sizeof(RY);
     if (y_lds <= 64 * 1024) break;
-    if (jc == JB) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
+    if (js == JB) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
   }
+  const int jc = js;
   for (int b = 0; b < nbatch; ++b) {
     // planning visits the batches whose GEMM shapes differ: the first and the last
     if (planning(ctx) && b != 0 && b != nbatch - 1) continue;
@@ -382,7 +402,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
       KALDO_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL((k_gamma_y<P, RY, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
                          y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
-                         cnt, jc);
+                         cnt, jc, js);
     } else if ((fs = fill_zero(ctx, Yh, y_elems * S * sizeof(T))) != KALDO_OK) {
       return fs;
     }
