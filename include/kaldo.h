@@ -78,8 +78,14 @@ typedef enum {
   KALDO_BF16X3 = 2     /* projection GEMMs as BF16 hi+lo split (3 MFMAs), FP32 accumulate */
 } kaldo_precision;
 
+/* Finite-width energy delta of eq. delta_deconstructed (the three kinds the
+ * paper's appendix names).  Each has unit area in angular frequency with the
+ * width s = 2 pi sigma_thz: Gaussian of standard deviation s; Lorentzian of
+ * half width at half maximum s; triangle of half base s. */
 typedef enum {
-  KALDO_DELTA_GAUSS = 0 /* Gaussian energy delta (Appendix A) */
+  KALDO_DELTA_GAUSS = 0,
+  KALDO_DELTA_LORENTZ = 1,
+  KALDO_DELTA_TRIANGLE = 2
 } kaldo_delta;
 
 typedef enum {
@@ -146,7 +152,11 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
 /* Three-phonon linewidths (paper Sec. II.B) of every mode on the grid of the
  * last kaldo_phonons call, for each of nT temperatures.
  *   T          [nT] temperatures [K] (> 0 unless classical), 1 <= nT <= KALDO_MAX_T
- *   sigma_thz  Gaussian width (standard deviation) in THz, > 0
+ *   sigma_thz  width of the energy delta in THz (see kaldo_delta), > 0
+ *   delta      kind of energy delta; the GPU drops a 16 x 16 tile of GEMM
+ *              products whose Gaussian arguments all exceed 6 sigma (mixed
+ *              precisions) or 8.9 sigma (FP64), or that all lie outside the
+ *              triangle; Lorentzian tails are kept
  *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
  *              resident for kaldo_kappa_*)
  * Every precision is accepted on every grid.  Cells with n = 3 or 6 branches
@@ -155,6 +165,23 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
 kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
                               double sigma_thz, kaldo_delta delta, kaldo_stats stats,
                               kaldo_precision precision, double* gamma_out);
+
+/* Normalised three-phonon phase space per mode (paper Sec. II.B, eq.
+ * phase_space and the per-mode sum that follows it) of every mode on the grid
+ * of the last kaldo_phonons call, for each of nT temperatures:
+ *   g_mu = (1/N_k) [ sum (n' - n'') delta(w + w' - w'')  over k'' = k + k'
+ *                  + 1/2 sum (1 + n' + n'') delta(w - w' - w'')  over k'' = k - k' ]
+ * summed over k', s', s'': the linewidth sum with the matrix-element factor
+ * (hbar pi / 8) |phi|^2 / (w w' w'') replaced by 1, hence the same 1/N_k and
+ * 1/2 on decay.  Needs frequencies only (no fc3); runs in FP64.
+ *   T, sigma_thz, delta, stats  as for kaldo_linewidths
+ *   g_out      [nT][Nk][n] phase space [ps/rad] (host or device), required;
+ *              0 for masked modes (nu < 0.01 THz).  Nothing is kept resident
+ *              and the state used by kaldo_kappa_* is not touched.
+ * Errors: KALDO_ESTATE before kaldo_phonons, KALDO_EINVAL for bad arguments or
+ * g_out == NULL. */
+kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_delta delta,
+                               kaldo_stats stats, double* g_out);
 
 /* RTA conductivity (paper eq. RTA) from the last linewidths:
  *   kappa_out [nT][3][3] W/(m K).  Degenerate sets enter through the basis

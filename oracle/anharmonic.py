@@ -10,10 +10,12 @@ Paper passages followed:
   eta_ks eta+-_k's' eta*_k''s'' chi+-_k'l' chi*_k''l'', with eta+ = eta, chi+ = chi,
   eta- = eta*, chi- = chi*, chi_kl = exp(-i q_k . R_l).
 * Sec. II.B, eq. gamma_operators: Gamma+- = (hbar pi / 8) g+- / (omega omega' omega'') |phi+-|^2.
-* Sec. II.B, eq. phase_space: g+ = (n' - n'') delta+, g- = (1 + n' + n'') delta-.
+* Sec. II.B, eq. phase_space: g+ = (n' - n'') delta+, g- = (1 + n' + n'') delta-,
+  and the normalised phase space per mode g_mu that follows it.
 * Sec. II.B, eq. delta_deconstructed: momentum Kronecker q +- q' - q'' = Q, and an
   energy delta.  The momentum delta is exact here: k'' = (k +- k') mod grid.
-* Appendix A: the energy delta is a broadened (here Gaussian) function.
+* Appendix A: the energy delta is a broadened function; the paper names three
+  implementations, Gaussian, Lorentzian and triangular.
 * Sec. II.B: Gamma^0 = sum (Gamma+ + Gamma-); tau = 1 / (2 Gamma^0).
 
 Readings of points the paper leaves open:
@@ -24,9 +26,17 @@ Readings of points the paper leaves open:
   Fermi-golden-rule half width (in rad/ps) of a phonon for the Hamiltonian
   term (1/3!) phi''' u u u of eq. potential_expansion.  The tests pin it
   against a Fock-space golden-rule calculation.
-* The Gaussian delta is in angular frequency: delta(x) = exp(-x^2 / 2 s^2) /
-  (sqrt(2 pi) s), s = 2 pi sigma_THz, not truncated.
+* The deltas are in angular frequency with width s = 2 pi sigma_THz and unit
+  area, none truncated: Gaussian exp(-x^2 / 2 s^2) / (sqrt(2 pi) s) with s the
+  standard deviation; Lorentzian s / (pi (x^2 + s^2)) with s the half width at
+  half maximum; triangle max(0, 1 - |x| / s) / s with s the half base.  The
+  paper gives no formula for the last two; these are their plain forms.
 * Masked modes (nu < 0.01 THz) take no part as mu, mu' or mu''; their gamma is 0.
+* Phase space per mode.  The paper normalises g_mu = sum_{mu' mu''} g / N
+  without saying which N or how the two processes combine.  Here
+  g_mu = (1/N_k) [ sum_{k's's''} g+ + 1/2 sum_{k's's''} g- ] in ps/rad: gamma_mu
+  with the matrix-element factor (hbar pi / 8) |phi|^2 / (omega omega'
+  omega'') replaced by 1, so the same counting (1/N_k, the 1/2 on creation).
 * gamma is averaged over each degenerate set at k (only set averages are
   basis independent).
 """
@@ -53,6 +63,19 @@ def occupation(omega, T, stats='quantum'):
 
 def gaussian_delta(x, sigma_omega):
     return np.exp(-0.5 * (x / sigma_omega) ** 2) / (np.sqrt(2.0 * np.pi) * sigma_omega)
+
+
+def lorentzian_delta(x, sigma_omega):
+    """Lorentzian of half width at half maximum sigma_omega, unit area."""
+    return sigma_omega / (np.pi * (x * x + sigma_omega * sigma_omega))
+
+
+def triangular_delta(x, sigma_omega):
+    """Triangle of half base sigma_omega (zero beyond), unit area."""
+    return np.maximum(0.0, 1.0 - np.abs(x) / sigma_omega) / sigma_omega
+
+
+DELTAS = {'gauss': gaussian_delta, 'lorentz': lorentzian_delta, 'triangle': triangular_delta}
 
 
 def rate_prefactor():
@@ -129,10 +152,13 @@ def _set_average(ph, k, g):
     return out
 
 
-def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, average=True):
+def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, average=True, delta='gauss'):
     """gamma_mu [rad/ps] for every mode mu = (k, s), k in k_subset, each T.
 
+    ``delta`` picks the finite-width energy delta of the appendix (Gaussian,
+    Lorentzian or triangular; width 2 pi sigma_thz in angular frequency).
     Returns an array (nT, len(k_subset), n)."""
+    delta_fn = DELTAS[delta]
     T = np.atleast_1d(np.asarray(T, dtype=float))
     ks = np.arange(ph.n_k) if k_subset is None else np.asarray(k_subset)
     n = crystal.n_modes
@@ -157,7 +183,7 @@ def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, averag
                   & ph.mask[kpps][:, None, None, :])
             with np.errstate(divide='ignore', invalid='ignore'):
                 inv = np.where(m3, 1.0 / (w1 * w2 * w3), 0.0)
-            delta = gaussian_delta(w1 + sign * w2 - w3, sig)
+            delta = delta_fn(w1 + sign * w2 - w3, sig)
             for it, t in enumerate(T):
                 n2 = np.where(ph.mask[kps][:, None, :, None], occupation(w2, t, stats), 0.0)
                 n3 = np.where(ph.mask[kpps][:, None, None, :], occupation(w3, t, stats), 0.0)
@@ -175,7 +201,45 @@ def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, averag
     return out
 
 
-def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset=None):
+def phase_space(ph, T, sigma_thz, stats='quantum', k_subset=None, delta='gauss'):
+    """Normalised three-phonon phase space per mode g_mu [ps/rad] (Sec. II.B,
+    eq. phase_space and the per-mode sum that follows it), every T.
+
+    g_mu = (1/N_k) [ sum_{k's's''} (n' - n'') delta(w + w' - w'')
+                     + 1/2 sum_{k's's''} (1 + n' + n'') delta(w - w' - w'') ]
+    with k'' = k + k' (plus) and k'' = k - k' (minus).  Depends on frequencies
+    only, so degenerate modes agree without averaging.  Returns (nT, len(k_subset), n)."""
+    delta_fn = DELTAS[delta]
+    T = np.atleast_1d(np.asarray(T, dtype=float))
+    ks = np.arange(ph.n_k) if k_subset is None else np.asarray(k_subset)
+    n = ph.omega.shape[1]
+    sig = units.TWO_PI * sigma_thz
+    out = np.zeros((len(T), len(ks), n))
+    for ik, k in enumerate(ks):
+        w = ph.omega[k]
+        mk = ph.mask[k]
+        acc = np.zeros((len(T), n))
+        for sign in (+1, -1):
+            kpps = partner_index(ph, k, sign)
+            w1 = w[None, :, None, None]
+            w2 = ph.omega[:, None, :, None]
+            w3 = ph.omega[kpps][:, None, None, :]
+            m3 = mk[None, :, None, None] & ph.mask[:, None, :, None] & ph.mask[kpps][:, None, None, :]
+            d = np.where(m3, delta_fn(w1 + sign * w2 - w3, sig), 0.0)
+            for it, t in enumerate(T):
+                n2 = np.where(ph.mask[:, None, :, None], occupation(w2, t, stats), 0.0)
+                n3 = np.where(ph.mask[kpps][:, None, None, :], occupation(w3, t, stats), 0.0)
+                if sign > 0:
+                    acc[it] += np.sum((n2 - n3) * d, axis=(0, 2, 3))
+                else:
+                    acc[it] += 0.5 * np.sum((1.0 + n2 + n3) * d, axis=(0, 2, 3))
+        acc /= ph.n_k
+        acc[:, ~mk] = 0.0
+        out[:, ik] = acc
+    return out
+
+
+def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset=None, delta='gauss'):
     """Gamma-point-only linewidths for large cells, per first mode s.
 
     Same definitions as ``linewidths`` with N_k = 1 (all phases are 1); the
@@ -184,6 +248,7 @@ def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset
     (returns raw per-mode values; disordered cells have no degeneracies above
     the acoustic modes)."""
     assert ph.n_k == 1
+    delta_kind = delta
     T = np.atleast_1d(np.asarray(T, dtype=float))
     n = crystal.n_modes
     E = ph.eigvec[0]
@@ -218,7 +283,7 @@ def linewidths_gamma_sparse(crystal, ph, T, sigma_thz, stats='quantum', s_subset
             Ep = E if sign > 0 else E.conj()
             V = Ep.T @ F @ E.conj()                       # V[s', s'']
             V2 = np.abs(V) ** 2
-            delta = gaussian_delta(w[s] + sign * w2 - w3, sig)
+            delta = DELTAS[delta_kind](w[s] + sign * w2 - w3, sig)
             for it, t in enumerate(T):
                 n2 = np.where(mask, occupation(w, t, stats), 0.0)[:, None]
                 n3 = np.where(mask, occupation(w, t, stats), 0.0)[None, :]

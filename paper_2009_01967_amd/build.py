@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkaldo.so")
 
-SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip"]
+SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip", "phase.hip"]
 
 ARCH = "gfx950"
 COMMON = [

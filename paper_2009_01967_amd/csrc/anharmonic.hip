@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "mfma.h"
 
 namespace kaldo {
 
@@ -30,7 +31,8 @@ struct ProjArgs {
   int k0;
   int ppt;       // p points per thread
   int k_local;   // XCD-aware order: the p tiles of one k on one XCD
-  double rc;     // 1 / (sqrt(2) sigma_omega): frequencies are scaled by it
+  double rc;     // 1 / (scale of the delta): frequencies are scaled by it
+  int kind;      // kaldo_delta (selects the kernel instance)
 };
 
 // ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
@@ -147,20 +149,6 @@ __global__ void k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict
 }
 
 // ---- fused step B + step C + epilogue ----------------------------------------------
-// exp(-x^2) with x the frequency mismatch in units of sqrt(2) sigma
-template <typename R>
-__device__ __forceinline__ R gauss(double x);
-
-template <>
-__device__ __forceinline__ double gauss<double>(double x) {
-  return exp(-x * x);
-}
-
-template <>
-__device__ __forceinline__ float gauss<float>(double x) {
-  return __expf((float)(-x * x));
-}
-
 // Opaque zero: keeps loads inside a loop (bounds register pressure).
 __device__ __forceinline__ int opaque_zero() {
   int z;
@@ -171,7 +159,7 @@ __device__ __forceinline__ int opaque_zero() {
 // LDS_A: the block's A_k (all s and Delta) is staged in LDS once and read as
 // wave-wide broadcasts; otherwise it is read from global memory through the
 // scalar cache (cells whose A_k does not fit).
-template <typename R, int NM, int NT, bool LDS_A>
+template <typename R, int NM, int NT, bool LDS_A, int DK>
 __global__ void __launch_bounds__(256)
     k_project_small(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ PH, const cplx<R>* __restrict__ ET,
                     const double* __restrict__ OM, const double* __restrict__ IW, const double* __restrict__ OCC,
@@ -223,7 +211,7 @@ __global__ void __launch_bounds__(256)
       for (int s1 = 0; s1 < NM; ++s1) {
 #pragma unroll
         for (int a = 0; a < NM; ++a) Ep[a][s1] = ET[((size_t)s1 * NM + a) * nk + p];
-        wp[s1] = OM[(size_t)s1 * nk + p] * P.rc;  // frequencies in units of sqrt(2) sigma
+        wp[s1] = OM[(size_t)s1 * nk + p] * P.rc;  // frequencies in units of the delta's scale
         iwp[s1] = (R)IW[(size_t)s1 * nk + p];
 #pragma unroll
         for (int t = 0; t < NT; ++t) np_[t][s1] = t < P.nT ? (R)OCC[((size_t)t * NM + s1) * nk + p] : (R)0;
@@ -267,7 +255,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int b = 0; b < NM; ++b) cfma_conj(Tc[a], F[a][b], ET[col + (size_t)b * nk]);
           }
-          const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / (sqrt(2) sigma)
+          const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / scale
           const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
           R n2[NT];
 #pragma unroll
@@ -278,8 +266,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int a = 0; a < NM; ++a) cfma(V, Ep[a][s1], Tc[a]);
             const R v2 = (V.re * V.re + V.im * V.im) * (iwp[s1] * iw2);
-            const R gp = (R)gauss<R>(d2 + wp[s1]) * v2;
-            const R gm = (R)0.5 * (R)gauss<R>(d2 - wp[s1]) * v2;
+            const R gp = delta_shape<R, DK>(d2 + wp[s1]) * v2;
+            const R gm = (R)0.5 * delta_shape<R, DK>(d2 - wp[s1]) * v2;
             // gp (n' - n'') + gm (1 + n' + n'') = gm + n' (gp + gm) + n'' (gm - gp)
             const R sp = gp + gm, sm = gm - gp;
 #pragma unroll
@@ -332,16 +320,16 @@ __global__ void k_finalize(double* __restrict__ gamma, const double* __restrict_
   }
 }
 
-template <typename R, int NM, bool LDS_A>
+template <typename R, int NM, bool LDS_A, int DK>
 static void launch_project_t(dim3 grid, size_t lds, hipStream_t st, const cplx<R>* A, const cplx<R>* PH,
                              const cplx<R>* ET, const double* OM, const double* IW, const double* OCC,
                              const ProjArgs& P, double* partial) {
 #define KALDO_LAUNCH(NTV)                                                                                    \
   {                                                                                                           \
     if (lds > 64 * 1024)                                                                                      \
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_small<R, NM, NTV, LDS_A>),          \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_project_small<R, NM, NTV, LDS_A, DK>),          \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
-    hipLaunchKernelGGL((k_project_small<R, NM, NTV, LDS_A>), grid, dim3(256), lds, st, A, PH, ET, OM, IW, OCC, \
+    hipLaunchKernelGGL((k_project_small<R, NM, NTV, LDS_A, DK>), grid, dim3(256), lds, st, A, PH, ET, OM, IW, OCC, \
                        P, partial);                                                                           \
   }
   if (P.nT <= 1) KALDO_LAUNCH(1)
@@ -359,10 +347,18 @@ static void launch_project(dim3 grid, hipStream_t st, const cplx<R>* A, const cp
                            const double* OM, const double* IW, const double* OCC, const ProjArgs& P,
                            double* partial) {
   const size_t lds = (size_t)NM * P.nd * NM * NM * sizeof(cplx<R>);
-  if (lds <= (sizeof(R) == 4 ? 76 : 150) * 1024)
-    launch_project_t<R, NM, true>(grid, lds, st, A, PH, ET, OM, IW, OCC, P, partial);
-  else
-    launch_project_t<R, NM, false>(grid, 0, st, A, PH, ET, OM, IW, OCC, P, partial);
+  const bool in_lds = lds <= (sizeof(R) == 4 ? 76 : 150) * 1024;
+#define KALDO_KIND(DKV)                                                                  \
+  {                                                                                      \
+    if (in_lds)                                                                          \
+      launch_project_t<R, NM, true, DKV>(grid, lds, st, A, PH, ET, OM, IW, OCC, P, partial); \
+    else                                                                                 \
+      launch_project_t<R, NM, false, DKV>(grid, 0, st, A, PH, ET, OM, IW, OCC, P, partial);  \
+  }
+  if (P.kind == KALDO_DELTA_GAUSS) KALDO_KIND(KALDO_DELTA_GAUSS)
+  else if (P.kind == KALDO_DELTA_LORENTZ) KALDO_KIND(KALDO_DELTA_LORENTZ)
+  else KALDO_KIND(KALDO_DELTA_TRIANGLE)
+#undef KALDO_KIND
 }
 
 template <typename R>
@@ -416,8 +412,11 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   // p-side tables read by every block: eigenvectors, phases, mode tables
   const size_t p_side = et_bytes + ph_bytes + tab_bytes;
   P.k_local = p_side <= ((size_t)7 << 19) ? 1 : 0;  // 3.5 MB of a 4 MB L2
-  P.rc = 1.0 / (sqrt(2.0) * sig);
-  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
+  double dscale, dnorm;
+  delta_scale(ctx->delta, sig, dscale, dnorm);
+  P.rc = 1.0 / dscale;
+  P.kind = ctx->delta;
+  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
   for (int k0 = 0; k0 < nk && !planning(ctx); k0 += kchunk) {

@@ -455,7 +455,8 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
 static kaldo_status check_linewidth_args(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz,
                                          kaldo_delta delta, kaldo_stats stats, kaldo_precision precision) {
   if (!T || nT < 1 || nT > KALDO_MAX_T) return fail(ctx, KALDO_EINVAL, "need 1 <= nT <= KALDO_MAX_T temperatures");
-  if (delta != KALDO_DELTA_GAUSS) return fail(ctx, KALDO_EINVAL, "only the Gaussian delta is available");
+  if (delta != KALDO_DELTA_GAUSS && delta != KALDO_DELTA_LORENTZ && delta != KALDO_DELTA_TRIANGLE)
+    return fail(ctx, KALDO_EINVAL, "unknown delta kind");
   if (stats != KALDO_QUANTUM && stats != KALDO_CLASSICAL) return fail(ctx, KALDO_EINVAL, "bad statistics");
   if (precision != KALDO_FP64 && precision != KALDO_FP32 && precision != KALDO_BF16X3)
     return fail(ctx, KALDO_EINVAL, "bad precision");
@@ -484,6 +485,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
   ctx->nT = nT;
   for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
   ctx->stats = stats;
+  ctx->delta = delta;
   ctx->have_gamma = false;
   if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
   ctx->have_gamma = true;
@@ -492,6 +494,20 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
     if ((st = copy_out(ctx, gamma_out, ctx->d_gamma.p, bytes)) != KALDO_OK) return st;
   }
   return KALDO_OK;
+}
+
+kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_delta delta,
+                               kaldo_stats stats, double* g_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_phase_space before kaldo_phonons");
+  kaldo_status st;
+  if ((st = check_linewidth_args(ctx, T, nT, sigma_thz, delta, stats, KALDO_FP64)) != KALDO_OK) return st;
+  if (!g_out) return fail(ctx, KALDO_EINVAL, "g_out is required");
+  double* g = nullptr;
+  if ((st = run_phase_space(ctx, T, nT, sigma_thz, delta, stats, &g)) != KALDO_OK) return st;
+  return copy_out(ctx, g_out, g, (size_t)nT * ctx->nk * ctx->nm * sizeof(double));
 }
 
 kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
@@ -602,6 +618,7 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
     sub->nT = nT;
     for (int t = 0; t < nT; ++t) sub->T[t] = T[t];
     sub->stats = stats;
+    sub->delta = KALDO_DELTA_GAUSS;
     sub->have_gamma = false;
   }
   if (!ctx->batch_exec || key != ctx->batch_key) {

@@ -196,20 +196,22 @@ struct EpiStoreY {
 // GEMM 2 epilogue: linewidth weights of V[s'][s''] for first mode (k, s), per
 // column (s, s'') summed over the rows s':
 //   |V|^2 / (w' w'') * [ g+ (n' - n'') + 1/2 g- (1 + n' + n'') ]
-template <int NT>
+// with g+- the shape of the delta of kind DK.
+template <int NT, int DK>
 struct EpiCrystal {
   const double *OM, *IW, *OCC;  // [s][k], [s][k], [t][s][k]
   const int* kmap;              // index of k + p for p = p0 + z
   double* partial;              // [z][m_tiles][ncol][nT]
   long long ncol;               // n * n
   int n, nk, nT, k, p0, m_tiles;
-  double c;                     // 1 / (2 sigma^2)
+  double rs;                    // 1 / (scale of the delta)
+  static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
 
   template <int P, int FM, int FN>
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
                                         char* lds) const {
     using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
-    constexpr double cut = gauss_cut<P>();
+    constexpr double cut = delta_cut<P>(DK);
     const int p = p0 + at.z;
     const int kk = kmap[at.z];
     // column data: w - w'' (first mode minus k+p mode), 1/w'', n''
@@ -221,7 +223,7 @@ struct EpiCrystal {
       const bool cv = col < ncol;
       const int s = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)s * n) : 0;
-      dcol[q] = OM[(size_t)s * nk + k] - OM[(size_t)s2 * nk + kk];
+      dcol[q] = (OM[(size_t)s * nk + k] - OM[(size_t)s2 * nk + kk]) * rs;
       iw2[q] = cv ? (R)IW[(size_t)s2 * nk + kk] : (R)0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -238,34 +240,27 @@ struct EpiCrystal {
       for (int h = 0; h < 2; ++h) {
         const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
         const int ic = i < n ? i : n - 1;
-        w1[h] = OM[(size_t)ic * nk + p];
+        w1[h] = OM[(size_t)ic * nk + p] * rs;
         iw1[h] = i < n ? (R)IW[(size_t)ic * nk + p] : (R)0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)OCC[((size_t)t * n + ic) * nk + p] : (R)0;
       }
 #pragma unroll
       for (int q = 0; q < FN; ++q) {
-        // a 16 x 16 sub-tile with every element outside the Gaussian cutoff adds nothing
+        // a 16 x 16 sub-tile with every element outside the delta's cutoff adds nothing
         bool need = false;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
-          need = need || fmin(xp * xp, xm * xm) * c < cut;
+          need = need || fmin(xp * xp, xm * xm) < cut;
         }
         if (__ballot(need) == 0) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const R vr = (R)acc[a][q][2 * h], vi = (R)acc[a][q][2 * h + 1];
           const R v2 = (vr * vr + vi * vi) * iw1[h] * iw2[q];
-          const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
-          R gp, gm;
-          if constexpr (P == KALDO_FP64) {
-            gp = exp(-xp * xp * c);
-            gm = exp(-xm * xm * c);
-          } else {
-            gp = __expf((float)(-xp * xp * c));
-            gm = __expf((float)(-xm * xm * c));
-          }
+          const R gp = delta_shape<R, DK>(dcol[q] + w1[h]);
+          const R gm = delta_shape<R, DK>(dcol[q] - w1[h]);
           const R hh = (R)0.5 * gm, a1 = gp + hh, a2 = hh - gp;
 #pragma unroll
           for (int t = 0; t < NT; ++t) o[q][t] += v2 * (hh + n1[h][t] * a1 + n2[q][t] * a2);
@@ -345,7 +340,7 @@ kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double*
 template <int P, class Epi>
 static int cr_gemm(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
-  const int v = autotune(ctx, key, gemm_variants<P>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
+  const int v = autotune(ctx, key, gemm_variants<P, Epi>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
   if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
   return v;
 }
@@ -409,8 +404,9 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
                      ctx->grid[1], ctx->grid[2]);
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
-  const double cexp = 1.0 / (2.0 * sig * sig);
-  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk / (sqrt(kTwoPi) * sig);
+  double dscale, dnorm;
+  delta_scale(ctx->delta, sig, dscale, dnorm);
+  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
   // planning visits one first-mode point and the batches whose GEMM shapes differ
   const bool plan = planning(ctx);
@@ -459,12 +455,13 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       g2.b_lo = Yl;
       g2.a_map = nullptr;
       int v = 0;
-      const std::string key2 = "cr2/" + shape + std::to_string(cnt) + "/" + std::to_string(nT);
-#define KALDO_EPI(NTV)                                                                                          \
+      const std::string key2 = "cr2/" + shape + std::to_string(cnt) + "/" + std::to_string(nT) + "/" +
+                               std::to_string(ctx->delta);
+#define KALDO_EPI(NTV, DKV)                                                                                          \
   {                                                                                                             \
-    EpiCrystal<NTV> e2{OM, IW, OCC, kmap + (size_t)k * nk + p0, partial, nn, n, nk, nT, k, p0, 0, cexp};       \
+    EpiCrystal<NTV, DKV> e2{OM, IW, OCC, kmap + (size_t)k * nk + p0, partial, nn, n, nk, nT, k, p0, 0, 1.0 / dscale}; \
     /* the partial layout depends on the row tiling of the variant that runs */                               \
-    const int vt = autotune(ctx, key2, gemm_variants<P>(), 0, [&](int w) {                                           \
+    const int vt = autotune(ctx, key2, gemm_variants<P, decltype(e2)>(), 0, [&](int w) {                                           \
       e2.m_tiles = gemm_m_tiles<P>(w, mrows);                                                                   \
       gemm_launch<P>(w, g2, e2, st);                                                                            \
     });                                                                                                         \
@@ -472,9 +469,16 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
     if (!plan) gemm_launch<P>(vt, g2, e2, st);                                                                  \
     v = vt;                                                                                                     \
   }
-      if (nT <= 1) KALDO_EPI(1)
-      else if (nT <= 4) KALDO_EPI(4)
-      else KALDO_EPI(8)
+#define KALDO_EPI_NT(DKV)               \
+  {                                     \
+    if (nT <= 1) KALDO_EPI(1, DKV)      \
+    else if (nT <= 4) KALDO_EPI(4, DKV) \
+    else KALDO_EPI(8, DKV)              \
+  }
+      if (ctx->delta == KALDO_DELTA_GAUSS) KALDO_EPI_NT(KALDO_DELTA_GAUSS)
+      else if (ctx->delta == KALDO_DELTA_LORENTZ) KALDO_EPI_NT(KALDO_DELTA_LORENTZ)
+      else KALDO_EPI_NT(KALDO_DELTA_TRIANGLE)
+#undef KALDO_EPI_NT
 #undef KALDO_EPI
       KALDO_HIP(ctx, hipGetLastError());
       prof_end(ctx, "project");

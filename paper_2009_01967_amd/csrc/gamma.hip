@@ -168,22 +168,24 @@ __global__ void k_gamma_a(typename Operand<P>::T* __restrict__ Ahi, typename Ope
 // Output row i = s' and column c = sl * n + s''.  For every element, both
 // processes at every temperature:
 //   |V|^2 / (w' w'') * [ g+ (n' - n'') + 1/2 g- (1 + n' + n'') ]
-// with g+- = exp(-(w +- w' - w'')^2 / 2 sigma^2); the 1/w of the first mode,
-// the Gaussian normalisation and the prefactor are applied when collecting.
-template <int NT>
+// with g+- the delta shape at (w +- w' - w''); the 1/w of the first mode, the
+// delta normalisation and the prefactor are applied when collecting.  DK is
+// the delta kind.
+template <int NT, int DK>
 struct EpiGamma {
   const double *OM, *IW, *OCC;
   double* partial;     // [m_tiles][ncol][nT]
   long long ncol;      // cnt * n
   int n, nT, s0;
-  double c;            // 1 / (2 sigma^2)
+  double rs;           // 1 / (scale of the delta)
+  static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
 
   template <int P, int FM, int FN>
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
                                         char* lds) const {
     using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
-    constexpr double cut = gauss_cut<P>();
-    // column data: w - w'' (first mode minus s''), 1/w'', n''
+    constexpr double cut = delta_cut<P>(DK);
+    // column data: (w - w'') / scale (first mode minus s''), 1/w'', n''
     double dcol[FN];
     R iw2[FN], n2[FN][NT], o[FN][NT];
 #pragma unroll
@@ -192,7 +194,7 @@ struct EpiGamma {
       const bool cv = col < ncol;
       const int sl = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)sl * n) : 0;
-      dcol[q] = OM[s0 + sl] - OM[s2];
+      dcol[q] = (OM[s0 + sl] - OM[s2]) * rs;
       iw2[q] = cv ? (R)IW[s2] : (R)0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -209,34 +211,27 @@ struct EpiGamma {
       for (int r = 0; r < 4; ++r) {
         const int i = at.m0 + 16 * a + acc_row<P>(at.lane, r);
         const int ic = i < n ? i : n - 1;
-        w1[r] = OM[ic];
+        w1[r] = OM[ic] * rs;
         iw1[r] = i < n ? (R)IW[ic] : (R)0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) n1[r][t] = t < nT ? (R)OCC[(size_t)t * n + ic] : (R)0;
       }
 #pragma unroll
       for (int q = 0; q < FN; ++q) {
-        // a 16 x 16 sub-tile with every element outside the Gaussian cutoff adds nothing
+        // a 16 x 16 sub-tile with every element outside the delta's cutoff adds nothing
         bool need = false;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const double xp = dcol[q] + w1[r], xm = dcol[q] - w1[r];
-          need = need || fmin(xp * xp, xm * xm) * c < cut;
+          need = need || fmin(xp * xp, xm * xm) < cut;
         }
         if (__ballot(need) == 0) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const R v = (R)acc[a][q][r];
           const R v2 = v * v * iw1[r] * iw2[q];
-          const double xp = dcol[q] + w1[r], xm = dcol[q] - w1[r];
-          R gp, gm;
-          if constexpr (P == KALDO_FP64) {
-            gp = exp(-xp * xp * c);
-            gm = exp(-xm * xm * c);
-          } else {
-            gp = __expf((float)(-xp * xp * c));
-            gm = __expf((float)(-xm * xm * c));
-          }
+          const R gp = delta_shape<R, DK>(dcol[q] + w1[r]);
+          const R gm = delta_shape<R, DK>(dcol[q] - w1[r]);
           const R h = (R)0.5 * gm, a1 = gp + h, a2 = h - gp;
 #pragma unroll
           for (int t = 0; t < NT; ++t) o[q][t] += v2 * (h + n1[r][t] * a1 + n2[q][t] * a2);
@@ -307,10 +302,10 @@ __global__ void k_tables_gamma(double* __restrict__ OM, double* __restrict__ IW,
   }
 }
 
-template <int P, int NT>
-static int gemm_lw(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const EpiGamma<NT>& e) {
+template <int P, class Epi>
+static int gemm_lw(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
-  const int v = autotune(ctx, key, gemm_variants<P>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
+  const int v = autotune(ctx, key, gemm_variants<P, Epi>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
   if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
   return v;
 }
@@ -371,7 +366,9 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   hipLaunchKernelGGL((k_transpose<RY>), dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et, E, n);
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
-  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / (sqrt(kTwoPi) * sig);
+  double dscale, dnorm;
+  delta_scale(ctx->delta, sig, dscale, dnorm);
+  const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit * dnorm;
   // atoms per block jc, staged in sub-runs of js atoms (multiples of JB) whose
   // X_s blocks must fit in 64 KB of LDS.  Short runs (one sub-run per block)
   // measured fastest: runs of 32 atoms halved the speed (fewer blocks in flight).
@@ -419,17 +416,24 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     g.m_valid = n;
     g.c_valid = (long long)cnt * n;
     const std::string key = "gamma/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt) +
-                            "/" + std::to_string(nT);
+                            "/" + std::to_string(nT) + "/" + std::to_string(ctx->delta);
     int v = 0;
     prof_begin(ctx);
-#define KALDO_EPI(NTV)                                                                                      \
-  {                                                                                                         \
-    EpiGamma<NTV> e{OM, IW, OCC, partial, (long long)cnt * n, n, nT, s0, 1.0 / (2.0 * sig * sig)};          \
-    v = gemm_lw<P, NTV>(ctx, key, g, e);                                                                    \
+#define KALDO_EPI(NTV, DKV)                                                                   \
+  {                                                                                           \
+    EpiGamma<NTV, DKV> e{OM, IW, OCC, partial, (long long)cnt * n, n, nT, s0, 1.0 / dscale}; \
+    v = gemm_lw<P>(ctx, key, g, e);                                                           \
   }
-    if (nT <= 1) KALDO_EPI(1)
-    else if (nT <= 4) KALDO_EPI(4)
-    else KALDO_EPI(8)
+#define KALDO_EPI_NT(DKV)              \
+  {                                    \
+    if (nT <= 1) KALDO_EPI(1, DKV)     \
+    else if (nT <= 4) KALDO_EPI(4, DKV) \
+    else KALDO_EPI(8, DKV)             \
+  }
+    if (ctx->delta == KALDO_DELTA_GAUSS) KALDO_EPI_NT(KALDO_DELTA_GAUSS)
+    else if (ctx->delta == KALDO_DELTA_LORENTZ) KALDO_EPI_NT(KALDO_DELTA_LORENTZ)
+    else KALDO_EPI_NT(KALDO_DELTA_TRIANGLE)
+#undef KALDO_EPI_NT
 #undef KALDO_EPI
     KALDO_HIP(ctx, hipGetLastError());
     prof_end(ctx, "project");

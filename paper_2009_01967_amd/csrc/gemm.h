@@ -356,6 +356,18 @@ inline int gemm_variants() {
   return P == KALDO_BF16X3 ? 7 : 4;
 }
 
+// An epilogue with kAllShapes = false is instantiated with the first tile shape
+// only (variant 0): fewer kernel instances for its less used cases.
+template <class Epi, class = void>
+struct AllShapes : std::true_type {};
+template <class Epi>
+struct AllShapes<Epi, std::void_t<decltype(Epi::kAllShapes)>> : std::integral_constant<bool, Epi::kAllShapes> {};
+
+template <int P, class Epi>
+inline int gemm_variants() {
+  return AllShapes<Epi>::value ? gemm_variants<P>() : 1;
+}
+
 template <int P>
 inline int gemm_fm(int v) {
   if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
@@ -378,7 +390,11 @@ inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
 
 template <int P, class Epi>
 inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
-  if constexpr (P == KALDO_FP64) {
+  if constexpr (!AllShapes<Epi>::value) {
+    (void)v;
+    if constexpr (P == KALDO_FP64) gemm_launch_tile<P, 2, 4>(g, e, st);
+    else gemm_launch_tile<P, 4, 4>(g, e, st);
+  } else if constexpr (P == KALDO_FP64) {
     if (v == 0) gemm_launch_tile<P, 2, 4>(g, e, st);
     else if (v == 1) gemm_launch_tile<P, 4, 2>(g, e, st);
     else if (v == 2) gemm_launch_tile<P, 2, 2>(g, e, st);

@@ -163,8 +163,10 @@ struct kaldo_ctx_s {
   int nT = 0;
   double T[KALDO_MAX_T] = {0};
   int stats = 0;
+  int delta = KALDO_DELTA_GAUSS;
   kaldo::DevBuf d_gamma;             // double [nT][Nk][n]
   kaldo::DevBuf d_tabs;              // per-call mode tables
+  kaldo::DevBuf d_phase;             // phase space: mode tables and g [nT][Nk][n]
   kaldo::DevBuf d_A;                 // step-A intermediate
   kaldo::DevBuf d_partial;           // partial sums
   kaldo::DevBuf d_kappa;             // double [nT][9]
@@ -201,6 +203,8 @@ kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity);
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision);
 kaldo_status run_linewidths_gamma(kaldo_ctx ctx, double sigma_thz, int precision);
 kaldo_status run_linewidths_crystal(kaldo_ctx ctx, double sigma_thz, int precision);
+kaldo_status run_phase_space(kaldo_ctx ctx, const double* T, int nT, double sigma_thz, int delta, int stats,
+                             double** g_dev);
 kaldo_status run_kappa_rta(kaldo_ctx ctx);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <type_traits>
 
 #include "../../include/kaldo.h"
@@ -79,6 +80,54 @@ __device__ __forceinline__ void store_operand2(typename Operand<P>::T* hi, typen
 template <int P>
 __host__ __device__ constexpr double gauss_cut() {
   return P == KALDO_FP64 ? 40.0 : 18.0;
+}
+
+// Squared scaled mismatch u^2 beyond which a delta of kind `kind` is dropped:
+// the Gaussian cut above, exactly 1 for the triangle (zero outside its base),
+// never for the Lorentzian (its tails are kept).
+template <int P>
+__host__ __device__ constexpr double delta_cut(int kind) {
+  return kind == KALDO_DELTA_GAUSS ? gauss_cut<P>() : (kind == KALDO_DELTA_TRIANGLE ? 1.0 : 1e300);
+}
+
+// Shape of the energy delta of kind DK as a function of the mismatch u in
+// units of the kind's scale s (Gaussian: s = sqrt(2) sigma, exp(-u^2);
+// Lorentzian: s = sigma the half width, 1 / (1 + u^2); triangle: s = sigma the
+// half base, max(0, 1 - |u|)).  The normalisation (1 / (sqrt(pi) s),
+// 1 / (pi s), 1 / s) is applied when the sums are collected.  u is formed in
+// FP64 (a difference of near-equal scaled frequencies); the shape is evaluated
+// in R.
+template <typename R, int DK>
+__device__ __forceinline__ R delta_shape(double u) {
+  if constexpr (DK == KALDO_DELTA_GAUSS) {
+    if constexpr (sizeof(R) == 8) return exp(-u * u);
+    else return __expf((float)(-u * u));
+  } else if constexpr (DK == KALDO_DELTA_LORENTZ) {
+    if constexpr (sizeof(R) == 8) return 1.0 / (1.0 + u * u);
+    else {
+      const float x = (float)u;
+      return __builtin_amdgcn_rcpf(fmaf(x, x, 1.0f));
+    }
+  } else {
+    const R t = (R)1 - fabs((R)u);
+    return t > (R)0 ? t : (R)0;
+  }
+}
+
+// Host: the scale s (rad/ps) and the normalisation of the delta of kind `kind`
+// for the width sigma_omega (rad/ps).
+inline void delta_scale(int kind, double sigma_omega, double& scale, double& norm) {
+  const double pi = 3.141592653589793238462643383279;
+  if (kind == KALDO_DELTA_GAUSS) {
+    scale = sqrt(2.0) * sigma_omega;
+    norm = 1.0 / (sqrt(pi) * scale);
+  } else if (kind == KALDO_DELTA_LORENTZ) {
+    scale = sigma_omega;
+    norm = 1.0 / (pi * scale);
+  } else {
+    scale = sigma_omega;
+    norm = 1.0 / scale;
+  }
 }
 
 // accumulator row of register r in lane l for a 16x16 tile

@@ -30,6 +30,9 @@ KALDO_BF16X3 = 2
 PRECISIONS = {"fp64": KALDO_FP64, "fp32": KALDO_FP32, "bf16x3": KALDO_BF16X3}
 
 KALDO_DELTA_GAUSS = 0
+KALDO_DELTA_LORENTZ = 1
+KALDO_DELTA_TRIANGLE = 2
+DELTAS = {"gauss": KALDO_DELTA_GAUSS, "lorentz": KALDO_DELTA_LORENTZ, "triangle": KALDO_DELTA_TRIANGLE}
 KALDO_QUANTUM = 0
 KALDO_CLASSICAL = 1
 KALDO_MAX_T = 8
@@ -42,7 +45,7 @@ STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALD
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
-            "kaldo_profile_read"]
+            "kaldo_profile_read", "kaldo_phase_space"]
 
 
 class kaldo_structure(C.Structure):
@@ -90,6 +93,9 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_linewidths.argtypes = [C.c_void_p, C.POINTER(kaldo_fc3), C.POINTER(C.c_double), C.c_int32,
                                      C.c_double, C.c_int, C.c_int, C.c_int, C.c_void_p]
     lib.kaldo_linewidths.restype = C.c_int
+    lib.kaldo_phase_space.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int,
+                                      C.c_int, C.c_void_p]
+    lib.kaldo_phase_space.restype = C.c_int
     lib.kaldo_kappa_rta.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
@@ -213,6 +219,13 @@ def kaldo_linewidths(ctx, fc3, T: Sequence[float], sigma_thz: float, stats: int 
                                            _out_ptr(gamma_out))
 
 
+def kaldo_phase_space(ctx, T: Sequence[float], sigma_thz: float, delta: int = KALDO_DELTA_GAUSS,
+                      stats: int = KALDO_QUANTUM, g_out=None) -> int:
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    return load_library().kaldo_phase_space(ctx, Ts, len(T), float(sigma_thz), int(delta), int(stats),
+                                            _out_ptr(g_out))
+
+
 def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_rta(ctx, _out_ptr(kappa_out))
 
@@ -310,7 +323,7 @@ class Context:
         return nu_out
 
     def linewidths(self, crystal=None, T=(300.0,), sigma_thz=0.1, precision="fp64", classical=False,
-                   gamma_out=None, want_host=True):
+                   gamma_out=None, want_host=True, delta="gauss"):
         keep = _Keep()
         f3 = None
         if crystal is not None:
@@ -321,7 +334,8 @@ class Context:
             gamma_out = np.zeros((len(T), self.nk, self.n))
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _check(self.h, kaldo_linewidths(self.h, f3, T, sigma_thz,
-                                        KALDO_CLASSICAL if classical else KALDO_QUANTUM, prec, gamma_out))
+                                        KALDO_CLASSICAL if classical else KALDO_QUANTUM, prec, gamma_out,
+                                        delta=DELTAS[delta] if isinstance(delta, str) else int(delta)))
         return gamma_out
 
     def batch_add(self, crystal) -> int:
@@ -351,6 +365,15 @@ class Context:
     def batch_clear(self):
         _check(self.h, kaldo_batch_clear(self.h))
         self.batch_shapes = []
+
+    def phase_space(self, T=(300.0,), sigma_thz=0.1, classical=False, delta="gauss", out=None):
+        """Phase space per mode g [nT][Nk][n] in ps/rad on the last phonons' grid."""
+        if out is None:
+            out = np.zeros((len(T), self.nk, self.n))
+        _check(self.h, kaldo_phase_space(self.h, T, sigma_thz,
+                                         DELTAS[delta] if isinstance(delta, str) else int(delta),
+                                         KALDO_CLASSICAL if classical else KALDO_QUANTUM, out))
+        return out
 
     def kappa_rta(self, out=None, want_host=True):
         if want_host and out is None:

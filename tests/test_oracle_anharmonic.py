@@ -110,6 +110,62 @@ def test_absorption_rate_matches_fock_space_golden_rule(T_K):
     assert abs(gamma0[0]) < 1e-12 * abs(gamma[0])
 
 
+@pytest.mark.parametrize("kind", ["gauss", "lorentz", "triangle"])
+def test_delta_shapes_have_unit_area_and_their_stated_width(kind):
+    from scipy.integrate import quad
+    s = 0.7
+    f = A.DELTAS[kind]
+    if kind == "triangle":
+        area = quad(lambda x: f(x, s), -s, s, points=[0.0])[0]
+    else:
+        area = quad(lambda x: f(x, s), -np.inf, np.inf)[0]
+    assert area == pytest.approx(1.0, abs=1e-9)
+    peak = f(0.0, s)
+    if kind == "gauss":          # standard deviation s: second moment s^2
+        m2 = quad(lambda x: x * x * f(x, s), -np.inf, np.inf)[0]
+        assert m2 == pytest.approx(s * s, rel=1e-9)
+    elif kind == "lorentz":      # half width at half maximum s
+        assert f(s, s) == pytest.approx(0.5 * peak, rel=1e-12)
+        assert f(-s, s) == pytest.approx(0.5 * peak, rel=1e-12)
+    else:                        # half base s, linear flanks
+        assert f(s, s) == 0.0 and f(1.5 * s, s) == 0.0
+        assert f(0.5 * s, s) == pytest.approx(0.5 * peak, rel=1e-12)
+    assert np.all(f(np.linspace(-5 * s, 5 * s, 101), s) >= 0.0)
+
+
+@pytest.mark.parametrize("kind", ["lorentz", "triangle"])
+def test_decay_rate_matches_golden_rule_with_each_delta(kind):
+    # the Fock-space decay of mode 2 with the energy delta of the given kind, at
+    # an exact resonance w2 = w0 + w1 and a width far below every other energy
+    # mismatch, so that the Lorentzian tails of the other processes stay below
+    # 1e-8 of the resonant term
+    sig_thz, T_K = 1e-5, 300.0
+    c, Q, w, T3, m = _molecule([4.05, 5.95, 10.0])
+    ph = P.phonons(c, velocities=False)
+    M0 = _golden_rule_matrix_element(Q, w, T3, m, (0, 0, 1), (1, 1, 0))
+    s = 2 * np.pi * sig_thz
+    wo = ph.omega[0]
+    x = wo[2] - wo[0] - wo[1]
+    d = s / (np.pi * (x * x + s * s)) if kind == "lorentz" else max(0.0, 1 - abs(x) / s) / s
+    n = 1.0 / np.expm1(HBAR * w / (KB * T_K))
+    rate = 2 * np.pi * M0 ** 2 / HBAR ** 2 * d * ((1 + n[0]) * (1 + n[1]) - n[0] * n[1])
+    gamma = A.linewidths(c, ph, [T_K], sig_thz, delta=kind)[0, 0]
+    assert gamma[2] == pytest.approx(0.5 * rate, rel=1e-7)
+
+
+def test_deltas_agree_in_the_narrow_limit():
+    # far from any resonance all three kinds vanish together; on the 2-atom
+    # diamond the linewidth per kind converges as the width shrinks relative to
+    # the spread of the energy mismatches
+    c = diamond_si(grid=(3, 3, 3), rc3=2.6)
+    ph = P.phonons(c, velocities=False)
+    g = {k: A.linewidths(c, ph, [300.0], 0.05, delta=k) for k in ("gauss", "lorentz", "triangle")}
+    for k in ("lorentz", "triangle"):
+        assert np.all(np.isfinite(g[k])) and np.all(g[k] >= -1e-15)
+    # identical support structure: where the Gaussian weight is exactly zero so is the triangle's
+    assert np.all(g["triangle"][g["gauss"] == 0.0] == 0.0)
+
+
 # ----------------------------------------------------------------------------
 # Bloch conventions against real-space supercell sums
 # ----------------------------------------------------------------------------
