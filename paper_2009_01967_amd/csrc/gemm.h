@@ -32,6 +32,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "mfma.h"
 
 namespace kaldo {
@@ -58,6 +60,19 @@ struct GemmChunk {
 };
 
 // Coordinates of one block tile, handed to the epilogue.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+// (array indices are constants from the start, so staging arrays stay in registers)
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 struct TileAt {
   int mt, nt, z;      // tile indices and batch item
   int m0;             // first row of this wavefront's 16 FM rows
@@ -143,22 +158,29 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     bp[S - 1] = static_cast<const T*>(g.b_lo);
   }
 
-  // staging registers of the next chunk: rg[s][u], u < NA for A rows, then NB for B rows
-  uint4 rg[S][NA + NB];
-#define KALDO_GLOAD(K0)                                                                                   \
-  _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
-    _Pragma("unroll") for (int u = 0; u < NA; ++u) rg[s][u] =                                          \
-        *reinterpret_cast<const uint4*>(ap[s] + aoff[u] + (K0));                                         \
-    _Pragma("unroll") for (int u = 0; u < NB; ++u) rg[s][NA + u] =                                     \
-        *reinterpret_cast<const uint4*>(bp[s] + boff[u] + (K0));                                         \
-  }
-#define KALDO_SSTORE(BUFI)                                                                                \
-  _Pragma("unroll") for (int s = 0; s < S; ++s) {                                                       \
-    _Pragma("unroll") for (int u = 0; u < NA + NB; ++u) {                                              \
-      const int row = (u < NA ? 0 : BM - RPP * NA) + row0 + RPP * u;                                    \
-      *reinterpret_cast<uint4*>(lds + (BUFI) * BUF + lds_off<CB>(s * ROWS + row, slot)) = rg[s][u];     \
-    }                                                                                                   \
-  }
+  // staging registers of the next chunk (declared per use, below; native
+  // vectors, so that the copies stay register moves): rg[s][u],
+  // u < NA for A rows, then NB for B rows
+#define KALDO_GLOAD(K0)                                                                \
+  static_for<S>([&](auto sc) __attribute__((always_inline)) {                                                         \
+    constexpr int s_ = decltype(sc)::value;                                            \
+    static_for<NA + NB>([&](auto uc) __attribute__((always_inline)) {                                                 \
+      constexpr int u_ = decltype(uc)::value;                                          \
+      if constexpr (u_ < NA)                                                           \
+        rg[s_][u_] = *reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + (K0));        \
+      else                                                                             \
+        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + (K0));   \
+    });                                                                                \
+  });
+#define KALDO_SSTORE(BUFI)                                                             \
+  static_for<S>([&](auto sc) __attribute__((always_inline)) {                                                         \
+    constexpr int s_ = decltype(sc)::value;                                            \
+    static_for<NA + NB>([&](auto uc) __attribute__((always_inline)) {                                                 \
+      constexpr int u_ = decltype(uc)::value;                                          \
+      const int row = (u_ < NA ? 0 : BM - RPP * NA) + row0 + RPP * u_;                 \
+      *reinterpret_cast<u32x4*>(lds + (BUFI) * BUF + lds_off<CB>(s_ * ROWS + row, slot)) = rg[s_][u_]; \
+    });                                                                                \
+  });
 
   Acc acc[FM][FN];
 #pragma unroll
@@ -190,20 +212,30 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   }
 
   const int nchunk = g.K / GemmChunk<P>::KC;
-  KALDO_GLOAD(0)
+  {
+    u32x4 rg[S][NA + NB];
+    KALDO_GLOAD(0)
+    KALDO_SSTORE(0)
+  }
   if constexpr (BD) {
     KALDO_BLOAD(0, bcur)
   }
-  KALDO_SSTORE(0)
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     // the next chunk (the last one again on the final pass: a harmless reload
     // into the buffer nobody reads any more keeps the loop free of branches)
     const int nxt = (ch + 1 < nchunk ? ch + 1 : ch) * GemmChunk<P>::KC;
+    u32x4 rg[S][NA + NB];
     KALDO_GLOAD(nxt)
     if constexpr (BD) {
       KALDO_BLOAD(nxt, bnx)
     }
+    // BF16X3: keep the next chunk's global loads ahead of this chunk's MFMAs.
+    // Left to itself the scheduler sinks them behind most of the MFMAs (to
+    // reuse fragment registers) and the wait before the LDS stores then
+    // exposes their latency.  (Measured: 2 % faster BF16X3 GEMMs, 3-5 %
+    // slower FP64 ones, whose chunks carry half as many MFMAs.)
+    if constexpr (P == KALDO_BF16X3) __builtin_amdgcn_sched_barrier(0);
     const char* base = lds + (ch & 1) * BUF;
     if constexpr (P == KALDO_BF16X3) {
 #pragma unroll
