@@ -10,7 +10,9 @@ gives ``value``; the FP64 path is timed beside it.
 The many-branch workloads that run the projection as MFMA GEMMs (the 46-atom
 cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed after it,
 BF16X3 beside FP64, and reported under ``mfma_paths`` with the roofline of
-their GEMMs (``--no-mfma`` skips them).
+their GEMMs (``--no-mfma`` skips them).  The 32-crystal batch (one HIP graph
+launch, FP32 beside FP64) is timed on a share of each crystal's first-mode
+points and reported under ``batched_path`` (``--no-batch`` skips it).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: one GPU only.
 """
@@ -217,6 +219,76 @@ def run_mfma(name, steps, warmup):
     return out
 
 
+def run_batch(div=64, steps=1, warmup=1):
+    """The 32-crystal batch (cells of 2..54 atoms, grids 4^3..10^3): linewidths
+    of every crystal in one HIP graph launch, FP32 beside FP64, on the first
+    ceil(N_k / div) first-mode points of each crystal (kaldo_batch_set_k_range:
+    one GPU's share of a k-sharded run).  The full draw is extrapolated with
+    the GEMM flops of each crystal as weights."""
+    import torch
+    from gen import batch_crystals
+    from paper_2009_01967_amd import kaldo
+
+    t0 = time.perf_counter()
+    crystals = batch_crystals()
+    log(f"batch: {len(crystals)} crystals generated in {time.perf_counter() - t0:.1f} s")
+    T, sigma = [300.0], 0.1
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = kaldo.Context(0, stream.cuda_stream)
+    t0 = time.perf_counter()
+    sub = []
+    for i, c in enumerate(crystals):
+        ctx.batch_add(c)
+        m = max(1, -(-c.n_k // div))
+        ctx.batch_set_k_range(i, 0, m)
+        sub.append(m)
+    torch.cuda.synchronize()
+    log(f"batch: phonons of {len(crystals)} crystals in {time.perf_counter() - t0:.1f} s")
+    outs = [torch.empty((len(T), c.n_k, c.n_modes), dtype=torch.float64, device=dev) for c in crystals]
+    res = {}
+    for label, prec in (("fp32", kaldo.KALDO_FP32), ("fp64", kaldo.KALDO_FP64)):
+        t0 = time.perf_counter()
+        for _ in range(warmup):  # the first call plans, tunes and captures the graph
+            kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, prec, outs))
+        torch.cuda.synchronize()
+        log(f"batch {label}: planned, captured and launched once in {time.perf_counter() - t0:.1f} s")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, prec, outs))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[label] = dict(ms=ms, g=[o[:, :m].cpu().numpy().copy() for o, m in zip(outs, sub)])
+        log(f"batch {label}: {ms:.1f} ms per graph launch")
+    ctx.close()
+    # accuracy of FP32 against FP64 on the computed points (unmasked modes)
+    err = 0.0
+    for g32, g64 in zip(res["fp32"]["g"], res["fp64"]["g"]):
+        on = g64 > 0
+        floor = 1e-6 * np.abs(g64).max()
+        err = max(err, float(np.max(np.abs(g32[on] - g64[on]) / np.maximum(g64[on], floor))))
+    lw = sum(m * c.n_modes for c, m in zip(crystals, sub)) * len(T)
+    gemm = [16.0 * m * c.n_k * c.n_modes ** 4 for c, m in zip(crystals, sub)]
+    gemm_full = [16.0 * c.n_k * c.n_k * c.n_modes ** 4 for c in crystals]
+    out = {"workload": "batch-32-crystals-2..54at-4^3..10^3", "crystals": len(crystals), "T_K": T,
+           "sigma_thz": sigma, "step": "one kaldo_batch_run graph launch on resident phonons",
+           "first_mode_points": f"ceil(N_k/{div}) per crystal, {sum(sub)} of {sum(c.n_k for c in crystals)}",
+           "gemm_flops_per_launch": sum(gemm), "gemm_flops_full_draw": sum(gemm_full),
+           "gamma_rel_err_fp32_vs_fp64": err}
+    for label, peak in (("fp32", FP32_MFMA_PEAK), ("fp64", FP64_MFMA_PEAK)):
+        ms = res[label]["ms"]
+        out[label] = {"ms_per_launch": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
+                      "extrapolated_full_draw_s": ms * 1e-3 * sum(gemm_full) / sum(gemm),
+                      "roofline": {"bound": "mfma", "kernel": "whole graph (all crystals, every kernel)",
+                                   "achieved": sum(gemm) / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                                   "unit": "TFLOP/s", "frac": sum(gemm) / (ms * 1e-3) / peak, "traffic": None}}
+    out["speedup_fp32_vs_fp64"] = res["fp64"]["ms"] / res["fp32"]["ms"]
+    return out
+
+
 def cpu_baseline(r, budget_s=20.0):
     """The FP64 oracle on the host, on a bounded sample of first-mode k points."""
     from oracle import phonons as P, anharmonic as A
@@ -261,6 +333,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the headline workload (prints only the MFMA workloads; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -281,7 +354,12 @@ def main():
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}))
         return
     if args.no_main:
-        print(json.dumps({"mfma_paths": [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]}))
+        extra = {}
+        if not args.no_mfma:
+            extra["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
+        if not args.no_batch:
+            extra["batched_path"] = run_batch()
+        print(json.dumps(extra))
         return
     r = run_gpu(args)
     nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
@@ -326,6 +404,8 @@ def main():
     }
     if not args.no_mfma:
         out["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
+    if not args.no_batch:
+        out["batched_path"] = run_batch()
     if not args.no_cpu:
         base, err = cpu_baseline(r)
         out["cpu_baseline"] = base

@@ -226,6 +226,25 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
                              kaldo_precision precision, double* const* gamma_out);
 kaldo_status kaldo_batch_clear(kaldo_ctx ctx);
 
+/* One GPU's share of a run sharded over first-mode grid points.  The
+ * linewidth of every mode is a sum of its own (paper Sec. II.B, Gamma^0), and
+ * the RTA conductivity (eq. RTA) is a sum over modes, so both split over
+ * disjoint ranges of first-mode points k.
+ *
+ * kaldo_set_k_range restricts later kaldo_linewidths calls on ctx to the
+ * points k_begin <= k < k_end of the grid (clamped to N_k; a call whose
+ * clamped range is empty returns KALDO_EINVAL).  gamma of the other points is
+ * returned as 0, and kaldo_kappa_rta then sums the covered modes only: the
+ * kappa of the shards [0, K1), [K1, K2), ... add up to the kappa of the full
+ * grid.  (0, INT32_MAX) is the default, the whole grid.  QHGK (grid {1,1,1})
+ * has the single point k = 0.  Errors: KALDO_EINVAL unless
+ * 0 <= k_begin < k_end.
+ *
+ * kaldo_batch_set_k_range does the same for crystal `handle` of the batch
+ * (0 <= k_begin < N_k of that crystal), and drops a captured graph. */
+kaldo_status kaldo_set_k_range(kaldo_ctx ctx, int32_t k_begin, int32_t k_end);
+kaldo_status kaldo_batch_set_k_range(kaldo_ctx ctx, int32_t handle, int32_t k_begin, int32_t k_end);
+
 /* Tile-shape selection for the MFMA GEMMs (not a step of the method).  With
  * KALDO_TUNE_AUTO (the default) the first call that meets a GEMM shape times
  * each candidate tile shape once and keeps the fastest for the context; the

@@ -419,8 +419,13 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
-  for (int k0 = 0; k0 < nk && !planning(ctx); k0 += kchunk) {
-    const int kc = std::min(kchunk, nk - k0);
+  const int kb = k_lo(ctx), ke = k_hi(ctx);
+  if (k_partial(ctx) && !planning(ctx)) {
+    const kaldo_status fs = fill_zero(ctx, ctx->d_gamma.p, (size_t)nT * nmode * sizeof(double));
+    if (fs != KALDO_OK) return fs;
+  }
+  for (int k0 = kb; k0 < ke && !planning(ctx); k0 += kchunk) {
+    const int kc = std::min(kchunk, ke - k0);
     P.k0 = k0;
     prof_begin(ctx);
     hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)a_per_k / sizeof(cplx<R>) * kc, TB)), dim3(TB), 0,

@@ -482,12 +482,15 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
   } else if (!ctx->have_fc3) {
     return fail(ctx, KALDO_ESTATE, "no fc3 resident: pass one");
   }
+  if (k_lo(ctx) >= k_hi(ctx)) return fail(ctx, KALDO_EINVAL, "the k range holds no grid point");
   ctx->nT = nT;
   for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
   ctx->stats = stats;
   ctx->delta = delta;
   ctx->have_gamma = false;
   if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
+  ctx->g_lo = k_lo(ctx);
+  ctx->g_hi = k_hi(ctx);
   ctx->have_gamma = true;
   if (gamma_out) {
     const size_t bytes = (size_t)nT * ctx->nk * ctx->nm * sizeof(double);
@@ -633,12 +636,39 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
   prof_end(ctx, "batch_graph");
   for (size_t i = 0; i < ctx->batch.size(); ++i) {
     kaldo_ctx sub = ctx->batch[i];
+    sub->g_lo = k_lo(sub);
+    sub->g_hi = k_hi(sub);
     sub->have_gamma = true;
     if (gamma_out && gamma_out[i]) {
       const size_t bytes = (size_t)nT * sub->nk * sub->nm * sizeof(double);
       if ((st = copy_out(ctx, gamma_out[i], sub->d_gamma.p, bytes)) != KALDO_OK) return st;
     }
   }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_set_k_range(kaldo_ctx ctx, int32_t k_begin, int32_t k_end) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  if (k_begin < 0 || k_end <= k_begin) return fail(ctx, KALDO_EINVAL, "kaldo_set_k_range: need 0 <= k_begin < k_end");
+  ctx->k_begin = k_begin;
+  ctx->k_end = k_end;
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_batch_set_k_range(kaldo_ctx ctx, int32_t handle, int32_t k_begin, int32_t k_end) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  if (handle < 0 || handle >= (int32_t)ctx->batch.size())
+    return fail(ctx, KALDO_EINVAL, "kaldo_batch_set_k_range: no such crystal");
+  kaldo_ctx sub = ctx->batch[handle];
+  if (k_begin < 0 || k_end <= k_begin || k_begin >= sub->nk)
+    return fail(ctx, KALDO_EINVAL, "kaldo_batch_set_k_range: need 0 <= k_begin < min(k_end, N_k)");
+  sub->k_begin = k_begin;
+  sub->k_end = k_end;
+  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);  // the captured launches change
+  ctx->batch_exec = nullptr;
+  ctx->batch_key.clear();
   return KALDO_OK;
 }
 

@@ -410,7 +410,12 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
   // planning visits one first-mode point and the batches whose GEMM shapes differ
   const bool plan = planning(ctx);
-  for (int k = 0; k < (plan ? 1 : nk); ++k) {
+  const int kb = k_lo(ctx), ke = k_hi(ctx);
+  if (k_partial(ctx) && !plan) {
+    const kaldo_status fs = fill_zero(ctx, gr, graw_n * sizeof(double));
+    if (fs != KALDO_OK) return fs;
+  }
+  for (int k = kb; k < (plan ? kb + 1 : ke); ++k) {
     prof_begin(ctx);
     if (!plan)
       hipLaunchKernelGGL((k_cr_zg<RZ>), dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,

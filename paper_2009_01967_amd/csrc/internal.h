@@ -164,6 +164,8 @@ struct kaldo_ctx_s {
   double T[KALDO_MAX_T] = {0};
   int stats = 0;
   int delta = KALDO_DELTA_GAUSS;
+  int k_begin = 0, k_end = 0x7fffffff;  // first-mode grid points computed (kaldo_set_k_range)
+  int g_lo = 0, g_hi = 0;                // the points the resident gamma covers
   kaldo::DevBuf d_gamma;             // double [nT][Nk][n]
   kaldo::DevBuf d_tabs;              // per-call mode tables
   kaldo::DevBuf d_phase;             // phase space: mode tables and g [nT][Nk][n]
@@ -194,6 +196,11 @@ void prof_clear(kaldo_ctx ctx);
 kaldo_status fill_zero(kaldo_ctx ctx, void* p, size_t bytes);
 
 inline bool planning(kaldo_ctx ctx) { return ctx->mode == kPlan; }
+
+// first-mode grid points [k_lo, k_hi) of the next linewidth run, clamped to the grid
+inline int k_lo(const kaldo_ctx_s* c) { return c->k_begin < c->nk ? c->k_begin : c->nk; }
+inline int k_hi(const kaldo_ctx_s* c) { return c->k_end < c->nk ? c->k_end : c->nk; }
+inline bool k_partial(const kaldo_ctx_s* c) { return k_lo(c) > 0 || k_hi(c) < c->nk; }
 
 // copy a device result into a caller pointer that may be host or device memory
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);

@@ -42,15 +42,17 @@ __device__ void block_sum9(double (&v)[9], double* out) {
   }
 }
 
-// one block per (temperature, slice of modes); partial[t][slice][9]
+// one block per (temperature, slice of modes); partial[t][slice][9].  Modes
+// m0 <= m < m1 (the first-mode points the linewidths cover) enter the sum.
 __global__ void __launch_bounds__(256) k_kappa_rta(double* __restrict__ partial, const double* __restrict__ gamma,
                                                    const double* __restrict__ omega, const double* __restrict__ vv,
-                                                   int nmode, double4 T03, double4 T47, int classical) {
+                                                   int nmode, int m0, int m1, double4 T03, double4 T47,
+                                                   int classical) {
   const int t = blockIdx.y;
   const double Ts[8] = {T03.x, T03.y, T03.z, T03.w, T47.x, T47.y, T47.z, T47.w};
   const double T = Ts[t];
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nmode; m += gridDim.x * blockDim.x) {
+  for (int m = m0 + blockIdx.x * blockDim.x + threadIdx.x; m < m1; m += gridDim.x * blockDim.x) {
     const double w = omega[m];
     if (w / kTwoPi < kNuMinThz) continue;
     const double ct = heat_capacity(w, T, classical) / (2.0 * gamma[(size_t)t * nmode + m]);
@@ -87,8 +89,8 @@ kaldo_status run_kappa_rta(kaldo_ctx ctx) {
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
   prof_begin(ctx);
   hipLaunchKernelGGL(k_kappa_rta, dim3(nslice, nT), dim3(256), 0, st, ctx->d_partial.as<double>(),
-                     ctx->d_gamma.as<double>(), ctx->d_omega.as<double>(), ctx->d_vv.as<double>(), nmode, T03, T47,
-                     ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+                     ctx->d_gamma.as<double>(), ctx->d_omega.as<double>(), ctx->d_vv.as<double>(), nmode,
+                     ctx->g_lo * ctx->nm, ctx->g_hi * ctx->nm, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
   KALDO_HIP(ctx, hipGetLastError());
   prof_end(ctx, "kappa_rta");
   const double scale = kKappaSI / (ctx->nk * cell_volume(ctx->cell));

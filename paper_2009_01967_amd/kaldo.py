@@ -45,7 +45,7 @@ STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALD
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
-            "kaldo_profile_read", "kaldo_phase_space"]
+            "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range"]
 
 
 class kaldo_structure(C.Structure):
@@ -93,6 +93,10 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_linewidths.argtypes = [C.c_void_p, C.POINTER(kaldo_fc3), C.POINTER(C.c_double), C.c_int32,
                                      C.c_double, C.c_int, C.c_int, C.c_int, C.c_void_p]
     lib.kaldo_linewidths.restype = C.c_int
+    lib.kaldo_set_k_range.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.kaldo_set_k_range.restype = C.c_int
+    lib.kaldo_batch_set_k_range.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.kaldo_batch_set_k_range.restype = C.c_int
     lib.kaldo_phase_space.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int,
                                       C.c_int, C.c_void_p]
     lib.kaldo_phase_space.restype = C.c_int
@@ -217,6 +221,14 @@ def kaldo_linewidths(ctx, fc3, T: Sequence[float], sigma_thz: float, stats: int 
     return load_library().kaldo_linewidths(ctx, C.byref(fc3) if fc3 is not None else None, Ts, len(T),
                                            float(sigma_thz), int(delta), int(stats), int(precision),
                                            _out_ptr(gamma_out))
+
+
+def kaldo_set_k_range(ctx, k_begin: int, k_end: int) -> int:
+    return load_library().kaldo_set_k_range(ctx, int(k_begin), int(k_end))
+
+
+def kaldo_batch_set_k_range(ctx, handle: int, k_begin: int, k_end: int) -> int:
+    return load_library().kaldo_batch_set_k_range(ctx, int(handle), int(k_begin), int(k_end))
 
 
 def kaldo_phase_space(ctx, T: Sequence[float], sigma_thz: float, delta: int = KALDO_DELTA_GAUSS,
@@ -365,6 +377,13 @@ class Context:
     def batch_clear(self):
         _check(self.h, kaldo_batch_clear(self.h))
         self.batch_shapes = []
+
+    def set_k_range(self, k_begin=0, k_end=2**31 - 1):
+        """Compute later linewidths for first-mode points k_begin <= k < k_end only."""
+        _check(self.h, kaldo_set_k_range(self.h, k_begin, k_end))
+
+    def batch_set_k_range(self, handle, k_begin, k_end):
+        _check(self.h, kaldo_batch_set_k_range(self.h, handle, k_begin, k_end))
 
     def phase_space(self, T=(300.0,), sigma_thz=0.1, classical=False, delta="gauss", out=None):
         """Phase space per mode g [nT][Nk][n] in ps/rad on the last phonons' grid."""
