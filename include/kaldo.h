@@ -133,6 +133,22 @@ kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream);
 /* Release all device memory of the context.  NULL is accepted. */
 void kaldo_destroy(kaldo_ctx ctx);
 
+/* Device memory from the caller (for instance one torch.empty(bytes,
+ * dtype=uint8, device='cuda') tensor) instead of the library's own hipMalloc
+ * (memory plumbing, not a step of the method).  From this call on, every device
+ * buffer of the context, and of the crystals it batches, is carved from
+ * [dev_ptr, dev_ptr + bytes), front to back, 256-byte aligned; a buffer that
+ * grows takes a new piece and the old one is not reused, so size the workspace
+ * generously.  The caller keeps the memory allocated and leaves it alone until
+ * kaldo_destroy.  The rocBLAS/rocSOLVER handle keeps its own small workspace.
+ *   dev_ptr  device memory on the context's device (NULL with bytes 0: back to
+ *            the library's allocations)
+ * A call that needs more than what is left returns KALDO_ENOMEM; its error text
+ * says how many bytes were missing.  Errors: KALDO_ESTATE unless the context
+ * holds no data yet (no phonons, fc3 or batch), KALDO_EINVAL for memory that is
+ * not device memory of the context's device. */
+kaldo_status kaldo_set_workspace(kaldo_ctx ctx, void* dev_ptr, size_t bytes);
+
 /* Text of the last error on this context ("" if none); valid until the next
  * call on the context. */
 const char* kaldo_last_error(kaldo_ctx ctx);

@@ -18,9 +18,13 @@ kaldo_status fail(kaldo_ctx ctx, kaldo_status s, const std::string& msg) {
   return s;
 }
 
+thread_local Arena* g_arena = nullptr;
+
 kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what) {
   std::ostringstream os;
   os << what << ": " << hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory && g_arena && g_arena->short_by)
+    os << " (the workspace is " << g_arena->short_by << " bytes short)";
   return fail(ctx, e == hipErrorOutOfMemory ? KALDO_ENOMEM : KALDO_EDEVICE, os.str());
 }
 
@@ -409,6 +413,7 @@ const char* kaldo_last_error(kaldo_ctx ctx) { return ctx ? ctx->err.c_str() : "N
 kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
                            const int32_t grid[3], double* nu_out, double* vel_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!grid) return fail(ctx, KALDO_EINVAL, "grid is NULL");
@@ -472,6 +477,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
                               double sigma_thz, kaldo_delta delta, kaldo_stats stats,
                               kaldo_precision precision, double* gamma_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_linewidths before kaldo_phonons");
@@ -502,6 +508,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
 kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_delta delta,
                                kaldo_stats stats, double* g_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_phase_space before kaldo_phonons");
@@ -515,6 +522,7 @@ kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, doubl
 
 kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_rta before kaldo_linewidths");
@@ -527,6 +535,7 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
 
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_qhgk before kaldo_linewidths");
@@ -540,6 +549,7 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
 kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
                              const kaldo_fc3* fc3, const int32_t grid[3], int32_t* handle) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (!structure || !fc2 || !fc3 || !grid || !handle)
@@ -610,6 +620,7 @@ static kaldo_status batch_capture(kaldo_ctx ctx, double sigma_thz, int precision
 kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
                              kaldo_precision precision, double* const* gamma_out) {
   if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (ctx->batch.empty()) return fail(ctx, KALDO_ESTATE, "kaldo_batch_run: the batch is empty");
@@ -644,6 +655,28 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
       if ((st = copy_out(ctx, gamma_out[i], sub->d_gamma.p, bytes)) != KALDO_OK) return st;
     }
   }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_set_workspace(kaldo_ctx ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  if (ctx->have_phonons || ctx->have_fc3 || !ctx->batch.empty())
+    return fail(ctx, KALDO_ESTATE, "kaldo_set_workspace: only on a context that holds no data yet");
+  if (!dev_ptr || bytes == 0) {
+    if (dev_ptr || bytes) return fail(ctx, KALDO_EINVAL, "kaldo_set_workspace: pointer and size go together");
+    ctx->arena = Arena{};
+    return KALDO_OK;
+  }
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+      attr.device != ctx->device) {
+    (void)hipGetLastError();
+    return fail(ctx, KALDO_EINVAL, "kaldo_set_workspace: not device memory of the context's device");
+  }
+  ctx->arena = Arena{static_cast<char*>(dev_ptr), bytes, 0, 0};
   return KALDO_OK;
 }
 

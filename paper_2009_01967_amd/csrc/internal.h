@@ -30,23 +30,53 @@ constexpr double kNuUnstableThz = -0.05; // below: imaginary mode error
 constexpr double kDegenerateThz = 1e-5;  // chained gap for degenerate sets
 
 // ---- device buffer ----------------------------------------------------------
+// A caller's workspace (kaldo_set_workspace): buffers are carved from it front
+// to back, 256-byte aligned, and never handed back one by one.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  size_t short_by = 0;  // bytes missing at the last failed carve
+};
+// The workspace of the context whose library call is running on this thread
+// (null: buffers come from hipMalloc).  Set for the duration of a call by ArenaScope.
+extern thread_local Arena* g_arena;
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(g_arena) { g_arena = a && a->base ? a : nullptr; }
+  ~ArenaScope() { g_arena = prev; }
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool ext = false;  // carved from a caller's workspace (not ours to free)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !ext) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    ext = false;
   }
   // (Re)allocate to at least n bytes; contents are not preserved.
   hipError_t ensure(size_t n) {
     if (n <= bytes && p) return hipSuccess;
     release();
     if (n == 0) n = 16;
+    if (g_arena) {
+      const size_t off = (g_arena->used + 255) & ~(size_t)255;
+      if (off > g_arena->size || n > g_arena->size - off) {
+        g_arena->short_by = off + n - g_arena->size;
+        return hipErrorOutOfMemory;
+      }
+      p = g_arena->base + off;
+      g_arena->used = off + n;
+      bytes = n;
+      ext = true;
+      return hipSuccess;
+    }
     hipError_t e = hipMalloc(&p, n);
     if (e == hipSuccess) bytes = n;
     else p = nullptr;
@@ -164,6 +194,7 @@ struct kaldo_ctx_s {
   double T[KALDO_MAX_T] = {0};
   int stats = 0;
   int delta = KALDO_DELTA_GAUSS;
+  kaldo::Arena arena;                   // caller's workspace (kaldo_set_workspace), if any
   int k_begin = 0, k_end = 0x7fffffff;  // first-mode grid points computed (kaldo_set_k_range)
   int g_lo = 0, g_hi = 0;                // the points the resident gamma covers
   kaldo::DevBuf d_gamma;             // double [nT][Nk][n]

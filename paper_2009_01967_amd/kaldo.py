@@ -45,7 +45,8 @@ STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALD
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
-            "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range"]
+            "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
+            "kaldo_set_workspace"]
 
 
 class kaldo_structure(C.Structure):
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_linewidths.argtypes = [C.c_void_p, C.POINTER(kaldo_fc3), C.POINTER(C.c_double), C.c_int32,
                                      C.c_double, C.c_int, C.c_int, C.c_int, C.c_void_p]
     lib.kaldo_linewidths.restype = C.c_int
+    lib.kaldo_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.kaldo_set_workspace.restype = C.c_int
     lib.kaldo_set_k_range.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.kaldo_set_k_range.restype = C.c_int
     lib.kaldo_batch_set_k_range.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
@@ -223,6 +226,10 @@ def kaldo_linewidths(ctx, fc3, T: Sequence[float], sigma_thz: float, stats: int 
                                            _out_ptr(gamma_out))
 
 
+def kaldo_set_workspace(ctx, dev_ptr: Optional[int], nbytes: int) -> int:
+    return load_library().kaldo_set_workspace(ctx, C.c_void_p(dev_ptr) if dev_ptr else None, int(nbytes))
+
+
 def kaldo_set_k_range(ctx, k_begin: int, k_end: int) -> int:
     return load_library().kaldo_set_k_range(ctx, int(k_begin), int(k_end))
 
@@ -294,16 +301,24 @@ class Context:
     """One library context on one GPU.  Inputs are numpy arrays; outputs are
     numpy arrays unless a device tensor is passed as ``out``."""
 
-    def __init__(self, device: int = 0, stream: Optional[int] = None):
+    def __init__(self, device: int = 0, stream: Optional[int] = None, workspace_bytes: Optional[int] = None):
+        """``workspace_bytes``: take every device buffer of the context from one
+        torch allocation of that size (kaldo_set_workspace) instead of hipMalloc."""
         self.h = kaldo_create(device, stream)
         self.nk = 0
         self.n = 0
         self.nT = 0
+        self.workspace = None
+        if workspace_bytes:
+            import torch
+            self.workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+            _check(self.h, kaldo_set_workspace(self.h, self.workspace.data_ptr(), self.workspace.numel()))
 
     def close(self):
         if self.h:
             kaldo_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
