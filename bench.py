@@ -289,6 +289,30 @@ def run_batch(div=64, steps=1, warmup=1):
     return out
 
 
+def measured_peaks():
+    """Attainable rates of the units the kernels use, from register-only MFMA /
+    FMA loops and a 1 GiB streaming copy (libpeaks.so), beside the published
+    peaks that the roofline fractions use."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2009_01967_amd", "libpeaks.so"))
+    for name in ("mi355x_peak_mfma_bf16", "mi355x_peak_mfma_f32", "mi355x_peak_mfma_f64"):
+        getattr(lib, name).restype = ctypes.c_double
+    lib.mi355x_peak_valu.restype = ctypes.c_double
+    lib.mi355x_peak_valu.argtypes = [ctypes.c_int]
+    lib.mi355x_peak_hbm.restype = ctypes.c_double
+    lib.mi355x_peak_hbm.argtypes = [ctypes.c_size_t]
+    out = {"mfma_bf16_tflops": lib.mi355x_peak_mfma_bf16() / 1e12,
+           "mfma_f32_tflops": lib.mi355x_peak_mfma_f32() / 1e12,
+           "mfma_f64_tflops": lib.mi355x_peak_mfma_f64() / 1e12,
+           "valu_f32_tflops_nonpacked": lib.mi355x_peak_valu(0) / 1e12,
+           "valu_f64_tflops": lib.mi355x_peak_valu(1) / 1e12,
+           "hbm_copy_gbps": lib.mi355x_peak_hbm(1 << 30) / 1e9,
+           "published": {"mfma_bf16_tflops": 2500.0, "mfma_f32_tflops": 157.3, "mfma_f64_tflops": 78.6,
+                         "valu_f32_tflops": 157.3, "valu_f64_tflops": 78.6, "hbm_gbps": 8000.0}}
+    log(f"measured peaks: {out}")
+    return out
+
+
 def cpu_baseline(r, budget_s=20.0):
     """The FP64 oracle on the host, on a bounded sample of first-mode k points."""
     from oracle import phonons as P, anharmonic as A
@@ -334,6 +358,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
+    ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the headline workload (prints only the MFMA workloads; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -352,6 +377,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}))
+        return
+    if args.peaks:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"measured_peaks": measured_peaks()}))
         return
     if args.no_main:
         extra = {}
@@ -406,6 +436,7 @@ def main():
         out["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
     if not args.no_batch:
         out["batched_path"] = run_batch()
+    out["measured_peaks"] = measured_peaks()
     if not args.no_cpu:
         base, err = cpu_baseline(r)
         out["cpu_baseline"] = base

@@ -1,4 +1,5 @@
-"""Build the gfx950 shared library ``libkaldo.so`` in-tree with hipcc.
+"""Build the gfx950 shared library ``libkaldo.so`` (and the peak
+microbenchmarks ``libpeaks.so`` used by the benchmark) in-tree with hipcc.
 
 Usage: ``python -m paper_2009_01967_amd.build`` (or ``build()`` from Python).
 Every call recompiles all sources.
@@ -17,6 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkaldo.so")
+PEAKS = os.path.join(HERE, "libpeaks.so")
 
 SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip", "phase.hip"]
 
@@ -66,6 +68,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the peak microbenchmarks (a measurement tool for the benchmark, not part of the ABI)
+    pobj = _compile("peaks.hip", verbose)
+    tmp = PEAKS + ".tmp"
+    r = subprocess.run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, pobj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAKS)
     return LIB
 
 
