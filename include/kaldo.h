@@ -95,7 +95,8 @@ typedef enum {
 
 typedef enum {
   KALDO_TUNE_AUTO = 0,  /* time the candidate tile shapes of each GEMM problem once, keep the fastest */
-  KALDO_TUNE_FIXED = 1  /* fixed tile shapes: results bitwise reproducible across contexts */
+  KALDO_TUNE_FIXED = 1, /* fixed tile shapes: results bitwise reproducible across contexts */
+  KALDO_TUNE_SHAPE0 = 2 /* KALDO_TUNE_SHAPE0 + v: tile shape v (0 .. 15) of every GEMM (for tests) */
 } kaldo_tuning;
 
 /* At most this many temperatures per kaldo_linewidths call. */
@@ -265,7 +266,9 @@ kaldo_status kaldo_batch_set_k_range(kaldo_ctx ctx, int32_t handle, int32_t k_be
  * KALDO_TUNE_AUTO (the default) the first call that meets a GEMM shape times
  * each candidate tile shape once and keeps the fastest for the context; the
  * results of different tile shapes agree to rounding, not bitwise.
- * KALDO_TUNE_FIXED uses one fixed shape per problem.  Returns KALDO_EINVAL for
+ * KALDO_TUNE_FIXED uses one fixed shape per problem.  KALDO_TUNE_SHAPE0 + v
+ * forces candidate v of every GEMM problem (shape 0 where a problem has fewer
+ * candidates), so that tests can reach every tile shape.  Returns KALDO_EINVAL for
  * an unknown mode. */
 kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
 

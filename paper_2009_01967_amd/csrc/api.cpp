@@ -69,6 +69,10 @@ void prof_clear(kaldo_ctx ctx) {
 
 int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const std::function<void(int)>& launch) {
   kaldo_ctx owner = ctx->tune_owner ? ctx->tune_owner : ctx;
+  if (owner->tuning >= KALDO_TUNE_SHAPE0) {
+    const int v = owner->tuning - KALDO_TUNE_SHAPE0;
+    return v < nv ? v : fallback;
+  }
   if (owner->tuning != KALDO_TUNE_AUTO || nv <= 1) return fallback;
   auto it = owner->tuned.find(key);
   if (it != owner->tuned.end()) return it->second;
@@ -707,7 +711,7 @@ kaldo_status kaldo_batch_set_k_range(kaldo_ctx ctx, int32_t handle, int32_t k_be
 
 kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode) {
   if (!ctx) return KALDO_EINVAL;
-  if (mode != KALDO_TUNE_AUTO && mode != KALDO_TUNE_FIXED)
+  if (mode != KALDO_TUNE_AUTO && mode != KALDO_TUNE_FIXED && !(mode >= KALDO_TUNE_SHAPE0 && mode < KALDO_TUNE_SHAPE0 + 16))
     return fail(ctx, KALDO_EINVAL, "kaldo_set_tuning: unknown mode");
   ctx->tuning = mode;
   ctx->tuned.clear();

@@ -99,14 +99,21 @@ __device__ __forceinline__ int lds_off(int row, int slot) {
 // BD (BF16X3 only): B fragments go from global memory (L1/L2) straight to the
 // wavefront's registers one chunk ahead, and LDS stages A alone.  The split
 // operands make BF16X3 LDS-bound; this halves its LDS traffic.
-template <int P, int FM, int FN, class Epi, bool BD = false>
+// WC (BF16X3 only, K a multiple of 64): 128-byte chunks in a single LDS
+// buffer, refilled between two barriers from registers loaded during the
+// chunk's MFMAs.  Twice the MFMA work per barrier in the same LDS space as the
+// double-buffered 64-byte chunks; faster on long contractions.
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
 __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   using T = typename Operand<P>::T;
   using Acc = typename Operand<P>::Acc;
   constexpr int S = Operand<P>::split;
   static_assert(!BD || P == KALDO_BF16X3, "direct B fragments are a BF16X3 variant");
+  static_assert(!WC || (P == KALDO_BF16X3 && !BD), "wide chunks are a BF16X3 variant with B in LDS");
   constexpr int BM = 32 * FM, BN = 32 * FN;
-  constexpr int CB = GemmChunk<P>::CB;
+  constexpr int CB = WC ? 128 : GemmChunk<P>::CB;
+  constexpr int KCH = CB / (int)sizeof(T);    // elements per row chunk
+  constexpr int NBUF = WC ? 1 : 2;            // LDS buffers
   constexpr int RB = CB == 64 ? 64 : CB + 16; // LDS bytes per tile row (see lds_off)
   constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
   constexpr int RPP = 256 / SLOTS;            // rows loaded per pass of the block
@@ -116,7 +123,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   constexpr int ROWS = BM + (BD ? 0 : BN);
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
-  __shared__ __attribute__((aligned(16))) char lds[2 * BUF];
+  __shared__ __attribute__((aligned(16))) char lds[NBUF * BUF];
 
   // XCD-aware order: logical tile = start of this XCD's run + position in it
   const int nb = (int)gridDim.x, b = (int)blockIdx.x;
@@ -211,7 +218,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
         *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + (K0));                                         \
   }
 
-  const int nchunk = g.K / GemmChunk<P>::KC;
+  const int nchunk = g.K / KCH;
   {
     u32x4 rg[S][NA + NB];
     KALDO_GLOAD(0)
@@ -224,7 +231,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   for (int ch = 0; ch < nchunk; ++ch) {
     // the next chunk (the last one again on the final pass: a harmless reload
     // into the buffer nobody reads any more keeps the loop free of branches)
-    const int nxt = (ch + 1 < nchunk ? ch + 1 : ch) * GemmChunk<P>::KC;
+    const int nxt = (ch + 1 < nchunk ? ch + 1 : ch) * KCH;
     u32x4 rg[S][NA + NB];
     KALDO_GLOAD(nxt)
     if constexpr (BD) {
@@ -236,7 +243,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     // exposes their latency.  (Measured: 2 % faster BF16X3 GEMMs, 3-5 %
     // slower FP64 ones, whose chunks carry half as many MFMAs.)
     if constexpr (P == KALDO_BF16X3) __builtin_amdgcn_sched_barrier(0);
-    const char* base = lds + (ch & 1) * BUF;
+    const char* base = lds + (WC ? 0 : (ch & 1) * BUF);
     if constexpr (P == KALDO_BF16X3) {
 #pragma unroll
       for (int j = 0; j < CB / 64; ++j) {
@@ -316,7 +323,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
           for (int c = 0; c < FN; ++c)
             acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][j], bf[c][j], acc[a][c], 0, 0, 0);
     }
-    KALDO_SSTORE((ch + 1) & 1)
+    if constexpr (WC) {
+      __syncthreads();  // every wavefront is done reading the buffer
+      KALDO_SSTORE(0)
+    } else {
+      KALDO_SSTORE((ch + 1) & 1)
+    }
     if constexpr (BD) {
 #pragma unroll
       for (int c = 0; c < FN; ++c) {
@@ -378,14 +390,16 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
 // Candidate (FM, FN) shapes, block tile 32 FM x 32 FN.  FP64 accumulators take
 // twice the registers of FP32 ones, so its candidates are one size smaller;
 // the 64-byte chunks of BF16 and FP32 load 64 rows per pass (FM, FN even).
-// BF16X3 adds candidates 4 and 5, whose B fragments bypass LDS, and 6, a
+// BF16X3 adds candidates 4 and 5, whose B fragments bypass LDS, 6, a
 // 128 x 256 block tile (64 x 128 per wavefront: twice the MFMA work per LDS
-// fragment read and half the A-panel re-reads).
-constexpr int kGemmVariantsMax = 7;
+// fragment read and half the A-panel re-reads), and 7 and 8, the tiles of 0
+// and 1 with wide chunks (WC; they fall back to 0 and 1 when K is not a
+// multiple of 64).
+constexpr int kGemmVariantsMax = 9;
 
 template <int P>
 inline int gemm_variants() {
-  return P == KALDO_BF16X3 ? 7 : 4;
+  return P == KALDO_BF16X3 ? 9 : 4;
 }
 
 // An epilogue with kAllShapes = false is instantiated with the first tile shape
@@ -403,7 +417,7 @@ inline int gemm_variants() {
 template <int P>
 inline int gemm_fm(int v) {
   if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
-  return v == 1 || v == 3 || v == 5 ? 2 : 4;
+  return v == 1 || v == 3 || v == 5 || v == 8 ? 2 : 4;
 }
 
 template <int P>
@@ -412,12 +426,12 @@ inline int gemm_m_tiles(int v, int m) {
   return (m + bm - 1) / bm;
 }
 
-template <int P, int FM, int FN, class Epi, bool BD = false>
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
 inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
   g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
   const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
-  hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi, BD>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
+  hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi, BD, WC>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
 }
 
 template <int P, class Epi>
@@ -443,6 +457,10 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     else if (v == 3) gemm_launch_tile<P, 2, 2>(g, e, st);
     else if (v == 4) gemm_launch_tile<P, 4, 4, Epi, true>(g, e, st);
     else if (v == 5) gemm_launch_tile<P, 2, 4, Epi, true>(g, e, st);
+    else if (v == 7 && g.K % 64 == 0) gemm_launch_tile<P, 4, 4, Epi, false, true>(g, e, st);
+    else if (v == 7) gemm_launch_tile<P, 4, 4>(g, e, st);
+    else if (v == 8 && g.K % 64 == 0) gemm_launch_tile<P, 2, 4, Epi, false, true>(g, e, st);
+    else if (v == 8) gemm_launch_tile<P, 2, 4>(g, e, st);
     else gemm_launch_tile<P, 4, 8>(g, e, st);
   }
 }

@@ -38,6 +38,7 @@ KALDO_CLASSICAL = 1
 KALDO_MAX_T = 8
 KALDO_TUNE_AUTO = 0
 KALDO_TUNE_FIXED = 1
+KALDO_TUNE_SHAPE0 = 2
 
 STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALDO_EDEVICE",
                 -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
@@ -278,7 +279,7 @@ def kaldo_batch_clear(ctx) -> int:
 
 
 def kaldo_set_tuning(ctx, mode: int) -> int:
-    """KALDO_TUNE_AUTO (0) or KALDO_TUNE_FIXED (1)."""
+    """KALDO_TUNE_AUTO (0), KALDO_TUNE_FIXED (1) or KALDO_TUNE_SHAPE0 + v (tile shape v)."""
     return load_library().kaldo_set_tuning(ctx, int(mode))
 
 
@@ -301,18 +302,23 @@ class Context:
     """One library context on one GPU.  Inputs are numpy arrays; outputs are
     numpy arrays unless a device tensor is passed as ``out``."""
 
-    def __init__(self, device: int = 0, stream: Optional[int] = None, workspace_bytes: Optional[int] = None):
-        """``workspace_bytes``: take every device buffer of the context from one
-        torch allocation of that size (kaldo_set_workspace) instead of hipMalloc."""
+    def __init__(self, device: int = 0, stream: Optional[int] = None, workspace=None):
+        """``workspace``: device memory for every buffer of the context
+        (kaldo_set_workspace): a CUDA uint8 torch tensor, kept alive by the
+        context, or a (device pointer, bytes) pair.  As with torch streams,
+        torch must have initialised the GPU before the library's first call in
+        the process (the library and torch each load a HIP runtime)."""
         self.h = kaldo_create(device, stream)
         self.nk = 0
         self.n = 0
         self.nT = 0
-        self.workspace = None
-        if workspace_bytes:
-            import torch
-            self.workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
-            _check(self.h, kaldo_set_workspace(self.h, self.workspace.data_ptr(), self.workspace.numel()))
+        self.workspace = workspace
+        if workspace is not None:
+            if isinstance(workspace, tuple):
+                ptr, nbytes = workspace
+            else:
+                ptr, nbytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+            _check(self.h, kaldo_set_workspace(self.h, ptr, nbytes))
 
     def close(self):
         if self.h:

@@ -179,7 +179,8 @@ def test_abi_errors():
         with pytest.raises(kaldo.KaldoError) as e:
             ctx.kappa_qhgk()
         assert e.value.status in (kaldo.KALDO_ESTATE, kaldo.KALDO_EINVAL)
-        assert kaldo.kaldo_set_tuning(ctx.h, 7) == kaldo.KALDO_EINVAL
+        assert kaldo.kaldo_set_tuning(ctx.h, 99) == kaldo.KALDO_EINVAL
+        assert kaldo.kaldo_set_tuning(ctx.h, -1) == kaldo.KALDO_EINVAL
         assert kaldo.kaldo_set_tuning(ctx.h, kaldo.KALDO_TUNE_FIXED) == kaldo.KALDO_OK
         assert kaldo.kaldo_set_tuning(ctx.h, kaldo.KALDO_TUNE_AUTO) == kaldo.KALDO_OK
         # a negative spring makes an imaginary mode

@@ -1,0 +1,52 @@
+"""Every candidate tile shape of the MFMA GEMM core (forced with
+KALDO_TUNE_SHAPE0 + v) against the FP64 oracle, on the crystal path (4-atom
+cell, 3x3x2 grid: K = 24 padded to one chunk) and the Gamma-point path
+(16-atom folded cell: K = 48 padded to 64, which also runs the wide-chunk
+BF16X3 shapes)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from gen import diamond_si, random_crystal
+from gen.crystals import M_SI, M_GE
+from oracle import phonons as P, anharmonic as A
+from tests.parity import TOL, gamma_error
+from tests.supercell import fold
+
+pytestmark = pytest.mark.gpu
+
+T = [200.0, 500.0]
+SHAPES = {"fp64": 4, "fp32": 4, "bf16x3": 9}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cases():
+    crystal = random_crystal(4, 3, np.random.default_rng(404)).with_grid((3, 3, 2))
+    gamma = fold(diamond_si(grid=(2, 2, 2), rc3=4.0, masses=(M_SI, M_GE), seed=17))
+    out = {}
+    for name, c in (("crystal", crystal), ("gamma", gamma)):
+        ph = P.phonons(c, velocities=False)
+        out[name] = (c, ph, A.linewidths(c, ph, T, 0.3))
+    return out
+
+
+@pytest.mark.parametrize("path", ["crystal", "gamma"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_every_tile_shape(cases, path, precision):
+    from paper_2009_01967_amd import kaldo
+    c, ph, g_ref = cases[path]
+    with kaldo.Context(0) as ctx:
+        ctx.phonons(c)
+        for v in range(SHAPES[precision]):
+            kaldo._check(ctx.h, kaldo.kaldo_set_tuning(ctx.h, kaldo.KALDO_TUNE_SHAPE0 + v))
+            g = ctx.linewidths(c, T=T, sigma_thz=0.3, precision=precision)
+            err = gamma_error(g, g_ref, ph.mask)
+            _say(f"case: {path}, {precision}, shape {v}: error {err:.3e}")
+            assert err < TOL[precision], (v, err)
