@@ -289,6 +289,27 @@ def run_batch(div=64, steps=1, warmup=1):
     return out
 
 
+def run_plain(name, precision, passes=2):
+    """One workload on the library's own stream with host outputs: the command
+    to run under rocprofv3 counters.  torch initialises the GPU first, as in
+    every other run of this file, but hands the library no stream or tensor."""
+    import torch
+    torch.cuda.init()
+    from gen import workload, WORKLOADS
+    from paper_2009_01967_amd import kaldo
+    w = WORKLOADS[name]
+    c = workload(name)
+    log(f"{name}: phonons")
+    with kaldo.Context(0) as ctx:
+        ctx.phonons(c)
+        for r in range(passes):
+            log(f"{name} {precision} pass {r}: start")
+            t0 = time.perf_counter()
+            ctx.linewidths(c, T=list(w["T"]), sigma_thz=w["sigma_thz"], precision=precision)
+            (ctx.kappa_qhgk if c.n_k == 1 else ctx.kappa_rta)()
+            log(f"{name} {precision} pass {r}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+
+
 def measured_peaks():
     """Attainable rates of the units the kernels use, from register-only MFMA /
     FMA loops and a 1 GiB streaming copy (libpeaks.so), beside the published
@@ -359,6 +380,9 @@ def main():
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
     ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
+    ap.add_argument("--plain", metavar="WORKLOAD", help="run one workload through the library alone "
+                    "(no torch; for rocprofv3 counters) with --precision, then exit")
+    ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the headline workload (prints only the MFMA workloads; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -377,6 +401,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "copies": 3}}))
+        return
+    if args.plain:
+        run_plain(args.plain, args.precision)
         return
     if args.peaks:
         import torch

@@ -26,8 +26,9 @@
 //
 // Block order: workgroups are dealt round-robin to the 8 XCDs, each with its
 // own L2.  The flat block id is remapped so that every XCD receives a
-// contiguous run of logical tiles with M fastest: tiles that share a B panel
-// run on the same XCD and read it from that XCD's L2.
+// contiguous run of logical tiles, ordered in groups of 8 row tiles with M
+// fastest inside a group: the blocks resident on one XCD at a time cover a
+// roughly square patch of tiles and read both operand panels from that XCD's L2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -129,10 +130,20 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int nb = (int)gridDim.x, b = (int)blockIdx.x;
   const int q = nb >> 3, r8 = nb & 7, x = b & 7;
   const int tile = x * q + (x < r8 ? x : r8) + (b >> 3);
-  const int mt = tile % g.m_tiles;
-  const int rest = tile / g.m_tiles;
-  const int nt = rest % g.n_tiles;
-  const int z = rest / g.n_tiles;
+  // within a batch item, tiles go in groups of GM row tiles: the blocks that
+  // run at the same time on one XCD then cover about GM x (64 / GM) tiles and
+  // share both operand panels in L2 (with M fastest over all row tiles, every
+  // N tile streams the whole A panel again from beyond L2)
+  constexpr int GM = 8;
+  const int per_z = g.m_tiles * g.n_tiles;
+  const int z = tile / per_z;
+  const int tz = tile - z * per_z;
+  const int per_group = GM * g.n_tiles;
+  const int first_m = (tz / per_group) * GM;
+  const int gm = min(g.m_tiles - first_m, GM);
+  const int tg = tz - (tz / per_group) * per_group;
+  const int mt = first_m + tg % gm;
+  const int nt = tg / gm;
 
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
