@@ -26,6 +26,9 @@
 
 namespace kaldo {
 
+// Bytes per K block of the Y operand (see GemmOps::b_kb): one 16-byte slot.
+constexpr int kYBlock = 32;
+
 // ---- X_s: contract fc3 with eta_s over the home atom ---------------------------------
 // Xs[pair][sl][beta][gamma] for sl < sbp (zero where s0 + sl >= n); pairs are the
 // distinct (j, l) atom pairs.  E is column major: eta_s[a] = E[s * n + a].
@@ -68,7 +71,10 @@ __global__ void k_transpose(R* __restrict__ Et, const double* __restrict__ E, in
 }
 
 // ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] as the GEMM's B operand ---------
-// Rows (sl, s'') of ldy elements, columns a'.  Lanes run over s'' (coalesced reads
+// Rows (sl, s''), columns a', K-blocked (GemmOps::b_kb): element (row, a') at
+// (a' / E) * bkb + row * E + a' % E with E the elements of kYBlock bytes, so
+// that the lanes (consecutive s'') of a store touch neighbouring 16-byte blocks
+// instead of rows a whole Y row apart.  Lanes run over s'' (coalesced reads
 // of Et); the SB modes of a block share every Et load.  R is FP64 for the FP64
 // path and FP32 for the mixed ones (Y then enters FP32 or BF16 hi+lo operands).  A block walks a run of
 // jc atoms j; the X_s blocks of its pairs are staged in LDS first and read as
@@ -78,7 +84,8 @@ template <int P, typename R, int SB, int JB>
 __global__ void __launch_bounds__(256)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
               const double* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
-              const int* __restrict__ pl, int n, int N, int sbp, long long ldy, int cnt, int jc, int js) {
+              const int* __restrict__ pl, int n, int N, int sbp, long long bkb, int cnt, int jc, int js) {
+  constexpr int E = kYBlock / (int)sizeof(typename Operand<P>::T);
   extern __shared__ __attribute__((aligned(16))) char xlraw[];
   // X_s blocks of the staged pairs, [pair][SB][XP]: each 3 x 3 block padded to
   // XP values (16-byte multiple) so that it is read with wave-wide ds_read_b128
@@ -137,15 +144,22 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
           if (slb + u < cnt) {
-            const size_t o = ((size_t)(slb + u) * n + s2) * ldy + 3 * (size_t)jb;
+            const size_t row = (size_t)(slb + u) * n + s2;
+            // 3 jb is even (runs start at even atoms), so each pair (a, a + 1)
+            // lies in one 16-byte block
             if (ne == 3 * JB) {
 #pragma unroll
-              for (int e = 0; e < 3 * JB; e += 2)
-                store_operand2<P>(Yhi, Ylo, o + e, (double)y[u][e], (double)y[u][e + 1]);
+              for (int e = 0; e < 3 * JB; e += 2) {
+                const size_t a = 3 * (size_t)jb + e;
+                store_operand2<P>(Yhi, Ylo, (a / E) * bkb + row * E + a % E, (double)y[u][e], (double)y[u][e + 1]);
+              }
             } else {
 #pragma unroll
               for (int e = 0; e < 3 * JB; ++e)
-                if (e < ne) store_operand<P>(Yhi, Ylo, o + e, (double)y[u][e]);
+                if (e < ne) {
+                  const size_t a = 3 * (size_t)jb + e;
+                  store_operand<P>(Yhi, Ylo, (a / E) * bkb + row * E + a % E, (double)y[u][e]);
+                }
             }
           }
         }
@@ -179,6 +193,7 @@ struct EpiGamma {
   int n, nT, s0;
   double rs;           // 1 / (scale of the delta)
   static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
+  static constexpr int kBlockBytes = kYBlock;  // B = Y is K-blocked
 
   template <int P, int FM, int FN>
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,
@@ -348,6 +363,10 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   RY* Et = reinterpret_cast<RY*>(Xs + xs);
   // operands: A [n][ld] planes, Y [sb * n][ld] planes
   const size_t a_elems = (size_t)n * ld, y_elems = (size_t)sb * n * ld;
+  // Y is K-blocked: blocks of kYBlock bytes of elements, each block column
+  // holding all sb * n rows
+  constexpr int EY = kYBlock / (int)sizeof(T);
+  const long long y_kb = (long long)sb * n * EY;
   KALDO_HIP(ctx, ctx->d_A.ensure((a_elems + y_elems) * S * sizeof(T)));
   T* Ah = ctx->d_A.as<T>();
   T* Al = S == 2 ? Ah + a_elems : nullptr;
@@ -398,7 +417,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
                          cntp);
       KALDO_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL((k_gamma_y<P, RY, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
-                         y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, (long long)ld,
+                         y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, y_kb,
                          cnt, jc, js);
     } else if ((fs = fill_zero(ctx, Yh, y_elems * S * sizeof(T))) != KALDO_OK) {
       return fs;
@@ -410,7 +429,9 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     g.a_lo = Al;
     g.b_hi = Yh;
     g.b_lo = Yl;
-    g.lda = g.ldb = ld;
+    g.lda = ld;
+    g.ldb = EY;
+    g.b_kb = y_kb;
     g.K = ld;
     g.nz = 1;
     g.m_valid = n;

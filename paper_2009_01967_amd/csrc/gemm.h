@@ -46,6 +46,9 @@ struct GemmOps {
   const void* b_lo;
   long long lda, ldb; // row strides in elements
   long long a_z, b_z; // element offsets between batch items (blockIdx -> z)
+  long long b_kb;     // K-blocked B (epilogues with kBlockBytes > 0): element (c, k)
+                      // at (k / L) * b_kb + c * L + k % L, L = kBlockBytes of
+                      // elements (ldb = L); otherwise B rows are K-contiguous
   const int* a_map;   // if set, batch item z takes A item a_map[z] (else z)
   int K;              // multiple of the chunk (128 bytes of one row)
   int m_tiles, n_tiles, nz; // filled in by the launcher from the tile shape
@@ -59,6 +62,12 @@ struct GemmChunk {
   static constexpr int CB = P == KALDO_FP64 ? 128 : 64;
   static constexpr int KC = CB / (int)sizeof(typename Operand<P>::T);
 };
+
+// An epilogue with kBlockBytes > 0 reads B in the K-blocked layout of GemmOps::b_kb.
+template <class Epi, class = void>
+struct BlockBytes : std::integral_constant<int, 0> {};
+template <class Epi>
+struct BlockBytes<Epi, std::void_t<decltype(Epi::kBlockBytes)>> : std::integral_constant<int, Epi::kBlockBytes> {};
 
 // Coordinates of one block tile, handed to the epilogue.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -154,6 +163,14 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int row0 = tid / SLOTS;
 
   // global element offsets of this thread's load slots (rows clamped to existing ones)
+  // element offset of B's k within a row (see GemmOps::b_kb); L divides the
+  // chunk, so a chunk start and a slot offset inside the chunk add without carry
+  constexpr int BKL = BlockBytes<Epi>::value / (int)sizeof(T);
+  static_assert(BKL == 0 || (KCH % BKL == 0 && BKL % EPT == 0), "B blocks must tile the chunk");
+  const auto bk = [&](int k0) -> long long {
+    if constexpr (BKL > 0) return (long long)(k0 / BKL) * g.b_kb + k0 % BKL;
+    else return (long long)k0;
+  };
   long long aoff[NA], boff[NB > 0 ? NB : 1];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
@@ -165,7 +182,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   for (int u = 0; u < NB; ++u) {
     long long row = (long long)nt * BN + row0 + RPP * u;
     row = row < g.c_valid ? row : g.c_valid - 1;
-    boff[u] = (long long)z * g.b_z + row * g.ldb + slot * EPT;
+    boff[u] = (long long)z * g.b_z + row * g.ldb + bk(slot * EPT);
   }
   const T* ap[S];
   const T* bp[S];
@@ -187,7 +204,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
       if constexpr (u_ < NA)                                                           \
         rg[s_][u_] = *reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + (K0));        \
       else                                                                             \
-        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + (K0));   \
+        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + bk(K0));  \
     });                                                                                \
   });
 #define KALDO_SSTORE(BUFI)                                                             \
@@ -220,13 +237,13 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     for (int c = 0; c < FN; ++c) {
       long long row = (long long)nt * BN + wn * 16 * FN + 16 * c + (lane & 15);
       row = row < g.c_valid ? row : g.c_valid - 1;
-      bfo[c] = (long long)z * g.b_z + row * g.ldb + 8 * grp;
+      bfo[c] = (long long)z * g.b_z + row * g.ldb + bk(8 * grp);
     }
   }
 #define KALDO_BLOAD(K0, DST)                                                                              \
   _Pragma("unroll") for (int c = 0; c < FN; ++c) {                                                      \
     _Pragma("unroll") for (int s = 0; s < 2; ++s) DST[c][s] =                                           \
-        *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + (K0));                                         \
+        *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + bk(K0));                                       \
   }
 
   const int nchunk = g.K / KCH;
