@@ -127,9 +127,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   constexpr int RB = CB == 64 ? 64 : CB + 16; // LDS bytes per tile row (see lds_off)
   constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
   constexpr int RPP = 256 / SLOTS;            // rows loaded per pass of the block
-  constexpr int NA = BM / RPP;                // passes for A
+  constexpr int NA = (BM + RPP - 1) / RPP;    // passes for A (the last one partial unless RPP divides BM)
   constexpr int NB = BD ? 0 : BN / RPP;       // passes for B (none when B is direct)
-  static_assert(NA * RPP == BM && (BD || NB * RPP == BN), "tile rows must be whole load passes");
+  static_assert(BD || NB * RPP == BN, "B tile rows must be whole load passes");
   constexpr int ROWS = BM + (BD ? 0 : BN);
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
@@ -213,7 +213,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
     static_for<NA + NB>([&](auto uc) __attribute__((always_inline)) {                                                 \
       constexpr int u_ = decltype(uc)::value;                                          \
       const int row = (u_ < NA ? 0 : BM - RPP * NA) + row0 + RPP * u_;                 \
-      *reinterpret_cast<u32x4*>(lds + (BUFI) * BUF + lds_off<CB>(s_ * ROWS + row, slot)) = rg[s_][u_]; \
+      if (u_ + 1 != NA || BM % RPP == 0 || row < BM)  /* rows of a partial last A pass */ \
+        *reinterpret_cast<u32x4*>(lds + (BUFI) * BUF + lds_off<CB>(s_ * ROWS + row, slot)) = rg[s_][u_]; \
     });                                                                                \
   });
 
@@ -422,12 +423,13 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
 // 128 x 256 block tile (64 x 128 per wavefront: twice the MFMA work per LDS
 // fragment read and half the A-panel re-reads), and 7 and 8, the tiles of 0
 // and 1 with wide chunks (WC; they fall back to 0 and 1 when K is not a
-// multiple of 64).
-constexpr int kGemmVariantsMax = 9;
+// multiple of 64).  BF16X3 9 and FP32 4 are 96 x 128 block tiles, whose 96
+// rows fit M = 276 (a 46-atom cell, realified) in three tiles with 4 % padding.
+constexpr int kGemmVariantsMax = 10;
 
 template <int P>
 inline int gemm_variants() {
-  return P == KALDO_BF16X3 ? 9 : 4;
+  return P == KALDO_BF16X3 ? 10 : (P == KALDO_FP32 ? 5 : 4);
 }
 
 // An epilogue with kAllShapes = false is instantiated with the first tile shape
@@ -445,6 +447,8 @@ inline int gemm_variants() {
 template <int P>
 inline int gemm_fm(int v) {
   if (P == KALDO_FP64) return v == 1 ? 4 : (v == 3 ? 3 : 2);
+  if (P == KALDO_FP32 && v == 4) return 3;
+  if (P == KALDO_BF16X3 && v == 9) return 3;
   return v == 1 || v == 3 || v == 5 || v == 8 ? 2 : 4;
 }
 
@@ -477,7 +481,8 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
     else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
     else if (v == 2) gemm_launch_tile<P, 4, 2>(g, e, st);
-    else gemm_launch_tile<P, 2, 2>(g, e, st);
+    else if (v == 3) gemm_launch_tile<P, 2, 2>(g, e, st);
+    else gemm_launch_tile<P, 3, 4>(g, e, st);
   } else {
     if (v == 0) gemm_launch_tile<P, 4, 4>(g, e, st);
     else if (v == 1) gemm_launch_tile<P, 2, 4>(g, e, st);
@@ -489,6 +494,7 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     else if (v == 7) gemm_launch_tile<P, 4, 4>(g, e, st);
     else if (v == 8 && g.K % 64 == 0) gemm_launch_tile<P, 2, 4, Epi, false, true>(g, e, st);
     else if (v == 8) gemm_launch_tile<P, 2, 4>(g, e, st);
+    else if (v == 9) gemm_launch_tile<P, 3, 4>(g, e, st);
     else gemm_launch_tile<P, 4, 8>(g, e, st);
   }
 }

@@ -18,7 +18,7 @@ from tests.supercell import fold
 pytestmark = pytest.mark.gpu
 
 T = [200.0, 500.0]
-SHAPES = {"fp64": 4, "fp32": 4, "bf16x3": 9}
+SHAPES = {"fp64": 4, "fp32": 5, "bf16x3": 10}
 
 
 def _say(*a):
