@@ -206,6 +206,40 @@ struct EpiCrystal {
   int n, nk, nT, k, p0, m_tiles;
   double rs;                    // 1 / (scale of the delta)
   static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
+  static constexpr bool kSkipEmpty = DK != KALDO_DELTA_LORENTZ;  // the Lorentzian has no cut
+
+  // Every element of block tile (mt, nt) of partner z beyond the delta's cut:
+  // frequencies ascend with the mode index at every grid point, rows hold the
+  // (Re, Im) pairs of modes s' in [mt BM / 2, (mt + 1) BM / 2), columns (s, s'').
+  template <int P, int FM, int FN>
+  __device__ bool tile_empty(int mt, int nt, int z) const {
+    constexpr int BM = 32 * FM, BN = 32 * FN;
+    const int m0 = mt * BM / 2;
+    if (m0 >= n) return true;
+    const int p = p0 + z, kk = kmap[z];
+    const double a = OM[(size_t)m0 * nk + p] * rs, b = OM[(size_t)(min(n, m0 + BM / 2) - 1) * nk + p] * rs;
+    const double W = sqrt(delta_cut<P>(DK)) * (1.0 + 1e-9) + 1e-9;
+    const long long c1 = min(ncol, (long long)nt * BN + BN) - 1;
+    for (long long c = (long long)nt * BN; c <= c1;) {
+      const int s = (int)(c / n);
+      const long long ce = min(c1, (long long)(s + 1) * n - 1);
+      const double ws = OM[(size_t)s * nk + k] * rs;
+      const double lo = OM[(size_t)(c - (long long)s * n) * nk + kk] * rs;
+      const double hi = OM[(size_t)(ce - (long long)s * n) * nk + kk] * rs;
+      if (ws - hi + a < W && ws - lo + b > -W) return false;  // w + w' - w''
+      if (ws - hi - b < W && ws - lo - a > -W) return false;  // w - w' - w''
+      c = ce + 1;
+    }
+    return true;
+  }
+  template <int P, int FM, int FN>
+  __device__ void clear_tile(int mt, int nt, int z) const {
+    const long long first = (long long)nt * 32 * FN;
+    for (int i = threadIdx.x; i < 32 * FN * nT; i += blockDim.x) {
+      const int col = i / nT, t = i % nT;
+      if (first + col < ncol) partial[(((size_t)z * m_tiles + mt) * ncol + first + col) * nT + t] = 0.0;
+    }
+  }
 
   template <int P, int FM, int FN>
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,

@@ -194,6 +194,38 @@ struct EpiGamma {
   double rs;           // 1 / (scale of the delta)
   static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
   static constexpr int kBlockBytes = kYBlock;  // B = Y is K-blocked
+  static constexpr bool kSkipEmpty = DK != KALDO_DELTA_LORENTZ;  // the Lorentzian has no cut
+
+  // Every element of block tile (mt, nt) beyond the delta's cut: frequencies
+  // ascend with the mode index, so the mismatches w -+ w' - w'' over the tile
+  // span intervals given by its corner modes (widened by a rounding margin).
+  template <int P, int FM, int FN>
+  __device__ bool tile_empty(int mt, int nt, int) const {
+    constexpr int BM = 32 * FM, BN = 32 * FN;
+    const int r0 = mt * BM;
+    if (r0 >= n) return true;  // padding rows only
+    const double a = OM[r0] * rs, b = OM[min(n, r0 + BM) - 1] * rs;  // w' range
+    const double W = sqrt(delta_cut<P>(DK)) * (1.0 + 1e-9) + 1e-9;
+    const long long c1 = min(ncol, (long long)nt * BN + BN) - 1;
+    for (long long c = (long long)nt * BN; c <= c1;) {
+      const int sl = (int)(c / n);
+      const long long ce = min(c1, (long long)(sl + 1) * n - 1);
+      const double ws = OM[s0 + sl] * rs;
+      const double lo = OM[(int)(c - (long long)sl * n)] * rs, hi = OM[(int)(ce - (long long)sl * n)] * rs;
+      if (ws - hi + a < W && ws - lo + b > -W) return false;  // w + w' - w''
+      if (ws - hi - b < W && ws - lo - a > -W) return false;  // w - w' - w''
+      c = ce + 1;
+    }
+    return true;
+  }
+  template <int P, int FM, int FN>
+  __device__ void clear_tile(int mt, int nt, int) const {
+    const long long first = (long long)nt * 32 * FN;
+    for (int i = threadIdx.x; i < 32 * FN * nT; i += blockDim.x) {
+      const int col = i / nT, t = i % nT;
+      if (first + col < ncol) partial[((size_t)mt * ncol + first + col) * nT + t] = 0.0;
+    }
+  }
 
   template <int P, int FM, int FN>
   __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at,

@@ -69,6 +69,15 @@ struct BlockBytes : std::integral_constant<int, 0> {};
 template <class Epi>
 struct BlockBytes<Epi, std::void_t<decltype(Epi::kBlockBytes)>> : std::integral_constant<int, Epi::kBlockBytes> {};
 
+// An epilogue with kSkipEmpty = true provides tile_empty<P, FM, FN>(mt, nt, z),
+// true when it would discard every output of block tile (mt, nt, z), and
+// clear_tile<P, FM, FN>(mt, nt, z), which writes what it would have written for
+// such a tile; the core then skips the tile's loads and MFMAs.
+template <class Epi, class = void>
+struct SkipEmpty : std::false_type {};
+template <class Epi>
+struct SkipEmpty<Epi, std::void_t<decltype(Epi::kSkipEmpty)>> : std::integral_constant<bool, Epi::kSkipEmpty> {};
+
 // Coordinates of one block tile, handed to the epilogue.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -153,6 +162,13 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int tg = tz - (tz / per_group) * per_group;
   const int mt = first_m + tg % gm;
   const int nt = tg / gm;
+  if constexpr (SkipEmpty<Epi>::value) {
+    // uniform across the block (block indices and operand-independent data only)
+    if (epi.template tile_empty<P, FM, FN>(mt, nt, z)) {
+      epi.template clear_tile<P, FM, FN>(mt, nt, z);
+      return;
+    }
+  }
 
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
