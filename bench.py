@@ -188,8 +188,10 @@ def run_mfma(name, steps, warmup):
             tot, cnt = kaldo.kaldo_profile_read(ctx.h, kname)
             if cnt:
                 kern[kname] = {"ms_per_step": tot / steps, "launches_per_step": cnt / steps}
+        ex, dense = kaldo.kaldo_profile_flops(ctx.h)
         kaldo.kaldo_profile_enable(ctx.h, False)
-        res[label] = dict(ms=ms, kern=kern, g=g_d.cpu().numpy().copy(), k=k_d.cpu().numpy().copy())
+        res[label] = dict(ms=ms, kern=kern, ex=ex / steps, dense=dense / steps,
+                          g=g_d.cpu().numpy().copy(), k=k_d.cpu().numpy().copy())
         log(f"{name} {label}: {ms:.2f} ms/step, kernels {kern}")
     ctx.close()
     lw = nk * n * len(T)
@@ -208,12 +210,19 @@ def run_mfma(name, steps, warmup):
         ent = {"ms_per_step": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
                "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in res[label]["kern"].items()}}
         if proj:
-            # BF16X3 executes three bf16 products per real product
-            executed = f_c * (3.0 if label == "bf16x3" else 1.0)
+            # Matrix-core flops of the block tiles that ran (the library's tally),
+            # and of all tiles launched: tiles whose outputs all lie beyond the
+            # delta cut are skipped.  BF16X3 issues three bf16 products per
+            # FP32-accurate product, so its peak is a third of the bf16 one.
+            mult = 3.0 if label == "bf16x3" else 1.0
+            ex, dense = res[label]["ex"], res[label]["dense"]
+            sec = proj * 1e-3
             ent["roofline"] = {"bound": "mfma", "kernel": "k_gemm (projection GEMMs, fused epilogue)",
-                               "achieved": f_c / (proj * 1e-3) / 1e12, "executed": executed / (proj * 1e-3) / 1e12,
-                               "peak": peak / 1e12, "unit": "TFLOP/s",
-                               "frac": executed / (proj * 1e-3) / peak, "traffic": None}
+                               "achieved": ex / mult / sec / 1e12, "peak": peak / mult / 1e12, "unit": "TFLOP/s",
+                               "frac": ex / sec / peak, "traffic": None,
+                               "mfma_tflops_issued": ex / sec / 1e12,
+                               "tiles_skipped_frac": 1.0 - ex / dense if dense else 0.0,
+                               "dense_equivalent_tflops": f_c / sec / 1e12}
         out[label] = ent
     out["speedup_bf16x3_vs_fp64"] = res["fp64"]["ms"] / res["bf16x3"]["ms"]
     return out

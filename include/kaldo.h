@@ -275,14 +275,25 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
 /* Kernel timing instrumentation (not a step of the method).  While enabled,
  * the library records a pair of HIP events on the context's stream around
  * every launch of its main kernels, named
- *   "dyn_assemble", "eigensolve", "step_a", "project", "finalize",
- *   "kappa_rta", "kappa_qhgk".
- * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables.
+ *   "dyn_assemble", "eigensolve", "step_a", "step_b", "gamma_sparse",
+ *   "project", "finalize", "kappa_rta", "kappa_qhgk", and "batch_graph"
+ *   around a kaldo_batch_run graph launch.
+ * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables
+ * and clears them.
  * kaldo_profile_read synchronises the stream and returns, for one kernel
  * name, the summed duration (ms) and the number of launches since enabling;
- * an unknown name gives 0 and 0. */
+ * an unknown name gives 0 and 0.
+ * kaldo_profile_flops synchronises the stream and returns the matrix-core
+ * flops of the projection GEMMs ("project" of the many-branch and Gamma-point
+ * paths) since enabling: `executed` counts the block tiles that ran (BF16X3
+ * counts its three bf16 products), `dense` every tile launched, including the
+ * tiles skipped because all their outputs lie beyond the delta cut.  The
+ * few-branch kernel and captured batch graphs are not counted.  Either
+ * pointer may be NULL.  Enabling allocates the 8-byte device counter with
+ * hipMalloc, outside any workspace set by kaldo_set_workspace. */
 kaldo_status kaldo_profile_enable(kaldo_ctx ctx, int enable);
 kaldo_status kaldo_profile_read(kaldo_ctx ctx, const char* kernel, double* total_ms, int64_t* launches);
+kaldo_status kaldo_profile_flops(kaldo_ctx ctx, double* executed, double* dense);
 
 #ifdef __cplusplus
 }

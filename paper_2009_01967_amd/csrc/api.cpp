@@ -65,6 +65,7 @@ void prof_clear(kaldo_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   prof_collect(ctx);
   ctx->prof_tab.clear();
+  ctx->prof_dense = 0.0;
 }
 
 int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const std::function<void(int)>& launch) {
@@ -723,6 +724,11 @@ kaldo_status kaldo_profile_enable(kaldo_ctx ctx, int enable) {
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   prof_clear(ctx);
   ctx->prof = enable != 0;
+  if (ctx->prof) KALDO_HIP(ctx, ctx->d_prof_flops.ensure(sizeof(unsigned long long)));
+  if (ctx->d_prof_flops.p) {
+    KALDO_HIP(ctx, hipMemsetAsync(ctx->d_prof_flops.p, 0, sizeof(unsigned long long), ctx->stream));
+    KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   return KALDO_OK;
 }
 
@@ -734,6 +740,19 @@ kaldo_status kaldo_profile_read(kaldo_ctx ctx, const char* kernel, double* total
   auto it = ctx->prof_tab.find(kernel);
   if (total_ms) *total_ms = it == ctx->prof_tab.end() ? 0.0 : it->second.total_ms;
   if (launches) *launches = it == ctx->prof_tab.end() ? 0 : it->second.launches;
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_profile_flops(kaldo_ctx ctx, double* executed, double* dense) {
+  if (!ctx) return KALDO_EINVAL;
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  unsigned long long run = 0;
+  if (ctx->d_prof_flops.p) {
+    KALDO_HIP(ctx, hipMemcpyAsync(&run, ctx->d_prof_flops.p, sizeof(run), hipMemcpyDeviceToHost, ctx->stream));
+    KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  if (executed) *executed = (double)run;
+  if (dense) *dense = ctx->prof_dense;
   return KALDO_OK;
 }
 

@@ -505,6 +505,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       gemm_launch<P>(w, g2, e2, st);                                                                            \
     });                                                                                                         \
     e2.m_tiles = gemm_m_tiles<P>(vt, mrows);                                                                    \
+    prof_tally(ctx, g2);                                                                                        \
     if (!plan) gemm_launch<P>(vt, g2, e2, st);                                                                  \
     v = vt;                                                                                                     \
   }

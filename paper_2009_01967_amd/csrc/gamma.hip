@@ -353,7 +353,11 @@ template <int P, class Epi>
 static int gemm_lw(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
   const int v = autotune(ctx, key, gemm_variants<P, Epi>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
-  if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
+  if (!planning(ctx)) {
+    GemmOps gt = g;
+    prof_tally(ctx, gt);
+    gemm_launch<P>(v, gt, e, st);
+  }
   return v;
 }
 
@@ -468,6 +472,10 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     g.nz = 1;
     g.m_valid = n;
     g.c_valid = (long long)cnt * n;
+    // With a cut delta most tiles of a column are skipped and the rest form
+    // bands: all row tiles of a column go together, so that its B panel is
+    // read once by the few tiles that run.
+    g.group_m = ctx->delta == KALDO_DELTA_LORENTZ ? 8 : 1 << 20;
     const std::string key = "gamma/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt) +
                             "/" + std::to_string(nT) + "/" + std::to_string(ctx->delta);
     int v = 0;

@@ -35,6 +35,7 @@
 
 #include <utility>
 
+#include "internal.h"
 #include "mfma.h"
 
 namespace kaldo {
@@ -54,6 +55,14 @@ struct GemmOps {
   int m_tiles, n_tiles, nz; // filled in by the launcher from the tile shape
   int m_valid;        // rows of A (= output rows); loads beyond are clamped
   long long c_valid;  // rows of B (= output columns) per batch item
+  // Flop tally of timed runs (null otherwise): each block tile that runs adds
+  // tile_flops (its MFMA flops, filled in by the launcher) to *tally; the
+  // launcher adds the flops of every tile it launches, run or skipped, to the
+  // host value *tally_dense.
+  unsigned long long* tally;
+  double* tally_dense;
+  unsigned long long tile_flops;
+  int group_m;        // row tiles per group of the tile order (0: 8; clamped to m_tiles)
 };
 
 // Bytes of one row per K chunk, and the chunk in elements.
@@ -148,11 +157,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int nb = (int)gridDim.x, b = (int)blockIdx.x;
   const int q = nb >> 3, r8 = nb & 7, x = b & 7;
   const int tile = x * q + (x < r8 ? x : r8) + (b >> 3);
-  // within a batch item, tiles go in groups of GM row tiles: the blocks that
-  // run at the same time on one XCD then cover about GM x (64 / GM) tiles and
-  // share both operand panels in L2 (with M fastest over all row tiles, every
-  // N tile streams the whole A panel again from beyond L2)
-  constexpr int GM = 8;
+  // within a batch item, tiles go in groups of GM row tiles (group_m, 8 by
+  // default), M fastest inside a group: the blocks that run at the same time
+  // on one XCD then cover about GM x (64 / GM) tiles and share both operand
+  // panels in L2 (with M fastest over all row tiles, every N tile streams the
+  // whole A panel again from beyond L2)
+  const int GM = g.group_m;
   const int per_z = g.m_tiles * g.n_tiles;
   const int z = tile / per_z;
   const int tz = tile - z * per_z;
@@ -169,6 +179,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
       return;
     }
   }
+  if (g.tally && threadIdx.x == 0) atomicAdd(g.tally, g.tile_flops);
 
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -478,7 +489,11 @@ template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
 inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
   g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
+  g.group_m = g.group_m <= 0 ? 8 : (g.group_m < g.m_tiles ? g.group_m : g.m_tiles);
   const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
+  // BF16X3 issues three bf16 products per element product
+  g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)g.K * (P == KALDO_BF16X3 ? 3 : 1);
+  if (g.tally_dense) *g.tally_dense += (double)g.tile_flops * (double)blocks;
   hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi, BD, WC>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
 }
 
@@ -513,6 +528,14 @@ inline void gemm_launch(int v, const GemmOps& g, const Epi& e, hipStream_t st) {
     else if (v == 9) gemm_launch_tile<P, 3, 4>(g, e, st);
     else gemm_launch_tile<P, 4, 8>(g, e, st);
   }
+}
+
+// Attach the context's flop tally to the operands of a projection GEMM launch
+// when kernel timing is on (kaldo_profile_enable) and the launch is not captured.
+inline void prof_tally(kaldo_ctx ctx, GemmOps& g) {
+  if (!ctx->prof || ctx->mode != kRun || !ctx->d_prof_flops.p) return;
+  g.tally = ctx->d_prof_flops.as<unsigned long long>();
+  g.tally_dense = &ctx->prof_dense;
 }
 
 }  // namespace kaldo

@@ -137,6 +137,8 @@ struct kaldo_ctx_s {
   };
   std::map<std::string, ProfEntry> prof_tab;
   hipEvent_t prof_open = nullptr;
+  kaldo::DevBuf d_prof_flops;        // unsigned long long: MFMA flops of the projection tiles that ran
+  double prof_dense = 0.0;           // MFMA flops of every projection tile launched
 
   // tile shapes chosen by the autotuner, per problem key (kept by tune_owner
   // when set: the crystals of a batch share their parent's choices)

@@ -47,7 +47,7 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
-            "kaldo_set_workspace"]
+            "kaldo_set_workspace", "kaldo_profile_flops"]
 
 
 class kaldo_structure(C.Structure):
@@ -122,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_profile_enable.restype = C.c_int
     lib.kaldo_profile_read.argtypes = [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.kaldo_profile_read.restype = C.c_int
+    lib.kaldo_profile_flops.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.kaldo_profile_flops.restype = C.c_int
     _lib = lib
     return lib
 
@@ -294,6 +296,14 @@ def kaldo_profile_read(ctx, kernel: str):
     st = load_library().kaldo_profile_read(ctx, kernel.encode(), C.byref(ms), C.byref(n))
     _check(ctx, st)
     return ms.value, n.value
+
+
+def kaldo_profile_flops(ctx):
+    """(executed, dense) projection-GEMM matrix-core flops since profiling was enabled."""
+    ex = C.c_double(0.0)
+    dn = C.c_double(0.0)
+    _check(ctx, load_library().kaldo_profile_flops(ctx, C.byref(ex), C.byref(dn)))
+    return ex.value, dn.value
 
 
 # ---- convenience context ---------------------------------------------------------
