@@ -71,99 +71,120 @@ __global__ void k_transpose(R* __restrict__ Et, const double* __restrict__ E, in
 }
 
 // ---- Y_s^T[s''][a'] = sum_a'' X_s[a'][a''] E[a''][s''] as the GEMM's B operand ---------
-// Rows (sl, s''), columns a', K-blocked (GemmOps::b_kb): element (row, a') at
-// (a' / E) * bkb + row * E + a' % E with E the elements of kYBlock bytes, so
-// that the lanes (consecutive s'') of a store touch neighbouring 16-byte blocks
-// instead of rows a whole Y row apart.  Lanes run over s'' (coalesced reads
-// of Et); the SB modes of a block share every Et load.  R is FP64 for the FP64
-// path and FP32 for the mixed ones (Y then enters FP32 or BF16 hi+lo operands).  A block walks a run of
-// jc atoms j; the X_s blocks of its pairs are staged in LDS first and read as
-// wave-wide broadcasts.  Rows of JB atoms are accumulated together so each lane
-// writes 3 JB contiguous elements.
-template <int P, typename R, int SB, int JB>
-__global__ void __launch_bounds__(256)
+// For one atom j and 16 first modes u this is a small dense product on the
+// matrix cores: C_alpha[u][s''] = sum_k A_alpha[u][k] B[k][s''] with k = (pair
+// (j, l), gamma) running over the 3 P_j components of the atoms l paired with j,
+// A_alpha[u][(l, gamma)] = X_s(u)[j alpha][l gamma] and B[(l, gamma)][s''] =
+// E[l gamma][s''] (rows of Et, read straight from global memory into the B
+// fragments: each lane one value, 16 consecutive s'' per k).  The block stages
+// A of the atom in LDS as [k][alpha][u] (zero past the last k), with the Et row
+// offset of every k; each of its W waves covers 16 columns s''.  R is FP64
+// (f64 16x16x4) for the FP64 path and FP32 (f32 16x16x4) for the mixed ones
+// (Y then enters FP32 or BF16 hi + lo operands).
+// Y rows (sl, s''), columns a', K-blocked (GemmOps::b_kb): element (row, a') at
+// (a' / E) * bkb + row * E + a' % E with E the elements of kYBlock bytes.  A
+// block takes a run of E atoms: its lanes hold all 3 E elements a' of their
+// rows, three whole K blocks, and store each with full 16-byte writes (the 16
+// lanes of a row group cover 16 neighbouring blocks).  LDS: kmax * (48 *
+// sizeof(R) + 4) bytes, kmax = 3 * (most pairs of one atom) rounded up to 4.
+template <int P, typename R, int W>
+__global__ void __launch_bounds__(64 * W)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
               const double* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
-              const int* __restrict__ pl, int n, int N, int sbp, long long bkb, int cnt, int jc, int js) {
-  constexpr int E = kYBlock / (int)sizeof(typename Operand<P>::T);
-  extern __shared__ __attribute__((aligned(16))) char xlraw[];
-  // X_s blocks of the staged pairs, [pair][SB][XP]: each 3 x 3 block padded to
-  // XP values (16-byte multiple) so that it is read with wave-wide ds_read_b128
-  constexpr int XP = sizeof(R) == 4 ? 12 : 10;
-  R* xl = reinterpret_cast<R*>(xlraw);
-  const int s2 = blockIdx.x * 256 + threadIdx.x;
-  const int slb = blockIdx.y * SB;
-  const int jbeg = blockIdx.z * jc;
-  const int jend = min(N, jbeg + jc);
-  const bool live = s2 < n;
-  const int s2c = live ? s2 : n - 1;
-  // the block walks jc atoms in sub-runs of js, staging the X_s blocks of each
-  // sub-run in LDS; one lane writes a long contiguous run of its row
-  for (int j0 = jbeg; j0 < jend; j0 += js) {
-    const int j1 = min(jend, j0 + js);
-    const int pb0 = rstart[j0], pb1 = rstart[j1];
-    __syncthreads();  // the previous sub-run is done with the staged blocks
-    for (int i = threadIdx.x; i < (pb1 - pb0) * SB * 9; i += 256) {
-      const int pp = i / (SB * 9), r = i % (SB * 9), u = r / 9;
-      xl[((size_t)pp * SB + u) * XP + r % 9] = (R)Xs[((size_t)(pb0 + pp) * sbp + slb) * 9 + r];
+              const int* __restrict__ pl, int n, int N, int sbp, long long bkb, int cnt, int kmax) {
+  using T = typename Operand<P>::T;
+  using Acc = typename std::conditional<std::is_same<R, double>::value, f64x4, f32x4>::type;
+  constexpr int E = kYBlock / (int)sizeof(T);  // atoms per block: 3 E elements = 3 K blocks
+  constexpr int V = 16 / (int)sizeof(T);        // elements per 16-byte store
+  constexpr int KS = sizeof(R) == 8 ? 8 : 16;   // k steps whose B loads are in flight together
+  extern __shared__ __attribute__((aligned(16))) char ylds[];
+  R* As = reinterpret_cast<R*>(ylds);                                      // [kmax][3][16]
+  int* Ko = reinterpret_cast<int*>(ylds + (size_t)kmax * 48 * sizeof(R));  // [kmax]
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int s2 = ((int)blockIdx.x * W + wave) * 16 + li;
+  const bool active = ((int)blockIdx.x * W + wave) * 16 < n;  // waves past the last column only stage
+  const int s2c = min(s2, n - 1);
+  const int slb = (int)blockIdx.y * 16;
+  const int jb = (int)blockIdx.z * E;
+  const int jend = min(N, jb + E);
+  Acc acc[E][3];
+#pragma unroll
+  for (int jj = 0; jj < E; ++jj)
+#pragma unroll
+    for (int al = 0; al < 3; ++al) acc[jj][al] = Acc{};
+#pragma unroll
+  for (int jj = 0; jj < E; ++jj) {
+    const int j = jb + jj;
+    if (j >= jend) break;  // uniform across the block
+    const int p0 = rstart[j];
+    const int np = rstart[j + 1] - p0;
+    const int kj = 3 * np, kjp = (kj + 3) & ~3;
+    __syncthreads();  // the previous atom is done with the staged values
+    // X_s blocks of the pairs: 16 modes x 9 values contiguous per pair
+    for (int i = tid; i < np * 144; i += 64 * W) {
+      const int q = i / 144, w = i - q * 144;
+      const int u = w / 9, e9 = w - u * 9;
+      const int al = e9 / 3, g = e9 - al * 3;
+      As[((3 * q + g) * 3 + al) * 16 + u] = (R)Xs[((size_t)(p0 + q) * sbp + slb) * 9 + w];
     }
+    for (int i = kj * 48 + tid; i < kjp * 48; i += 64 * W) As[i] = (R)0;
+    for (int k = tid; k < kjp; k += 64 * W) Ko[k] = k < kj ? (3 * pl[p0 + k / 3] + k % 3) * n : 0;
     __syncthreads();
-    for (int jb = j0; jb < j1; jb += JB) {
-      R y[SB][3 * JB];
+    if (active) {
+      // KS k steps at a time: all their Et loads are issued before the first MFMA
+      for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
+        R bv[KS];
 #pragma unroll
-      for (int u = 0; u < SB; ++u)
+        for (int q = 0; q < KS; ++q)
+          bv[q] = k0 + 4 * q < kjp ? Et[Ko[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
 #pragma unroll
-        for (int e = 0; e < 3 * JB; ++e) y[u][e] = (R)0;
-#pragma unroll
-      for (int jj = 0; jj < JB; ++jj) {
-        const int j = jb + jj;
-        if (j >= j1) break;
-        const int p1 = rstart[j + 1];
-        for (int p = rstart[j]; p < p1; ++p) {
-          const size_t l3 = 3 * (size_t)pl[p];
-          const R e0 = Et[l3 * n + s2c], e1 = Et[(l3 + 1) * n + s2c], e2 = Et[(l3 + 2) * n + s2c];
-          const R* x = xl + (size_t)(p - pb0) * SB * XP;
-#pragma unroll
-          for (int u = 0; u < SB; ++u) {
-            // the padded block as XP / (16 / sizeof(R)) 16-byte reads
-            R xu[XP];
-            const uint4* src = reinterpret_cast<const uint4*>(x + XP * u);
-#pragma unroll
-            for (int q = 0; q < XP * (int)sizeof(R) / 16; ++q) {
-              const uint4 v = src[q];
-              __builtin_memcpy(&xu[q * 16 / sizeof(R)], &v, 16);
-            }
-            y[u][3 * jj + 0] += xu[0] * e0 + xu[1] * e1 + xu[2] * e2;
-            y[u][3 * jj + 1] += xu[3] * e0 + xu[4] * e1 + xu[5] * e2;
-            y[u][3 * jj + 2] += xu[6] * e0 + xu[7] * e1 + xu[8] * e2;
+        for (int q = 0; q < KS; ++q) {
+          if (k0 + 4 * q >= kjp) break;
+          const int k = k0 + 4 * q + lk;
+          const R a0 = As[(k * 3 + 0) * 16 + li], a1 = As[(k * 3 + 1) * 16 + li], a2 = As[(k * 3 + 2) * 16 + li];
+          if constexpr (std::is_same<R, double>::value) {
+            acc[jj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[q], acc[jj][0], 0, 0, 0);
+            acc[jj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[q], acc[jj][1], 0, 0, 0);
+            acc[jj][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[q], acc[jj][2], 0, 0, 0);
+          } else {
+            acc[jj][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv[q], acc[jj][0], 0, 0, 0);
+            acc[jj][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv[q], acc[jj][1], 0, 0, 0);
+            acc[jj][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bv[q], acc[jj][2], 0, 0, 0);
           }
         }
       }
-      if (live) {
-        const int ne = 3 * min(JB, j1 - jb);  // elements of this run
+    }
+  }
+  if (!active || s2 >= n) return;
+  // lane: column s2, rows u = acc_row(lane, r); local element e = 3 jj + alpha
+  // of a' = 3 jb + e (3 jb is a multiple of E: the three K blocks of the run)
+  const int ne = 3 * (jend - jb);
+  const size_t kb0 = (size_t)(3 * jb / E);
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-          if (slb + u < cnt) {
-            const size_t row = (size_t)(slb + u) * n + s2;
-            // 3 jb is even (runs start at even atoms), so each pair (a, a + 1)
-            // lies in one 16-byte block
-            if (ne == 3 * JB) {
+  for (int r = 0; r < 4; ++r) {
+    const int u = acc_row<P == KALDO_FP64 ? KALDO_FP64 : KALDO_FP32>(lane, r);
+    if (slb + u >= cnt) continue;
+    const size_t row = (size_t)(slb + u) * n + s2;
+    if (ne == 3 * E) {
 #pragma unroll
-              for (int e = 0; e < 3 * JB; e += 2) {
-                const size_t a = 3 * (size_t)jb + e;
-                store_operand2<P>(Yhi, Ylo, (a / E) * bkb + row * E + a % E, (double)y[u][e], (double)y[u][e + 1]);
-              }
-            } else {
+      for (int m = 0; m < 3; ++m)
 #pragma unroll
-              for (int e = 0; e < 3 * JB; ++e)
-                if (e < ne) {
-                  const size_t a = 3 * (size_t)jb + e;
-                  store_operand<P>(Yhi, Ylo, (a / E) * bkb + row * E + a % E, (double)y[u][e]);
-                }
-            }
+        for (int h = 0; h < E; h += V) {
+          double v[V];
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            const int e = m * E + h + q;
+            v[q] = (double)acc[e / 3][e % 3][r];
           }
+          store_operand_vec<P>(Yhi, Ylo, (kb0 + m) * bkb + row * E + h, v);
         }
-      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 3 * E; ++e)
+        if (e < ne)
+          store_operand<P>(Yhi, Ylo, (kb0 + e / E) * bkb + row * E + e % E, (double)acc[e / 3][e % 3][r]);
     }
   }
 }
@@ -365,9 +386,9 @@ template <int P>
 static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   using T = typename Operand<P>::T;
   constexpr int S = Operand<P>::split;
-  // sparse step: FP64 for the FP64 path, FP32 with 16 first modes per E load otherwise
+  // sparse step: FP64 for the FP64 path, FP32 otherwise; 16 first modes per block
   using RY = typename std::conditional<P == KALDO_FP64, double, float>::type;
-  constexpr int SB = P == KALDO_FP64 ? 8 : 16;
+  constexpr int SB = 16;
   const int N = ctx->n_atoms, n = ctx->nm, nT = ctx->nT;
   const int KC = GemmChunk<P>::KC;
   const int ld = (n + KC - 1) / KC * KC;  // K padded to whole chunks
@@ -424,21 +445,12 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   double dscale, dnorm;
   delta_scale(ctx->delta, sig, dscale, dnorm);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit * dnorm;
-  // atoms per block jc, staged in sub-runs of js atoms (multiples of JB) whose
-  // X_s blocks must fit in 64 KB of LDS.  Short runs (one sub-run per block)
-  // measured fastest: runs of 32 atoms halved the speed (fewer blocks in flight).
-  constexpr int JB = 2;
-  int js = 4;
-  size_t y_lds = 0;
-  for (;; js -= JB) {
-    int max_pairs = 1;
-    for (int j0 = 0; j0 < N; j0 += js)
-      max_pairs = std::max(max_pairs, L.grow_start[std::min(N, j0 + js)] - L.grow_start[j0]);
-    y_lds = (size_t)max_pairs * SB * (sizeof(RY) == 4 ? 12 : 10) * sizeof(RY);
-    if (y_lds <= 64 * 1024) break;
-    if (js == JB) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
-  }
-  const int jc = js;
+  int max_pairs = 1;
+  if ((int)L.grow_start.size() == N + 1)
+    for (int j = 0; j < N; ++j) max_pairs = std::max(max_pairs, L.grow_start[j + 1] - L.grow_start[j]);
+  const int kmax = (3 * max_pairs + 3) & ~3;
+  const size_t y_lds = (size_t)kmax * (48 * sizeof(RY) + sizeof(int));
+  if (y_lds > 64 * 1024) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
   for (int b = 0; b < nbatch; ++b) {
     // planning visits the batches whose GEMM shapes differ: the first and the last
     if (planning(ctx) && b != 0 && b != nbatch - 1) continue;
@@ -452,9 +464,23 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
                          L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
                          cntp);
       KALDO_HIP(ctx, hipGetLastError());
-      hipLaunchKernelGGL((k_gamma_y<P, RY, SB, JB>), dim3((n + 255) / 256, cntp / SB, (N + jc - 1) / jc), dim3(256),
-                         y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, cntp, y_kb,
-                         cnt, jc, js);
+      // waves per block (16 columns s'' each, sharing the staged X_s values):
+      // 8, 4 or 2, tuned per problem; smaller blocks overlap one block's staging
+      // with another's MFMAs on the same CU, larger ones stage less
+      auto ylaunch = [&](int w) {
+        const dim3 grid_yz(0, cntp / SB, (N + EY - 1) / EY);
+        auto go = [&](auto wc) {
+          constexpr int W = decltype(wc)::value;
+          hipLaunchKernelGGL((k_gamma_y<P, RY, W>), dim3((n + 16 * W - 1) / (16 * W), grid_yz.y, grid_yz.z),
+                             dim3(64 * W), y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(),
+                             L.d_gpair_l.as<int>(), n, N, cntp, y_kb, cnt, kmax);
+        };
+        if (w == 0) go(std::integral_constant<int, 8>{});
+        else if (w == 1) go(std::integral_constant<int, 4>{});
+        else go(std::integral_constant<int, 2>{});
+      };
+      const std::string ykey = "gy/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt);
+      ylaunch(autotune(ctx, ykey, 3, 0, ylaunch));
     } else if ((fs = fill_zero(ctx, Yh, y_elems * S * sizeof(T))) != KALDO_OK) {
       return fs;
     }

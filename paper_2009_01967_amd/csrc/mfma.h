@@ -130,6 +130,29 @@ inline void delta_scale(int kind, double sigma_omega, double& scale, double& nor
   }
 }
 
+// Store 16 bytes of elements v[0 .. 16 / sizeof(T)) at o (a multiple of that
+// count) with one write per plane.
+template <int P>
+__device__ __forceinline__ void store_operand_vec(typename Operand<P>::T* hi, typename Operand<P>::T* lo, size_t o,
+                                                  const double* v) {
+  if constexpr (P == KALDO_BF16X3) {
+    typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8v;
+    bf16x8v h, l;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float f = (float)v[q];
+      h[q] = (__bf16)f;
+      l[q] = (__bf16)(f - (float)h[q]);
+    }
+    *reinterpret_cast<bf16x8v*>(hi + o) = h;
+    *reinterpret_cast<bf16x8v*>(lo + o) = l;
+  } else if constexpr (P == KALDO_FP32) {
+    *reinterpret_cast<float4*>(hi + o) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  } else {
+    *reinterpret_cast<double2*>(hi + o) = make_double2(v[0], v[1]);
+  }
+}
+
 // accumulator row of register r in lane l for a 16x16 tile
 template <int P>
 __device__ __forceinline__ int acc_row(int lane, int r) {
