@@ -30,9 +30,13 @@ namespace kaldo {
 constexpr int kYBlock = 32;
 
 // ---- X_s: contract fc3 with eta_s over the home atom ---------------------------------
-// Xs[pair][sl][beta][gamma] for sl < sbp (zero where s0 + sl >= n); pairs are the
-// distinct (j, l) atom pairs.  E is column major: eta_s[a] = E[s * n + a].
-__global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E, const int* __restrict__ pstart,
+// X_s[j beta][l gamma] for the first modes s0 + sl, sl < sbp (zero where
+// s0 + sl >= n), in the layout the sparse step stages into LDS as it is:
+// Xs[sl / 16][pair][gamma][beta][sl % 16] (R values), pairs being the distinct
+// (j, l) atom pairs, so that the values of one atom's pairs for a group of 16
+// modes are contiguous.  E is column major: eta_s[a] = E[s * n + a].
+template <typename R>
+__global__ void k_gamma_xs(R* __restrict__ Xs, const double* __restrict__ E, const int* __restrict__ pstart,
                            const int* __restrict__ gi, const double* __restrict__ gval, int n, int npairs, int s0,
                            int sbp) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,7 +54,8 @@ __global__ void k_gamma_xs(double* __restrict__ Xs, const double* __restrict__ E
       v += es[i3] * f[0] + es[i3 + 1] * f[9] + es[i3 + 2] * f[18];
     }
   }
-  Xs[idx] = v;
+  const int beta = e9 / 3, gamma = e9 - 3 * beta;
+  Xs[(((size_t)(sl >> 4) * npairs + pr) * 9 + gamma * 3 + beta) * 16 + (sl & 15)] = (R)v;
 }
 
 // Et[a][s] = eta_s[a]: 32 x 32 tiles through LDS, both sides coalesced.
@@ -90,8 +95,8 @@ __global__ void k_transpose(R* __restrict__ Et, const double* __restrict__ E, in
 template <int P, typename R, int W>
 __global__ void __launch_bounds__(64 * W)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
-              const double* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
-              const int* __restrict__ pl, int n, int N, int sbp, long long bkb, int cnt, int kmax) {
+              const R* __restrict__ Xs, const R* __restrict__ Et, const int* __restrict__ rstart,
+              const int* __restrict__ pl, int n, int N, int npairs, long long bkb, int cnt, int kmax) {
   using T = typename Operand<P>::T;
   using Acc = typename std::conditional<std::is_same<R, double>::value, f64x4, f32x4>::type;
   constexpr int E = kYBlock / (int)sizeof(T);  // atoms per block: 3 E elements = 3 K blocks
@@ -122,12 +127,12 @@ __global__ void __launch_bounds__(64 * W)
     const int np = rstart[j + 1] - p0;
     const int kj = 3 * np, kjp = (kj + 3) & ~3;
     __syncthreads();  // the previous atom is done with the staged values
-    // X_s blocks of the pairs: 16 modes x 9 values contiguous per pair
-    for (int i = tid; i < np * 144; i += 64 * W) {
-      const int q = i / 144, w = i - q * 144;
-      const int u = w / 9, e9 = w - u * 9;
-      const int al = e9 / 3, g = e9 - al * 3;
-      As[((3 * q + g) * 3 + al) * 16 + u] = (R)Xs[((size_t)(p0 + q) * sbp + slb) * 9 + w];
+    // the X_s values of the atom's pairs for this group of 16 modes, stored by
+    // k_gamma_xs as [pair][gamma][alpha][u]: As[k][alpha][u] with k = 3 q + gamma
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(Xs + ((size_t)blockIdx.y * npairs + p0) * 144);
+      uint4* dst = reinterpret_cast<uint4*>(As);
+      for (int i = tid; i < np * 144 * (int)sizeof(R) / 16; i += 64 * W) dst[i] = src[i];
     }
     for (int i = kj * 48 + tid; i < kjp * 48; i += 64 * W) As[i] = (R)0;
     for (int k = tid; k < kjp; k += 64 * W) Ko[k] = k < kj ? (3 * pl[p0 + k / 3] + k % 3) * n : 0;
@@ -410,13 +415,14 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   const size_t part = (size_t)mt_max * ncol_max * nT;
   const size_t xs = (size_t)sbp * npairs * 9;
   const size_t et = (size_t)n * n;
-  KALDO_HIP(ctx, ctx->d_tabs.ensure((tab + graw + part + xs + et) * sizeof(double)));
+  const size_t xs_at = (tab + graw + part + 1) & ~(size_t)1;  // Xs 16-byte aligned (read as uint4)
+  KALDO_HIP(ctx, ctx->d_tabs.ensure((xs_at + xs + et) * sizeof(double)));
   double* OM = ctx->d_tabs.as<double>();
   double* IW = OM + n;
   double* OCC = IW + n;
   double* gr = OCC + (size_t)nT * n;
   double* partial = gr + graw;
-  double* Xs = partial + part;
+  double* Xs = ctx->d_tabs.as<double>() + xs_at;
   RY* Et = reinterpret_cast<RY*>(Xs + xs);
   // operands: A [n][ld] planes, Y [sb * n][ld] planes
   const size_t a_elems = (size_t)n * ld, y_elems = (size_t)sb * n * ld;
@@ -460,9 +466,9 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     prof_begin(ctx);
     if (planning(ctx)) {
     } else if (L.n_pairs > 0) {
-      hipLaunchKernelGGL(k_gamma_xs, dim3(blocks_for((long long)cntp * npairs * 9, TB)), dim3(TB), 0, st, Xs, E,
-                         L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(), L.d_gblk_val.as<double>(), n, npairs, s0,
-                         cntp);
+      hipLaunchKernelGGL(k_gamma_xs<RY>, dim3(blocks_for((long long)cntp * npairs * 9, TB)), dim3(TB), 0, st,
+                         reinterpret_cast<RY*>(Xs), E, L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(),
+                         L.d_gblk_val.as<double>(), n, npairs, s0, cntp);
       KALDO_HIP(ctx, hipGetLastError());
       // waves per block (16 columns s'' each, sharing the staged X_s values):
       // 8, 4 or 2, tuned per problem; smaller blocks overlap one block's staging
@@ -472,8 +478,8 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
         auto go = [&](auto wc) {
           constexpr int W = decltype(wc)::value;
           hipLaunchKernelGGL((k_gamma_y<P, RY, W>), dim3((n + 16 * W - 1) / (16 * W), grid_yz.y, grid_yz.z),
-                             dim3(64 * W), y_lds, st, Yh, Yl, Xs, Et, L.d_grow_start.as<int>(),
-                             L.d_gpair_l.as<int>(), n, N, cntp, y_kb, cnt, kmax);
+                             dim3(64 * W), y_lds, st, Yh, Yl, reinterpret_cast<const RY*>(Xs), Et,
+                             L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, npairs, y_kb, cnt, kmax);
         };
         if (w == 0) go(std::integral_constant<int, 8>{});
         else if (w == 1) go(std::integral_constant<int, 4>{});
