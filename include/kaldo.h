@@ -284,8 +284,8 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
  * name, the summed duration (ms) and the number of launches since enabling;
  * an unknown name gives 0 and 0.
  * kaldo_profile_flops synchronises the stream and returns the matrix-core
- * flops of the projection GEMMs ("project" of the many-branch and Gamma-point
- * paths) since enabling: `executed` counts the block tiles that ran (BF16X3
+ * flops of the projection GEMMs (those timed as "project": GEMM 1 and GEMM 2 of
+ * the many-branch path, the Gamma-point GEMM) since enabling: `executed` counts the block tiles that ran (BF16X3
  * counts its three bf16 products), `dense` every tile launched, including the
  * tiles skipped because all their outputs lie beyond the delta cut.  The
  * few-branch kernel and captured batch graphs are not counted.  Either

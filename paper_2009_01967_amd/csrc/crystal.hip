@@ -375,7 +375,11 @@ template <int P, class Epi>
 static int cr_gemm(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
   hipStream_t st = ctx->stream;
   const int v = autotune(ctx, key, gemm_variants<P, Epi>(), 0, [&](int w) { gemm_launch<P>(w, g, e, st); });
-  if (!planning(ctx)) gemm_launch<P>(v, g, e, st);
+  if (!planning(ctx)) {
+    GemmOps gt = g;
+    prof_tally(ctx, gt);
+    gemm_launch<P>(v, gt, e, st);
+  }
   return v;
 }
 
