@@ -90,8 +90,11 @@ __global__ void k_transpose(R* __restrict__ Et, const double* __restrict__ E, in
 // (a' / E) * bkb + row * E + a' % E with E the elements of kYBlock bytes.  A
 // block takes a run of E atoms: its lanes hold all 3 E elements a' of their
 // rows, three whole K blocks, and store each with full 16-byte writes (the 16
-// lanes of a row group cover 16 neighbouring blocks).  LDS: kmax * (48 *
-// sizeof(R) + 4) bytes, kmax = 3 * (most pairs of one atom) rounded up to 4.
+// lanes of a row group cover 16 neighbouring blocks).  With FP32 values the
+// staging is double buffered: the next atom's values are loaded into registers
+// while this one's MFMAs run.  LDS: NBUF kmax * (48 * sizeof(R) + 4) bytes,
+// NBUF = 2 for FP32 and 1 for FP64, kmax = 3 * (most pairs of one atom)
+// rounded up to 4.
 template <int P, typename R, int W>
 __global__ void __launch_bounds__(64 * W)
     k_gamma_y(typename Operand<P>::T* __restrict__ Yhi, typename Operand<P>::T* __restrict__ Ylo,
@@ -102,9 +105,14 @@ __global__ void __launch_bounds__(64 * W)
   constexpr int E = kYBlock / (int)sizeof(T);  // atoms per block: 3 E elements = 3 K blocks
   constexpr int V = 16 / (int)sizeof(T);        // elements per 16-byte store
   constexpr int KS = sizeof(R) == 8 ? 8 : 16;   // k steps whose B loads are in flight together
+  constexpr int AR = (W >= 8 ? 2 : 16 / W) * (int)sizeof(R) / 4;  // 16-byte staging registers per thread
   extern __shared__ __attribute__((aligned(16))) char ylds[];
-  R* As = reinterpret_cast<R*>(ylds);                                      // [kmax][3][16]
-  int* Ko = reinterpret_cast<int*>(ylds + (size_t)kmax * 48 * sizeof(R));  // [kmax]
+  // double-buffered staging for FP32 values; FP64 keeps one buffer (its
+  // registers would drop a wave per SIMD)
+  constexpr bool DB = sizeof(R) == 4;
+  constexpr int NBUF = DB ? 2 : 1;
+  R* As = reinterpret_cast<R*>(ylds);                                             // [NBUF][kmax][3][16]
+  int* Ko = reinterpret_cast<int*>(ylds + (size_t)NBUF * kmax * 48 * sizeof(R));  // [NBUF][kmax]
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -119,44 +127,133 @@ __global__ void __launch_bounds__(64 * W)
   for (int jj = 0; jj < E; ++jj)
 #pragma unroll
     for (int al = 0; al < 3; ++al) acc[jj][al] = Acc{};
-#pragma unroll
-  for (int jj = 0; jj < E; ++jj) {
-    const int j = jb + jj;
-    if (j >= jend) break;  // uniform across the block
-    const int p0 = rstart[j];
-    const int np = rstart[j + 1] - p0;
-    const int kj = 3 * np, kjp = (kj + 3) & ~3;
-    __syncthreads();  // the previous atom is done with the staged values
-    // the X_s values of the atom's pairs for this group of 16 modes, stored by
-    // k_gamma_xs as [pair][gamma][alpha][u]: As[k][alpha][u] with k = 3 q + gamma
-    {
-      const uint4* src = reinterpret_cast<const uint4*>(Xs + ((size_t)blockIdx.y * npairs + p0) * 144);
-      uint4* dst = reinterpret_cast<uint4*>(As);
+  if constexpr (DB) {
+    // Double-buffered staging: buffer b holds atom jb + jj while the loads of the
+    // next atom are in flight in registers; one barrier per atom.
+    const int bufR = kmax * 48;  // R values of one A buffer
+    auto stage_direct = [&](int j, int b) __attribute__((always_inline)) {
+      const int p0 = rstart[j], np = rstart[j + 1] - p0;
+      const int kj = 3 * np, kjp = (kj + 3) & ~3;
+      const u32x4* src = reinterpret_cast<const u32x4*>(Xs + ((size_t)blockIdx.y * npairs + p0) * 144);
+      u32x4* dst = reinterpret_cast<u32x4*>(As + b * bufR);
       for (int i = tid; i < np * 144 * (int)sizeof(R) / 16; i += 64 * W) dst[i] = src[i];
-    }
-    for (int i = kj * 48 + tid; i < kjp * 48; i += 64 * W) As[i] = (R)0;
-    for (int k = tid; k < kjp; k += 64 * W) Ko[k] = k < kj ? (3 * pl[p0 + k / 3] + k % 3) * n : 0;
+      for (int i = kj * 48 + tid; i < kjp * 48; i += 64 * W) As[b * bufR + i] = (R)0;
+      for (int k = tid; k < kjp; k += 64 * W) Ko[b * kmax + k] = k < kj ? (3 * pl[p0 + k / 3] + k % 3) * n : 0;
+    };
+    stage_direct(jb, 0);
     __syncthreads();
-    if (active) {
-      // KS k steps at a time: all their Et loads are issued before the first MFMA
-      for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
-        R bv[KS];
-#pragma unroll
-        for (int q = 0; q < KS; ++q)
-          bv[q] = k0 + 4 * q < kjp ? Et[Ko[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
-#pragma unroll
-        for (int q = 0; q < KS; ++q) {
-          if (k0 + 4 * q >= kjp) break;
-          const int k = k0 + 4 * q + lk;
-          const R a0 = As[(k * 3 + 0) * 16 + li], a1 = As[(k * 3 + 1) * 16 + li], a2 = As[(k * 3 + 2) * 16 + li];
-          if constexpr (std::is_same<R, double>::value) {
-            acc[jj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[q], acc[jj][0], 0, 0, 0);
-            acc[jj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[q], acc[jj][1], 0, 0, 0);
-            acc[jj][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[q], acc[jj][2], 0, 0, 0);
-          } else {
-            acc[jj][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv[q], acc[jj][0], 0, 0, 0);
-            acc[jj][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv[q], acc[jj][1], 0, 0, 0);
-            acc[jj][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bv[q], acc[jj][2], 0, 0, 0);
+    // atoms of the run as compile-time indices (the accumulators stay in registers)
+    static_for<E>([&](auto jc) __attribute__((always_inline)) {
+      constexpr int jj = decltype(jc)::value;
+      constexpr int b = jj & 1;
+      const int j = jb + jj;
+      if (j >= jend) return;  // uniform across the block; so are the later atoms
+      const int kjp = (3 * (rstart[j + 1] - rstart[j]) + 3) & ~3;
+      // next atom: X_s values (16-byte pieces) and Et row offsets into registers
+      const bool more = j + 1 < jend;
+      int np1 = 0, p01 = 0, n16 = 0;
+      u32x4 areg[AR];
+      int ko = 0;
+      bool inreg = false;
+      if (more) {
+        p01 = rstart[j + 1];
+        np1 = rstart[j + 2] - p01;
+        n16 = np1 * 144 * (int)sizeof(R) / 16;
+        inreg = n16 <= AR * 64 * W && 3 * np1 <= 64 * W;
+        if (inreg) {
+          const u32x4* src = reinterpret_cast<const u32x4*>(Xs + ((size_t)blockIdx.y * npairs + p01) * 144);
+  #pragma unroll
+          for (int r = 0; r < AR; ++r) {
+            const int i = tid + r * 64 * W;
+            if (i < n16) areg[r] = src[i];
+          }
+          if (tid < 3 * np1) ko = (3 * pl[p01 + tid / 3] + tid % 3) * n;
+        }
+      }
+      if (active) {
+        const R* Ab = As + b * bufR;
+        const int* Kb = Ko + b * kmax;
+        // KS k steps at a time: all their Et loads are issued before the first MFMA
+        for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
+          R bv[KS];
+  #pragma unroll
+          for (int q = 0; q < KS; ++q)
+            bv[q] = k0 + 4 * q < kjp ? Et[Kb[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
+  #pragma unroll
+          for (int q = 0; q < KS; ++q) {
+            if (k0 + 4 * q >= kjp) break;
+            const int k = k0 + 4 * q + lk;
+            const R a0 = Ab[(k * 3 + 0) * 16 + li], a1 = Ab[(k * 3 + 1) * 16 + li], a2 = Ab[(k * 3 + 2) * 16 + li];
+            if constexpr (std::is_same<R, double>::value) {
+              acc[jj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[q], acc[jj][0], 0, 0, 0);
+              acc[jj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[q], acc[jj][1], 0, 0, 0);
+              acc[jj][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[q], acc[jj][2], 0, 0, 0);
+            } else {
+              acc[jj][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv[q], acc[jj][0], 0, 0, 0);
+              acc[jj][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv[q], acc[jj][1], 0, 0, 0);
+              acc[jj][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bv[q], acc[jj][2], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (more) {
+        // the other buffer was last read before the previous barrier
+        if (inreg) {
+          const int kj1 = 3 * np1, kjp1 = (kj1 + 3) & ~3;
+          u32x4* dst = reinterpret_cast<u32x4*>(As + (b ^ 1) * bufR);
+  #pragma unroll
+          for (int r = 0; r < AR; ++r) {
+            const int i = tid + r * 64 * W;
+            if (i < n16) dst[i] = areg[r];
+          }
+          for (int i = kj1 * 48 + tid; i < kjp1 * 48; i += 64 * W) As[(b ^ 1) * bufR + i] = (R)0;
+          if (tid < kjp1) Ko[(b ^ 1) * kmax + tid] = tid < kj1 ? ko : 0;
+        } else {
+          stage_direct(j + 1, b ^ 1);
+        }
+        __syncthreads();
+      }
+    });
+  } else {
+  #pragma unroll
+    for (int jj = 0; jj < E; ++jj) {
+      const int j = jb + jj;
+      if (j >= jend) break;  // uniform across the block
+      const int p0 = rstart[j];
+      const int np = rstart[j + 1] - p0;
+      const int kj = 3 * np, kjp = (kj + 3) & ~3;
+      __syncthreads();  // the previous atom is done with the staged values
+      // the X_s values of the atom's pairs for this group of 16 modes, stored by
+      // k_gamma_xs as [pair][gamma][alpha][u]: As[k][alpha][u] with k = 3 q + gamma
+      {
+        const uint4* src = reinterpret_cast<const uint4*>(Xs + ((size_t)blockIdx.y * npairs + p0) * 144);
+        uint4* dst = reinterpret_cast<uint4*>(As);
+        for (int i = tid; i < np * 144 * (int)sizeof(R) / 16; i += 64 * W) dst[i] = src[i];
+      }
+      for (int i = kj * 48 + tid; i < kjp * 48; i += 64 * W) As[i] = (R)0;
+      for (int k = tid; k < kjp; k += 64 * W) Ko[k] = k < kj ? (3 * pl[p0 + k / 3] + k % 3) * n : 0;
+      __syncthreads();
+      if (active) {
+        // KS k steps at a time: all their Et loads are issued before the first MFMA
+        for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
+          R bv[KS];
+  #pragma unroll
+          for (int q = 0; q < KS; ++q)
+            bv[q] = k0 + 4 * q < kjp ? Et[Ko[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
+  #pragma unroll
+          for (int q = 0; q < KS; ++q) {
+            if (k0 + 4 * q >= kjp) break;
+            const int k = k0 + 4 * q + lk;
+            const R a0 = As[(k * 3 + 0) * 16 + li], a1 = As[(k * 3 + 1) * 16 + li], a2 = As[(k * 3 + 2) * 16 + li];
+            if constexpr (std::is_same<R, double>::value) {
+              acc[jj][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[q], acc[jj][0], 0, 0, 0);
+              acc[jj][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[q], acc[jj][1], 0, 0, 0);
+              acc[jj][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[q], acc[jj][2], 0, 0, 0);
+            } else {
+              acc[jj][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv[q], acc[jj][0], 0, 0, 0);
+              acc[jj][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv[q], acc[jj][1], 0, 0, 0);
+              acc[jj][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bv[q], acc[jj][2], 0, 0, 0);
+            }
           }
         }
       }
@@ -455,8 +552,8 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   if ((int)L.grow_start.size() == N + 1)
     for (int j = 0; j < N; ++j) max_pairs = std::max(max_pairs, L.grow_start[j + 1] - L.grow_start[j]);
   const int kmax = (3 * max_pairs + 3) & ~3;
-  const size_t y_lds = (size_t)kmax * (48 * sizeof(RY) + sizeof(int));
-  if (y_lds > 64 * 1024) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
+  const size_t y_lds = (size_t)(sizeof(RY) == 4 ? 2 : 1) * kmax * (48 * sizeof(RY) + sizeof(int));
+  if (y_lds > 160 * 1024) return fail(ctx, KALDO_EINVAL, "Gamma path: too many fc3 atom pairs per atom");
   for (int b = 0; b < nbatch; ++b) {
     // planning visits the batches whose GEMM shapes differ: the first and the last
     if (planning(ctx) && b != 0 && b != nbatch - 1) continue;
@@ -477,6 +574,9 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
         const dim3 grid_yz(0, cntp / SB, (N + EY - 1) / EY);
         auto go = [&](auto wc) {
           constexpr int W = decltype(wc)::value;
+          if (y_lds > 64 * 1024)  // beyond the default dynamic LDS limit (gfx950 has 160 KB)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gamma_y<P, RY, W>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)y_lds);
           hipLaunchKernelGGL((k_gamma_y<P, RY, W>), dim3((n + 16 * W - 1) / (16 * W), grid_yz.y, grid_yz.z),
                              dim3(64 * W), y_lds, st, Yh, Yl, reinterpret_cast<const RY*>(Xs), Et,
                              L.d_grow_start.as<int>(), L.d_gpair_l.as<int>(), n, N, npairs, y_kb, cnt, kmax);
