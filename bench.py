@@ -398,7 +398,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
     ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
     ap.add_argument("--plain", metavar="WORKLOAD", help="run one workload through the library alone "
-                    "(no torch; for rocprofv3 counters) with --precision, then exit")
+                    "(torch initialises the GPU but hands the library no stream or tensor; for rocprofv3 "
+                    "counters) with --precision, then exit")
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the headline workload (prints only the MFMA workloads; for profiling)")
@@ -406,8 +407,9 @@ def main():
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part "
-              f"of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): it measures one GPU's share of "
+              f"the path; a sharded run would give each GPU a range of first-mode points "
+              f"(kaldo_set_k_range)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch

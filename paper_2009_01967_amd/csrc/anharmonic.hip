@@ -480,9 +480,9 @@ kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision) {
   if (n == 3 || n == 6) {
     if (precision == KALDO_FP64) return linewidths_small<double>(ctx, sigma_thz);
     if (precision == KALDO_FP32) return linewidths_small<float>(ctx, sigma_thz);
-    return fail(ctx, KALDO_EINVAL, "BF16X3 needs the Gamma-point path (grid {1,1,1})");
+    return fail(ctx, KALDO_EINVAL, "unknown projection precision");
   }
-  return fail(ctx, KALDO_EINVAL, "this build handles cells of 1 or 2 atoms (n = 3 or 6) on crystal grids");
+  return fail(ctx, KALDO_EINVAL, "no linewidth kernel for " + std::to_string(n) + " modes per grid point");
 }
 
 }  // namespace kaldo
