@@ -279,6 +279,23 @@ def run_batch(div=64, steps=1, warmup=1):
         res[label] = dict(ms=ms, g=[o[:, :m].cpu().numpy().copy() for o, m in zip(outs, sub)])
         log(f"batch {label}: {ms:.1f} ms per graph launch")
     ctx.close()
+    # the fraction of the tiled GEMM work that runs (tiles beyond the delta cut
+    # are skipped): one eager FP32 pass per crystal on the same points, with the
+    # library's flop tally (captured graphs carry no tally)
+    t0 = time.perf_counter()
+    ex_all = dense_all = 0.0
+    for c, m in zip(crystals, sub):
+        with kaldo.Context(0, stream.cuda_stream) as one:
+            one.phonons(c)
+            one.set_k_range(0, m)
+            one.linewidths(c, T=T, sigma_thz=sigma, precision="fp32", want_host=False)
+            kaldo.kaldo_profile_enable(one.h, True)
+            one.linewidths(None, T=T, sigma_thz=sigma, precision="fp32", want_host=False)
+            ex, dense = kaldo.kaldo_profile_flops(one.h)
+            ex_all += ex
+            dense_all += dense
+    ran = ex_all / dense_all if dense_all else 1.0
+    log(f"batch: {1.0 - ran:.3f} of the tiled GEMM work skipped (eager tally, {time.perf_counter() - t0:.1f} s)")
     # accuracy of FP32 against FP64 on the computed points (unmasked modes)
     err = 0.0
     for g32, g64 in zip(res["fp32"]["g"], res["fp64"]["g"]):
@@ -298,10 +315,13 @@ def run_batch(div=64, steps=1, warmup=1):
         out[label] = {"ms_per_launch": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
                       "extrapolated_full_draw_s": ms * 1e-3 * sum(gemm_full) / sum(gemm),
                       "roofline": {"bound": "mfma", "kernel": "whole graph (all crystals, every kernel)",
-                                   "achieved": sum(gemm) / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
-                                   "unit": "TFLOP/s", "frac": sum(gemm) / (ms * 1e-3) / peak, "traffic": None,
-                                   "basis": "dense GEMM flops of the computed points (tiles skipped by the "
-                                            "delta window count as work)"}}
+                                   "achieved": sum(gemm) * ran / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                                   "unit": "TFLOP/s", "frac": sum(gemm) * ran / (ms * 1e-3) / peak,
+                                   "traffic": None,
+                                   "basis": "algorithmic GEMM flops of the computed points times the fraction "
+                                            "of tiled work that ran (eager FP32 tally)",
+                                   "tiles_skipped_frac": 1.0 - ran,
+                                   "dense_equivalent_tflops": sum(gemm) / (ms * 1e-3) / 1e12}}
     out["speedup_fp32_vs_fp64"] = res["fp64"]["ms"] / res["fp32"]["ms"]
     return out
 
