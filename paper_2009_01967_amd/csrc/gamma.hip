@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(64 * W)
         inreg = n16 <= AR * 64 * W && 3 * np1 <= 64 * W;
         if (inreg) {
           const u32x4* src = reinterpret_cast<const u32x4*>(Xs + ((size_t)blockIdx.y * npairs + p01) * 144);
-  #pragma unroll
+#pragma unroll
           for (int r = 0; r < AR; ++r) {
             const int i = tid + r * 64 * W;
             if (i < n16) areg[r] = src[i];
@@ -176,10 +176,10 @@ __global__ void __launch_bounds__(64 * W)
         // KS k steps at a time: all their Et loads are issued before the first MFMA
         for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
           R bv[KS];
-  #pragma unroll
+#pragma unroll
           for (int q = 0; q < KS; ++q)
             bv[q] = k0 + 4 * q < kjp ? Et[Kb[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
-  #pragma unroll
+#pragma unroll
           for (int q = 0; q < KS; ++q) {
             if (k0 + 4 * q >= kjp) break;
             const int k = k0 + 4 * q + lk;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(64 * W)
         if (inreg) {
           const int kj1 = 3 * np1, kjp1 = (kj1 + 3) & ~3;
           u32x4* dst = reinterpret_cast<u32x4*>(As + (b ^ 1) * bufR);
-  #pragma unroll
+#pragma unroll
           for (int r = 0; r < AR; ++r) {
             const int i = tid + r * 64 * W;
             if (i < n16) dst[i] = areg[r];
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(64 * W)
       }
     });
   } else {
-  #pragma unroll
+#pragma unroll
     for (int jj = 0; jj < E; ++jj) {
       const int j = jb + jj;
       if (j >= jend) break;  // uniform across the block
@@ -237,10 +237,10 @@ __global__ void __launch_bounds__(64 * W)
         // KS k steps at a time: all their Et loads are issued before the first MFMA
         for (int k0 = 0; k0 < kjp; k0 += 4 * KS) {
           R bv[KS];
-  #pragma unroll
+#pragma unroll
           for (int q = 0; q < KS; ++q)
             bv[q] = k0 + 4 * q < kjp ? Et[Ko[k0 + 4 * q + lk] + s2c] : (R)0;  // padded k: row 0, A = 0
-  #pragma unroll
+#pragma unroll
           for (int q = 0; q < KS; ++q) {
             if (k0 + 4 * q >= kjp) break;
             const int k = k0 + 4 * q + lk;
