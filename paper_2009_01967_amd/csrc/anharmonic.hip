@@ -112,40 +112,51 @@ template <typename R>
 __global__ void k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict__ E, const int2* __restrict__ group,
                          const int* __restrict__ bi, const int* __restrict__ bR2, const double* __restrict__ bval,
                          int N, int nd, int G0, int G1, int G2, int k0, int kcount) {
+  // one thread per (k, s, Delta, j, l): all 9 (beta, gamma) elements of the
+  // 3 x 3 block share the eigenvector loads and the phase of every fc3 block
   const int n = 3 * N;
-  const long long per_k = (long long)n * nd * n * n;
+  const long long per_k = (long long)n * nd * N * N;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= per_k * kcount) return;
-  const int app = (int)(idx % n);
-  const int ap = (int)((idx / n) % n);
-  const int d = (int)((idx / ((long long)n * n)) % nd);
-  const int s = (int)((idx / ((long long)n * n * nd)) % n);
   const int kl = (int)(idx / per_k);
+  int r = (int)(idx - kl * per_k);
+  const int l = r % N;
+  r /= N;
+  const int j = r % N;
+  r /= N;
+  const int d = r % nd;
+  const int s = r / nd;
   const int k = k0 + kl;
-  const int j = ap / 3, be = ap % 3, l = app / 3, ga = app % 3;
   const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
   const long long Gt = (long long)G0 * G1 * G2;
   const int2 g = group[((size_t)d * N + j) * N + l];
   const cplx<double>* e = E + ((size_t)k * n + s) * n;
-  double re = 0.0, im = 0.0;
+  double re[9], im[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) re[q] = im[q] = 0.0;
   for (int b = g.x; b < g.y; ++b) {
     const int i = bi[b];
-    const double* v = bval + 27 * (size_t)b + 3 * be + ga;
-    double sr = 0.0, si = 0.0;
-    for (int al = 0; al < 3; ++al) {
-      const cplx<double> ev = e[3 * i + al];
-      const double f = v[9 * al];
-      sr += ev.re * f;
-      si += ev.im * f;
-    }
+    const cplx<double> e0 = e[3 * i], e1 = e[3 * i + 1], e2 = e[3 * i + 2];
     const long long num = (long long)m0 * bR2[3 * b] * (G1 * G2) + (long long)m1 * bR2[3 * b + 1] * (G0 * G2) +
                           (long long)m2 * bR2[3 * b + 2] * (G0 * G1);
     double c, sn;
     unit_phase(num, Gt, c, sn);  // exp(+2 pi i k.R2)
-    re += sr * c - si * sn;
-    im += sr * sn + si * c;
+    const double* v = bval + 27 * (size_t)b;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {  // q = 3 beta + gamma
+      const double f0 = v[q], f1 = v[9 + q], f2 = v[18 + q];
+      const double sr = e0.re * f0 + e1.re * f1 + e2.re * f2;
+      const double si = e0.im * f0 + e1.im * f1 + e2.im * f2;
+      re[q] += sr * c - si * sn;
+      im[q] += sr * sn + si * c;
+    }
   }
-  A[idx] = {(R)re, (R)im};
+  cplx<R>* out = A + (((size_t)kl * n + s) * nd + d) * n * n;
+#pragma unroll
+  for (int be = 0; be < 3; ++be)
+#pragma unroll
+    for (int ga = 0; ga < 3; ++ga)
+      out[(size_t)(3 * j + be) * n + 3 * l + ga] = {(R)re[3 * be + ga], (R)im[3 * be + ga]};
 }
 
 // ---- fused step B + step C + epilogue ----------------------------------------------
@@ -428,7 +439,7 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
     const int kc = std::min(kchunk, ke - k0);
     P.k0 = k0;
     prof_begin(ctx);
-    hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)a_per_k / sizeof(cplx<R>) * kc, TB)), dim3(TB), 0,
+    hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)n * nd * N * N * kc, TB)), dim3(TB), 0,
                        st, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(), ctx->fc3.d_blk_i.as<int>(),
                        ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, k0, kc);
     KALDO_HIP(ctx, hipGetLastError());
