@@ -31,7 +31,8 @@
  *    part anywhere (gamma = 0, no kappa contribution).
  *  - gamma_mu = Gamma^0_mu = (1/N_k) [sum Gamma+ + 1/2 sum Gamma-] is the
  *    half width (rad/ps); tau = 1 / (2 gamma).  The energy delta is a Gaussian
- *    of standard deviation 2 pi sigma_thz in angular frequency.
+ *    of standard deviation 2 pi sigma_thz in angular frequency, or a
+ *    Lorentzian or triangle of that width (kaldo_delta).
  *  - gamma is averaged over each set of degenerate modes at one k (chained
  *    frequency gaps below 1e-5 THz); only set averages are basis independent.
  *
@@ -173,7 +174,10 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
  *   delta      kind of energy delta; the GPU drops a 16 x 16 tile of GEMM
  *              products whose Gaussian arguments all exceed 6 sigma (mixed
  *              precisions) or 8.9 sigma (FP64), or that all lie outside the
- *              triangle; Lorentzian tails are kept
+ *              triangle, and never runs a GEMM block tile all of whose
+ *              products would be dropped (frequencies ascend within a grid
+ *              point, so the test uses interval bounds); Lorentzian tails are
+ *              kept
  *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
  *              resident for kaldo_kappa_*)
  * Every precision is accepted on every grid.  Cells with n = 3 or 6 branches
