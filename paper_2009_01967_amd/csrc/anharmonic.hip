@@ -259,6 +259,21 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 1
         for (int s2 = 0; s2 < NM; ++s2) {
           const size_t col = (size_t)s2 * NM * nk + kk + z;
+          const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / scale
+          if constexpr (DK != KALDO_DELTA_LORENTZ && std::is_same<R, float>::value) {
+            // a column whose every element, over the wave's partners and all
+            // s', lies beyond the delta's cut adds nothing: skip its step C
+            // (FP32 only: FP64 keeps more of the tail and runs one wave per
+            // SIMD, where the test costs more than it saves)
+            constexpr double cut = delta_cut<KALDO_FP32>(DK);
+            bool need = false;
+#pragma unroll
+            for (int s1 = 0; s1 < NM; ++s1) {
+              const double xp = d2 + wp[s1], xm = d2 - wp[s1];
+              need = need || fmin(xp * xp, xm * xm) < cut;
+            }
+            if (__ballot(need) == 0) continue;
+          }
           cplx<R> Tc[NM];
 #pragma unroll
           for (int a = 0; a < NM; ++a) {
@@ -266,7 +281,6 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int b = 0; b < NM; ++b) cfma_conj(Tc[a], F[a][b], ET[col + (size_t)b * nk]);
           }
-          const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / scale
           const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
           R n2[NT];
 #pragma unroll
