@@ -176,8 +176,10 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
  *              precisions) or 8.9 sigma (FP64), or that all lie outside the
  *              triangle, and never runs a GEMM block tile all of whose
  *              products would be dropped (frequencies ascend within a grid
- *              point, so the test uses interval bounds); Lorentzian tails are
- *              kept
+ *              point, so the test uses interval bounds); the FP32 few-branch
+ *              kernel skips a column s'' for a wavefront of 64 partners when
+ *              all of its elements lie beyond the same cut; Lorentzian tails
+ *              are kept
  *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
  *              resident for kaldo_kappa_*)
  * Every precision is accepted on every grid.  Cells with n = 3 or 6 branches
