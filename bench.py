@@ -8,7 +8,9 @@ outputs stay in device memory.  The mixed-precision (FP32 projection) path
 gives ``value``; the FP64 path is timed beside it.
 
 The many-branch workloads that run the projection as MFMA GEMMs (the 46-atom
-cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed after it,
+cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed beside it
+(in a child process, like the batch, so that a failure there costs only that
+section, reported as ``mfma_paths_error`` / ``batched_path_error``),
 BF16X3 beside FP64, and reported under ``mfma_paths`` with the roofline of
 their GEMMs (``--no-mfma`` skips them).  The 32-crystal batch (one HIP graph
 launch, FP32 beside FP64) is timed on a share of each crystal's first-mode
@@ -250,19 +252,19 @@ def run_batch(div=64, steps=1, warmup=1):
     T, sigma = [300.0], 0.1
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    ctx = kaldo.Context(0, stream.cuda_stream)
-    t0 = time.perf_counter()
-    sub = []
-    for i, c in enumerate(crystals):
-        ctx.batch_add(c)
-        m = max(1, -(-c.n_k // div))
-        ctx.batch_set_k_range(i, 0, m)
-        sub.append(m)
-    torch.cuda.synchronize()
-    log(f"batch: phonons of {len(crystals)} crystals in {time.perf_counter() - t0:.1f} s")
+    sub = [max(1, -(-c.n_k // div)) for c in crystals]
     outs = [torch.empty((len(T), c.n_k, c.n_modes), dtype=torch.float64, device=dev) for c in crystals]
     res = {}
     for label, prec in (("fp32", kaldo.KALDO_FP32), ("fp64", kaldo.KALDO_FP64)):
+        # one context per precision: each graph is captured once, on a context
+        # that has captured nothing before
+        ctx = kaldo.Context(0, stream.cuda_stream)
+        t0 = time.perf_counter()
+        for i, (c, m) in enumerate(zip(crystals, sub)):
+            ctx.batch_add(c)
+            ctx.batch_set_k_range(i, 0, m)
+        torch.cuda.synchronize()
+        log(f"batch {label}: phonons of {len(crystals)} crystals in {time.perf_counter() - t0:.1f} s")
         t0 = time.perf_counter()
         for _ in range(warmup):  # the first call plans, tunes and captures the graph
             kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, prec, outs))
@@ -278,7 +280,7 @@ def run_batch(div=64, steps=1, warmup=1):
         ms = e0.elapsed_time(e1) / steps
         res[label] = dict(ms=ms, g=[o[:, :m].cpu().numpy().copy() for o, m in zip(outs, sub)])
         log(f"batch {label}: {ms:.1f} ms per graph launch")
-    ctx.close()
+        ctx.close()
     # the fraction of the tiled GEMM work that runs (tiles beyond the delta cut
     # are skipped): one eager FP32 pass per crystal on the same points, with the
     # library's flop tally (captured graphs carry no tally)
@@ -345,6 +347,23 @@ def run_plain(name, precision, passes=2):
             ctx.linewidths(c, T=list(w["T"]), sigma_thz=w["sigma_thz"], precision=precision)
             (ctx.kappa_qhgk if c.n_k == 1 else ctx.kappa_rta)()
             log(f"{name} {precision} pass {r}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+
+
+def run_section(flags, key):
+    """One optional section of the benchmark (the MFMA workloads or the batch)
+    in a child process, so that a failure there costs that section only.  The
+    child's progress goes to this process's stderr; its JSON line is parsed.
+    Returns (value, None) or (None, reason)."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--no-main"] + flags
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True, timeout=1800, cwd=ROOT)
+    except subprocess.TimeoutExpired:
+        return None, "section timed out"
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip().startswith("{")]
+    if r.returncode != 0 or not lines:
+        return None, f"section exited with status {r.returncode}"
+    return json.loads(lines[-1]).get(key), None
 
 
 def measured_peaks():
@@ -457,6 +476,13 @@ def main():
             extra["batched_path"] = run_batch()
         print(json.dumps(extra))
         return
+    # the MFMA workloads and the batch run first, each in a child process
+    # started before this process touches the GPU
+    sections = {}
+    if not args.no_mfma:
+        sections["mfma_paths"] = run_section(["--no-batch"], "mfma_paths")
+    if not args.no_batch:
+        sections["batched_path"] = run_section(["--no-mfma"], "batched_path")
     r = run_gpu(args)
     nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
     lw = nk * n * nT
@@ -498,10 +524,11 @@ def main():
             "flops_per_launch": f_b + f_c,
         },
     }
-    if not args.no_mfma:
-        out["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
-    if not args.no_batch:
-        out["batched_path"] = run_batch()
+    for key, (val, why) in sections.items():
+        if val is not None:
+            out[key] = val
+        else:
+            out[key + "_error"] = why
     out["measured_peaks"] = measured_peaks()
     if not args.no_cpu:
         base, err = cpu_baseline(r)
