@@ -109,7 +109,7 @@ __global__ void k_evec_transpose(cplx<R>* __restrict__ ET, const cplx<double>* _
 
 // ---- step A ---------------------------------------------------------------------
 template <typename R>
-__global__ void k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict__ E, const int2* __restrict__ group,
+__global__ void __launch_bounds__(256) k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict__ E, const int2* __restrict__ group,
                          const int* __restrict__ bi, const int* __restrict__ bR2, const double* __restrict__ bval,
                          int N, int nd, int G0, int G1, int G2, int k0, int kcount) {
   // one thread per (k, s, Delta, j, l): all 9 (beta, gamma) elements of the
