@@ -24,3 +24,12 @@ def test_algorithmic_flops_of_the_headline_workload():
     assert f_b == 8.0 * 4096 ** 2 * 25 * 6 ** 3
     assert f_c == 16.0 * 4096 ** 2 * 6 ** 4
     assert abs((f_b + f_c) - 1.0727e12) / 1.0727e12 < 1e-3
+
+
+def test_failed_section_is_reported_not_raised():
+    # a child that exits before touching a GPU (more than one GPU asked for)
+    sys.path.insert(0, ROOT)
+    import bench
+    val, why = bench.run_section(["--gpus", "2"], "mfma_paths")
+    assert val is None
+    assert "status 2" in why
