@@ -421,18 +421,22 @@ struct EpiGamma {
 };
 
 // g[t][s] = C / w_s * sum over row tiles and the n columns of s (one block per (sl, t))
-__global__ void k_gamma_collect(double* __restrict__ graw, const double* __restrict__ partial,
-                                const double* __restrict__ IW, int n, int nT, int m_tiles, long long ncol, int s0,
-                                double C) {
-  __shared__ double red[256];
+__global__ void __launch_bounds__(1024)
+    k_gamma_collect(double* __restrict__ graw, const double* __restrict__ partial, const double* __restrict__ IW,
+                    int n, int nT, int m_tiles, long long ncol, int s0, double C) {
+  // one block of 1024 threads per (first mode, temperature): the (row tile,
+  // s'') partial sums are walked flat, so that many loads are in flight
+  __shared__ double red[1024];
   const int sl = blockIdx.x, t = blockIdx.y;
   double v = 0.0;
-  for (int mt = 0; mt < m_tiles; ++mt)
-    for (int s2 = threadIdx.x; s2 < n; s2 += 256)
-      v += partial[((size_t)mt * ncol + (size_t)sl * n + s2) * nT + t];
+  const int total = m_tiles * n;
+  for (int i = threadIdx.x; i < total; i += 1024) {
+    const int mt = i / n, s2 = i - mt * n;
+    v += partial[((size_t)mt * ncol + (size_t)sl * n + s2) * nT + t];
+  }
   red[threadIdx.x] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -631,7 +635,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     KALDO_HIP(ctx, hipGetLastError());
     prof_end(ctx, "project");
     if (planning(ctx)) continue;
-    hipLaunchKernelGGL(k_gamma_collect, dim3(cnt, nT), dim3(256), 0, st, gr, partial, IW, n, nT, gemm_m_tiles<P>(v, n),
+    hipLaunchKernelGGL(k_gamma_collect, dim3(cnt, nT), dim3(1024), 0, st, gr, partial, IW, n, nT, gemm_m_tiles<P>(v, n),
                        (long long)cnt * n, s0, C);
     KALDO_HIP(ctx, hipGetLastError());
   }
