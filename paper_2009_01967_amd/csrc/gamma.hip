@@ -39,23 +39,32 @@ template <typename R>
 __global__ void k_gamma_xs(R* __restrict__ Xs, const double* __restrict__ E, const int* __restrict__ pstart,
                            const int* __restrict__ gi, const double* __restrict__ gval, int n, int npairs, int s0,
                            int sbp) {
+  // one thread per (pair, sl): all 9 (beta, gamma) values share the
+  // eigenvector loads of every fc3 block of the pair
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)sbp * npairs * 9) return;
-  const int e9 = (int)(idx % 9);
-  const int sl = (int)((idx / 9) % sbp);
-  const int pr = (int)(idx / (9LL * sbp));
+  if (idx >= (long long)sbp * npairs) return;
+  const int sl = (int)(idx % sbp);
+  const int pr = (int)(idx / sbp);
   const int s = s0 + sl;
-  double v = 0.0;
+  double v[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) v[q] = 0.0;
   if (s < n) {
     const double* es = E + (size_t)s * n;
     for (int b = pstart[pr]; b < pstart[pr + 1]; ++b) {
-      const double* f = gval + 27 * (size_t)b + e9;
+      const double* f = gval + 27 * (size_t)b;
       const int i3 = 3 * gi[b];
-      v += es[i3] * f[0] + es[i3 + 1] * f[9] + es[i3 + 2] * f[18];
+      const double e0 = es[i3], e1 = es[i3 + 1], e2 = es[i3 + 2];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[q] += e0 * f[q] + e1 * f[9 + q] + e2 * f[18 + q];
     }
   }
-  const int beta = e9 / 3, gamma = e9 - 3 * beta;
-  Xs[(((size_t)(sl >> 4) * npairs + pr) * 9 + gamma * 3 + beta) * 16 + (sl & 15)] = (R)v;
+  R* out = Xs + ((size_t)(sl >> 4) * npairs + pr) * 144 + (sl & 15);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {  // q = 3 beta + gamma, stored at [gamma][beta]
+    const int beta = q / 3, gamma = q % 3;
+    out[(gamma * 3 + beta) * 16] = (R)v[q];
+  }
 }
 
 // Et[a][s] = eta_s[a]: 32 x 32 tiles through LDS, both sides coalesced.
@@ -567,7 +576,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     prof_begin(ctx);
     if (planning(ctx)) {
     } else if (L.n_pairs > 0) {
-      hipLaunchKernelGGL(k_gamma_xs<RY>, dim3(blocks_for((long long)cntp * npairs * 9, TB)), dim3(TB), 0, st,
+      hipLaunchKernelGGL(k_gamma_xs<RY>, dim3(blocks_for((long long)cntp * npairs, TB)), dim3(TB), 0, st,
                          reinterpret_cast<RY*>(Xs), E, L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(),
                          L.d_gblk_val.as<double>(), n, npairs, s0, cntp);
       KALDO_HIP(ctx, hipGetLastError());
