@@ -11,7 +11,7 @@ The many-branch workloads that run the projection as MFMA GEMMs (the 46-atom
 cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed beside it
 (in a child process, like the batch, so that a failure there costs only that
 section, reported as ``mfma_paths_error`` / ``batched_path_error``),
-BF16X3 beside FP64, and reported under ``mfma_paths`` with the roofline of
+BF16X3 and FP32 beside FP64, and reported under ``mfma_paths`` with the roofline of
 their GEMMs (``--no-mfma`` skips them).  The 32-crystal batch (one HIP graph
 launch, FP32 beside FP64) is timed on a share of each crystal's first-mode
 points and reported under ``batched_path`` (``--no-batch`` skips it).
@@ -136,9 +136,9 @@ def run_gpu(args):
 
 
 def run_mfma(name, steps, warmup):
-    """Linewidths and kappa of a many-branch workload on resident phonons, BF16X3
-    then FP64, with the projection GEMMs timed through the library's hooks; one
-    phonon pass is timed on its own."""
+    """Linewidths and kappa of a many-branch workload on resident phonons, BF16X3,
+    FP32 and FP64, with the projection GEMMs timed through the library's hooks;
+    one phonon pass is timed on its own."""
     import torch
     from gen import workload, WORKLOADS
     from paper_2009_01967_amd import kaldo
@@ -172,7 +172,7 @@ def run_mfma(name, steps, warmup):
     torch.cuda.synchronize()
     phonon_ms = e0.elapsed_time(e1)
     res = {}
-    for label, prec in (("bf16x3", kaldo.KALDO_BF16X3), ("fp64", kaldo.KALDO_FP64)):
+    for label, prec in (("bf16x3", kaldo.KALDO_BF16X3), ("fp32", kaldo.KALDO_FP32), ("fp64", kaldo.KALDO_FP64)):
         for _ in range(warmup):
             step(prec)
         torch.cuda.synchronize()
@@ -202,11 +202,12 @@ def run_mfma(name, steps, warmup):
     floor = 1e-6 * np.abs(g64).max()
     err = float(np.max(np.abs(res["bf16x3"]["g"] - g64) / np.maximum(np.abs(g64), floor)))
     kerr = float(np.max(np.abs(res["bf16x3"]["k"] - res["fp64"]["k"])) / np.abs(res["fp64"]["k"]).max())
+    err32 = float(np.max(np.abs(res["fp32"]["g"] - g64) / np.maximum(np.abs(g64), floor)))
     out = {"workload": name, "n_k": nk, "n_modes": n, "T_K": T, "sigma_thz": sigma,
            "step": "kaldo_linewidths + kaldo_kappa on resident phonons", "phonons_ms": phonon_ms,
            "gemm_flops_per_step": f_c, "gamma_rel_err_bf16x3_vs_fp64": err,
-           "kappa_rel_err_bf16x3_vs_fp64": kerr}
-    for label, peak in (("bf16x3", BF16_MFMA_PEAK), ("fp64", FP64_MFMA_PEAK)):
+           "kappa_rel_err_bf16x3_vs_fp64": kerr, "gamma_rel_err_fp32_vs_fp64": err32}
+    for label, peak in (("bf16x3", BF16_MFMA_PEAK), ("fp32", FP32_MFMA_PEAK), ("fp64", FP64_MFMA_PEAK)):
         ms = res[label]["ms"]
         proj = res[label]["kern"].get("project", {}).get("ms_per_step")
         ent = {"ms_per_step": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
@@ -233,6 +234,7 @@ def run_mfma(name, steps, warmup):
                                "dense_equivalent_tflops": f_c / sec / 1e12}
         out[label] = ent
     out["speedup_bf16x3_vs_fp64"] = res["fp64"]["ms"] / res["bf16x3"]["ms"]
+    out["speedup_fp32_vs_fp64"] = res["fp64"]["ms"] / res["fp32"]["ms"]
     return out
 
 
