@@ -76,3 +76,18 @@ def test_sige_1000_gaussian_window_skips_tiles():
     # every tile launched covers at least the 3 x 2 n^4 bf16 flops of the dense projection
     assert dense >= 3 * 2.0 * n ** 4
     assert 0.0 < ex < dense
+
+
+@pytest.mark.parametrize("name", ["four-atom-3x3x2", "cage-12at", "folded-16at-gamma"])
+def test_frequencies_ascend_at_every_grid_point(name):
+    """The tile skip bounds a tile's frequencies by its first and last modes."""
+    from paper_2009_01967_amd import kaldo
+    from gen.crystals import cage_cell
+    if name == "cage-12at":
+        c = cage_cell(n_atoms=12, L=6.0, grid=(2, 2, 2))   # 36 modes: the library solver, not Jacobi
+    else:
+        c = CASES[name][0]()
+    _say(f"case: ascending frequencies, {name} ({c.n_modes} modes, grid {c.grid})")
+    with kaldo.Context(0) as ctx:
+        nu = ctx.phonons(c)
+    assert np.all(np.diff(nu, axis=1) >= 0.0)
