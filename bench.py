@@ -351,6 +351,52 @@ def run_plain(name, precision, passes=2):
             log(f"{name} {precision} pass {r}: {1e3 * (time.perf_counter() - t0):.1f} ms")
 
 
+def run_next2(steps=3):
+    """The variants beside the Gaussian linewidths on the headline workload:
+    the FP32 step with the Lorentzian and the triangle delta (same kernels,
+    other delta kind), and the FP64 phase space per mode (kaldo_phase_space,
+    frequencies only)."""
+    import torch
+    from gen import workload, WORKLOADS
+    from paper_2009_01967_amd import kaldo
+    w = WORKLOADS[WORKLOAD]
+    c = workload(WORKLOAD)
+    T, sigma = list(w["T"]), w["sigma_thz"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    g_d = torch.empty((len(T), c.n_k, c.n_modes), dtype=torch.float64, device=dev)
+    out = {"workload": WORKLOAD, "steps": steps}
+    with kaldo.Context(0, stream.cuda_stream) as ctx:
+        ctx.phonons(c)
+        ctx.linewidths(c, T=T, sigma_thz=sigma, precision="fp32", want_host=False)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        lw = c.n_k * c.n_modes * len(T)
+        for kind in ("lorentz", "triangle"):
+            ms = timed(lambda: kaldo._check(ctx.h, kaldo.kaldo_linewidths(
+                ctx.h, None, T, sigma, stats=kaldo.KALDO_QUANTUM, precision=kaldo.KALDO_FP32, gamma_out=g_d,
+                delta=kaldo.DELTAS[kind])))
+            out[f"linewidths_fp32_{kind}"] = {"ms_per_call": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s"}
+            log(f"next2: FP32 linewidths with the {kind} delta: {ms:.2f} ms")
+        ms = timed(lambda: kaldo._check(ctx.h, kaldo.kaldo_phase_space(
+            ctx.h, T, sigma, delta=kaldo.KALDO_DELTA_GAUSS, stats=kaldo.KALDO_QUANTUM, g_out=g_d)))
+        out["phase_space_fp64_gauss"] = {"ms_per_call": ms, "value": lw / (ms * 1e-3), "unit": "modes/s",
+                                         "triples_per_s": c.n_k * c.n_k * c.n_modes ** 3 / (ms * 1e-3)}
+        log(f"next2: FP64 phase space: {ms:.2f} ms")
+    return out
+
+
 def run_section(flags, key):
     """One optional section of the benchmark (the MFMA workloads or the batch)
     in a child process, so that a failure there costs that section only.  The
@@ -437,6 +483,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
+    ap.add_argument("--no-next2", action="store_true",
+                    help="skip the Lorentzian/triangle linewidths and the phase space on the headline workload")
     ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
     ap.add_argument("--plain", metavar="WORKLOAD", help="run one workload through the library alone "
                     "(torch initialises the GPU but hands the library no stream or tensor; for rocprofv3 "
@@ -526,6 +574,8 @@ def main():
             "flops_per_launch": f_b + f_c,
         },
     }
+    if not args.no_next2:
+        out["next2"] = run_next2()
     for key, (val, why) in sections.items():
         if val is not None:
             out[key] = val
