@@ -18,29 +18,36 @@ __global__ void k_tables(double* __restrict__ OM, double* __restrict__ IW, doubl
                          const double* __restrict__ omega, int nk, int n, int nT, double4 T03, double4 T47,
                          int classical);
 
+// Frequencies in units of the delta's scale, +infinity for masked modes (every
+// mismatch with them is then beyond any cut, so one load serves both tests).
+__global__ void k_phase_omx(double* __restrict__ OMX, const double* __restrict__ OM, const double* __restrict__ IW,
+                            int nmode, double rs) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < nmode) OMX[i] = IW[i] != 0.0 ? OM[i] * rs : __builtin_inf();
+}
+
 template <int DK>
 __global__ void __launch_bounds__(256)
-    k_phase_space(double* __restrict__ g, const double* __restrict__ OM, const double* __restrict__ IW,
-                  const double* __restrict__ OCC, int nk, int n, int nT, int G0, int G1, int G2, double rs,
-                  double scale) {
+    k_phase_space(double* __restrict__ g, const double* __restrict__ OMX, const double* __restrict__ IW,
+                  const double* __restrict__ OCC, int nk, int n, int nT, int G0, int G1, int G2, double scale) {
   constexpr double cut = delta_cut<KALDO_FP64>(DK);
-  const long long mode = blockIdx.x;
-  const int s = (int)(mode % n);
-  const int k = (int)(mode / n);
-  const size_t nmode = (size_t)nk * n;
+  const int mode = (int)blockIdx.x;
+  const int s = mode % n;
+  const int k = mode / n;
+  const int nmode = nk * n;
   __shared__ double red[4][KALDO_MAX_T];
   double acc[KALDO_MAX_T];
 #pragma unroll
   for (int t = 0; t < KALDO_MAX_T; ++t) acc[t] = 0.0;
   const bool on = IW[(size_t)s * nk + k] != 0.0;  // uniform across the block
   if (on) {
-    const double w = OM[(size_t)s * nk + k] * rs;
+    const double w = OMX[(size_t)s * nk + k];
     const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
-    for (long long j = threadIdx.x; j < (long long)nmode; j += blockDim.x) {
-      if (IW[j] == 0.0) continue;
-      const int s1 = (int)(j / nk);
-      const int p = (int)(j - (long long)s1 * nk);
-      const double w1 = OM[j] * rs;
+    for (int j = threadIdx.x; j < nmode; j += blockDim.x) {
+      const double w1 = OMX[j];
+      if (!(w1 < __builtin_inf())) continue;  // masked partner
+      const int s1 = j / nk;
+      const int p = j - s1 * nk;
       double n1[KALDO_MAX_T];
 #pragma unroll
       for (int t = 0; t < KALDO_MAX_T; ++t) n1[t] = t < nT ? OCC[(size_t)t * nmode + j] : 0.0;
@@ -49,9 +56,10 @@ __global__ void __launch_bounds__(256)
       const int km = (imod(m0 - p0, G0) * G1 + imod(m1 - p1, G1)) * G2 + imod(m2 - p2, G2);
       for (int s2 = 0; s2 < n; ++s2) {
         // absorption: k'' = k + k', weight (n' - n'') delta(w + w' - w'')
-        const size_t op = (size_t)s2 * nk + kp;
-        if (IW[op] != 0.0) {
-          const double u = w + w1 - OM[op] * rs;
+        // (a masked k'' mode has +infinity: u = -infinity fails the cut)
+        const int op = s2 * nk + kp;
+        {
+          const double u = w + w1 - OMX[op];
           if (u * u < cut) {
             const double d = delta_shape<double, DK>(u);
 #pragma unroll
@@ -60,9 +68,9 @@ __global__ void __launch_bounds__(256)
           }
         }
         // decay: k'' = k - k', weight 1/2 (1 + n' + n'') delta(w - w' - w'')
-        const size_t om = (size_t)s2 * nk + km;
-        if (IW[om] != 0.0) {
-          const double u = w - w1 - OM[om] * rs;
+        const int om = s2 * nk + km;
+        {
+          const double u = w - w1 - OMX[om];
           if (u * u < cut) {
             const double d = 0.5 * delta_shape<double, DK>(u);
 #pragma unroll
@@ -94,11 +102,13 @@ kaldo_status run_phase_space(kaldo_ctx ctx, const double* T, int nT, double sigm
   const int n = ctx->nm, nk = ctx->nk;
   const size_t nmode = (size_t)nk * n;
   hipStream_t st = ctx->stream;
-  KALDO_HIP(ctx, ctx->d_phase.ensure(((2 + (size_t)nT) * nmode + (size_t)nT * nmode) * sizeof(double)));
+  if (nmode >= ((size_t)1 << 31)) return fail(ctx, KALDO_EINVAL, "kaldo_phase_space: too many modes");
+  KALDO_HIP(ctx, ctx->d_phase.ensure(((3 + (size_t)nT) * nmode + (size_t)nT * nmode) * sizeof(double)));
   double* OM = ctx->d_phase.as<double>();
   double* IW = OM + nmode;
   double* OCC = IW + nmode;
   double* G = OCC + (size_t)nT * nmode;
+  double* OMX = G + (size_t)nT * nmode;
   double Ts[KALDO_MAX_T] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = 0; t < nT; ++t) Ts[t] = T[t];
   hipLaunchKernelGGL(k_tables, dim3(blocks_for((long long)nmode, 256)), dim3(256), 0, st, OM, IW, OCC,
@@ -108,16 +118,19 @@ kaldo_status run_phase_space(kaldo_ctx ctx, const double* T, int nT, double sigm
   double dscale, dnorm;
   delta_scale(delta, kTwoPi * sigma_thz, dscale, dnorm);
   const double rs = 1.0 / dscale, scale = dnorm / nk;
+  hipLaunchKernelGGL(k_phase_omx, dim3(blocks_for((long long)nmode, 256)), dim3(256), 0, st, OMX, OM, IW,
+                     (int)nmode, rs);
+  KALDO_HIP(ctx, hipGetLastError());
   const dim3 grid((unsigned)nmode);
   if (delta == KALDO_DELTA_GAUSS)
-    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_GAUSS>, grid, dim3(256), 0, st, G, OM, IW, OCC, nk, n, nT,
-                       ctx->grid[0], ctx->grid[1], ctx->grid[2], rs, scale);
+    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_GAUSS>, grid, dim3(256), 0, st, G, OMX, IW, OCC, nk, n, nT,
+                       ctx->grid[0], ctx->grid[1], ctx->grid[2], scale);
   else if (delta == KALDO_DELTA_LORENTZ)
-    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_LORENTZ>, grid, dim3(256), 0, st, G, OM, IW, OCC, nk, n, nT,
-                       ctx->grid[0], ctx->grid[1], ctx->grid[2], rs, scale);
+    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_LORENTZ>, grid, dim3(256), 0, st, G, OMX, IW, OCC, nk, n, nT,
+                       ctx->grid[0], ctx->grid[1], ctx->grid[2], scale);
   else
-    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_TRIANGLE>, grid, dim3(256), 0, st, G, OM, IW, OCC, nk, n, nT,
-                       ctx->grid[0], ctx->grid[1], ctx->grid[2], rs, scale);
+    hipLaunchKernelGGL(k_phase_space<KALDO_DELTA_TRIANGLE>, grid, dim3(256), 0, st, G, OMX, IW, OCC, nk, n, nT,
+                       ctx->grid[0], ctx->grid[1], ctx->grid[2], scale);
   KALDO_HIP(ctx, hipGetLastError());
   *g_dev = G;
   return KALDO_OK;
