@@ -617,10 +617,14 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     g.nz = 1;
     g.m_valid = n;
     g.c_valid = (long long)cnt * n;
-    // With a cut delta most tiles of a column are skipped and the rest form
-    // bands: all row tiles of a column go together, so that its B panel is
-    // read once by the few tiles that run.
-    g.group_m = ctx->delta == KALDO_DELTA_LORENTZ ? 8 : 1 << 20;
+    // With a cut delta most tiles are skipped and the rest form two bands
+    // across the tile grid.  The tiles go in chunks of 16 column panels, and
+    // inside a chunk in groups of 2 row tiles: each XCD's run then holds whole
+    // chunks (the skipped work is spread evenly), and the tiles that run at the
+    // same time share A and B panels in L2 (measured against all row tiles of
+    // a column together: 88 -> 85 ms on the 1000-atom SiGe cell, BF16X3).
+    g.group_m = ctx->delta == KALDO_DELTA_LORENTZ ? 8 : 2;
+    g.group_n = ctx->delta == KALDO_DELTA_LORENTZ ? 0 : 16;
     const std::string key = "gamma/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt) +
                             "/" + std::to_string(nT) + "/" + std::to_string(ctx->delta);
     int v = 0;

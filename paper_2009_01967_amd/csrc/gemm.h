@@ -63,6 +63,7 @@ struct GemmOps {
   double* tally_dense;
   unsigned long long tile_flops;
   int group_m;        // row tiles per group of the tile order (0: 8; clamped to m_tiles)
+  int group_n;        // column panels per chunk of the tile order (0: all)
 };
 
 // Bytes of one row per K chunk, and the chunk in elements.
@@ -165,13 +166,19 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   const int GM = g.group_m;
   const int per_z = g.m_tiles * g.n_tiles;
   const int z = tile / per_z;
-  const int tz = tile - z * per_z;
-  const int per_group = GM * g.n_tiles;
+  int tz = tile - z * per_z;
+  // optionally the column panels first go in chunks of GN (group_n): the
+  // ordering above then applies inside each chunk
+  const int GN = g.group_n;
+  const int chunk = tz / (g.m_tiles * GN);
+  tz -= chunk * g.m_tiles * GN;
+  const int width = min(GN, g.n_tiles - chunk * GN);
+  const int per_group = GM * width;
   const int first_m = (tz / per_group) * GM;
   const int gm = min(g.m_tiles - first_m, GM);
   const int tg = tz - (tz / per_group) * per_group;
   const int mt = first_m + tg % gm;
-  const int nt = tg / gm;
+  const int nt = chunk * GN + tg / gm;
   if constexpr (SkipEmpty<Epi>::value) {
     // uniform across the block (block indices and operand-independent data only)
     if (epi.template tile_empty<P, FM, FN>(mt, nt, z)) {
@@ -490,6 +497,7 @@ inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
   g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
   g.group_m = g.group_m <= 0 ? 8 : (g.group_m < g.m_tiles ? g.group_m : g.m_tiles);
+  g.group_n = g.group_n <= 0 ? g.n_tiles : (g.group_n < g.n_tiles ? g.group_n : g.n_tiles);
   const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
   // BF16X3 issues three bf16 products per element product
   g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)g.K * (P == KALDO_BF16X3 ? 3 : 1);
