@@ -623,8 +623,11 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     // chunks (the skipped work is spread evenly), and the tiles that run at the
     // same time share A and B panels in L2 (measured against all row tiles of
     // a column together: 88 -> 85 ms on the 1000-atom SiGe cell, BF16X3).
-    g.group_m = ctx->delta == KALDO_DELTA_LORENTZ ? 8 : 2;
-    g.group_n = ctx->delta == KALDO_DELTA_LORENTZ ? 0 : 16;
+    // (FP64 keeps all row tiles of a column together: its smaller tiles did
+    // not gain from the chunks)
+    const bool cut = ctx->delta != KALDO_DELTA_LORENTZ;
+    g.group_m = !cut ? 8 : (P == KALDO_FP64 ? 1 << 20 : 2);
+    g.group_n = !cut || P == KALDO_FP64 ? 0 : 16;
     const std::string key = "gamma/" + std::to_string(P) + "/" + std::to_string(n) + "/" + std::to_string(cnt) +
                             "/" + std::to_string(nT) + "/" + std::to_string(ctx->delta);
     int v = 0;
