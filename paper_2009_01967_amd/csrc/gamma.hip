@@ -34,9 +34,9 @@ constexpr int kYBlock = 32;
 // s0 + sl >= n), in the layout the sparse step stages into LDS as it is:
 // Xs[sl / 16][pair][gamma][beta][sl % 16] (R values), pairs being the distinct
 // (j, l) atom pairs, so that the values of one atom's pairs for a group of 16
-// modes are contiguous.  E is column major: eta_s[a] = E[s * n + a].
+// modes are contiguous.  Et64[a][s] = eta_s[a] (FP64).
 template <typename R>
-__global__ void k_gamma_xs(R* __restrict__ Xs, const double* __restrict__ E, const int* __restrict__ pstart,
+__global__ void k_gamma_xs(R* __restrict__ Xs, const double* __restrict__ Et64, const int* __restrict__ pstart,
                            const int* __restrict__ gi, const double* __restrict__ gval, int n, int npairs, int s0,
                            int sbp) {
   // one thread per (pair, sl): all 9 (beta, gamma) values share the
@@ -50,11 +50,11 @@ __global__ void k_gamma_xs(R* __restrict__ Xs, const double* __restrict__ E, con
 #pragma unroll
   for (int q = 0; q < 9; ++q) v[q] = 0.0;
   if (s < n) {
-    const double* es = E + (size_t)s * n;
+    // Et64[a][s] = eta_s[a]: the lanes (consecutive s) read neighbouring values
     for (int b = pstart[pr]; b < pstart[pr + 1]; ++b) {
       const double* f = gval + 27 * (size_t)b;
-      const int i3 = 3 * gi[b];
-      const double e0 = es[i3], e1 = es[i3 + 1], e2 = es[i3 + 2];
+      const double* e = Et64 + (size_t)(3 * gi[b]) * n + s;
+      const double e0 = e[0], e1 = e[n], e2 = e[2 * (size_t)n];
 #pragma unroll
       for (int q = 0; q < 9; ++q) v[q] += e0 * f[q] + e1 * f[9 + q] + e2 * f[18 + q];
     }
@@ -519,14 +519,16 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   const int nbatch = (n + sb - 1) / sb;
   const long long ncol_max = (long long)sb * n;
   const int mt_max = (n + 63) / 64;  // the smallest candidate block tile has 64 rows
-  // d_tabs: tables | graw | partial | Xs | Et
+  // d_tabs: tables | graw | partial | Xs | Et | Et64 (FP32 Et only)
   const size_t tab = (2 + (size_t)nT) * n;
   const size_t graw = (size_t)nT * n;
   const size_t part = (size_t)mt_max * ncol_max * nT;
   const size_t xs = (size_t)sbp * npairs * 9;
   const size_t et = (size_t)n * n;
   const size_t xs_at = (tab + graw + part + 1) & ~(size_t)1;  // Xs 16-byte aligned (read as uint4)
-  KALDO_HIP(ctx, ctx->d_tabs.ensure((xs_at + xs + et) * sizeof(double)));
+  // an FP64 transposed copy of E for k_gamma_xs when Et holds FP32 values
+  const size_t et64 = std::is_same<RY, double>::value ? 0 : (size_t)n * n;
+  KALDO_HIP(ctx, ctx->d_tabs.ensure((xs_at + xs + et + et64) * sizeof(double)));
   double* OM = ctx->d_tabs.as<double>();
   double* IW = OM + n;
   double* OCC = IW + n;
@@ -534,6 +536,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
   double* partial = gr + graw;
   double* Xs = ctx->d_tabs.as<double>() + xs_at;
   RY* Et = reinterpret_cast<RY*>(Xs + xs);
+  double* Et64 = std::is_same<RY, double>::value ? reinterpret_cast<double*>(Et) : Xs + xs + et;
   // operands: A [n][ld] planes, Y [sb * n][ld] planes
   const size_t a_elems = (size_t)n * ld, y_elems = (size_t)sb * n * ld;
   // Y is K-blocked: blocks of kYBlock bytes of elements, each block column
@@ -556,6 +559,8 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
                      ctx->d_omega.as<double>(), n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
   hipLaunchKernelGGL((k_gamma_a<P>), dim3(blocks_for((long long)n * ld, TB)), dim3(TB), 0, st, Ah, Al, E, n, ld);
   hipLaunchKernelGGL((k_transpose<RY>), dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et, E, n);
+  if constexpr (!std::is_same<RY, double>::value)
+    hipLaunchKernelGGL((k_transpose<double>), dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, st, Et64, E, n);
   KALDO_HIP(ctx, hipGetLastError());
   const double sig = kTwoPi * sigma_thz;
   double dscale, dnorm;
@@ -577,7 +582,7 @@ static kaldo_status gamma_point_impl(kaldo_ctx ctx, double sigma_thz) {
     if (planning(ctx)) {
     } else if (L.n_pairs > 0) {
       hipLaunchKernelGGL(k_gamma_xs<RY>, dim3(blocks_for((long long)cntp * npairs, TB)), dim3(TB), 0, st,
-                         reinterpret_cast<RY*>(Xs), E, L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(),
+                         reinterpret_cast<RY*>(Xs), Et64, L.d_gpair_start.as<int>(), L.d_gblk_i.as<int>(),
                          L.d_gblk_val.as<double>(), n, npairs, s0, cntp);
       KALDO_HIP(ctx, hipGetLastError());
       // waves per block (16 columns s'' each, sharing the staged X_s values):
