@@ -46,7 +46,7 @@ MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 # scaled by what the counter reads for a plain 1 GiB device copy
 # (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Taken on the
 # current k_project_small; set to None when that kernel changes.
-HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3,true,0>", "fetch_kib": 98137.3, "write_kib": 10425.7,
+HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3,true,0>", "fetch_kib": 96612.7, "write_kib": 10212.3,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -129,9 +129,12 @@ def run_gpu(args):
     log(f"fp32: {ms32:.3f} ms/step (wall {wall32:.3f}), kernels {kern32}")
     ms64, wall64, kern64, g64, k64 = timed(kaldo.KALDO_FP64, max(2, args.steps // 2), 1)
     log(f"fp64: {ms64:.3f} ms/step (wall {wall64:.3f}), kernels {kern64}")
-    nd = int(len({tuple(x) for x in (c.fc3_R2 - c.fc3_R1)}))
+    dset = {tuple(int(v) for v in x) for x in (c.fc3_R2 - c.fc3_R1)}
+    nd = len(dset)
+    # (Delta, -Delta) pairs, Delta != 0: the FP32 step B sums each with two real multiplies
+    npair = sum(1 for x in dset if x > (0, 0, 0) and tuple(-v for v in x) in dset)
     ctx.close()
-    return dict(c=c, w=w, T=T, sigma=sigma, nk=nk, n=n, nd=nd, ms32=ms32, ms64=ms64, wall32=wall32,
+    return dict(c=c, w=w, T=T, sigma=sigma, nk=nk, n=n, nd=nd, npair=npair, ms32=ms32, ms64=ms64, wall32=wall32,
                 wall64=wall64, kern32=kern32, kern64=kern64, g32=g32, g64=g64, k32=k32, k64=k64)
 
 
@@ -572,6 +575,12 @@ def main():
             "traffic_unit": "HBM bytes per launch (scaled rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "algorithmic_bytes": algorithmic_bytes(nk, n, nd, nT),
             "flops_per_launch": f_b + f_c,
+            # arithmetic the kernel runs: step B over nd - npair slot groups
+            # (each (Delta, -Delta) pair costs one Delta), before the column skip
+            "flops_executed_per_launch": f_b * (nd - r["npair"]) / nd + f_c,
+            "executed_frac": ((f_b * (nd - r["npair"]) / nd + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK
+                              if proj32 else None),
+            "delta_pairs": r["npair"],
         },
     }
     if not args.no_next2:

@@ -33,6 +33,7 @@ struct ProjArgs {
   int k_local;   // XCD-aware order: the p tiles of one k on one XCD
   double rc;     // 1 / (scale of the delta): frequencies are scaled by it
   int kind;      // kaldo_delta (selects the kernel instance)
+  int npair;     // leading slot pairs (2m, 2m + 1) of A_k in sum/difference form
 };
 
 // ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
@@ -159,6 +160,27 @@ __global__ void __launch_bounds__(256) k_step_a(cplx<R>* __restrict__ A, const c
       out[(size_t)(3 * j + be) * n + 3 * l + ga] = {(R)re[3 * be + ga], (R)im[3 * be + ga]};
 }
 
+// ---- step B in pairs ------------------------------------------------------------
+// Slots 2m and 2m + 1 of A_k hold Delta and -Delta, whose phases are conjugate:
+// with a = A_k[Delta], b = A_k[-Delta] and ph = e^{2 pi i p.Delta},
+//   ph a + conj(ph) b = Re(ph) (a + b) + Im(ph) i (a - b).
+// Rewriting the slots as a + b and i (a - b) lets step B spend two real
+// multiplies per element of the pair instead of two complex ones.
+template <typename R>
+__global__ void k_pair_delta(cplx<R>* __restrict__ A, int n, int nd, int npair, long long count) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;  // count = kc * n * npair * n * n
+  const long long nn = (long long)n * n;
+  const long long e = idx % nn;
+  const long long r = idx / nn;
+  const long long m = r % npair, ks = r / npair;  // ks = kl * n + s
+  cplx<R>* a = A + ((size_t)ks * nd + 2 * m) * nn + e;
+  cplx<R>* b = a + nn;
+  const cplx<R> x = *a, y = *b;
+  *a = {x.re + y.re, x.im + y.im};
+  *b = {y.im - x.im, x.re - y.re};
+}
+
 // ---- fused step B + step C + epilogue ----------------------------------------------
 // Opaque zero: keeps loads inside a loop (bounds register pressure).
 __device__ __forceinline__ int opaque_zero() {
@@ -244,7 +266,26 @@ __global__ void __launch_bounds__(256)
         const cplx<R>* As = Ablk + (size_t)s * P.nd * NM * NM;
         // the phase of the next Delta is in flight while this one is applied
         cplx<R> ph = PH[p];
-        for (int d = 0; d < P.nd; ++d) {
+        int d = 0;
+        // pairs: slots a + b, i (a - b) (FP32 only; FP64 keeps every slot
+        // as written by step A)
+        if constexpr (sizeof(R) == 4) {
+          for (; d < 2 * P.npair; d += 2) {
+            const cplx<R> cur = ph;
+            if (d + 2 < P.nd) ph = PH[(size_t)(d + 2) * nk + p];
+            const cplx<R>* Sd = As + (size_t)d * NM * NM;
+            const cplx<R>* Dd = Sd + NM * NM;
+#pragma unroll
+            for (int a = 0; a < NM; ++a)
+#pragma unroll
+              for (int b = 0; b < NM; ++b) {
+                const cplx<R> sv = Sd[a * NM + b], dv = Dd[a * NM + b];
+                F[a][b].re += cur.re * sv.re + cur.im * dv.re;
+                F[a][b].im += cur.re * sv.im + cur.im * dv.im;
+              }
+          }
+        }
+        for (; d < P.nd; ++d) {
           const cplx<R> cur = ph;
           if (d + 1 < P.nd) ph = PH[(size_t)(d + 1) * nk + p];
           const cplx<R>* Ad = As + (size_t)d * NM * NM;
@@ -441,6 +482,9 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   delta_scale(ctx->delta, sig, dscale, dnorm);
   P.rc = 1.0 / dscale;
   P.kind = ctx->delta;
+  // FP64 runs step B over single slots: at one wave per SIMD the paired
+  // loop was slower there
+  P.npair = sizeof(R) == 4 ? ctx->fc3.n_dpair : 0;
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
@@ -457,6 +501,11 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
                        st, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(), ctx->fc3.d_blk_i.as<int>(),
                        ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, k0, kc);
     KALDO_HIP(ctx, hipGetLastError());
+    if (P.npair > 0) {
+      const long long cnt = (long long)kc * n * P.npair * n * n;
+      hipLaunchKernelGGL((k_pair_delta<R>), dim3(blocks_for(cnt, TB)), dim3(TB), 0, st, A, n, nd, P.npair, cnt);
+      KALDO_HIP(ctx, hipGetLastError());
+    }
     prof_end(ctx, "step_a");
     dim3 grid(nchunk, kc);
     prof_begin(ctx);

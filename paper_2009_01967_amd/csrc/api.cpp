@@ -224,17 +224,31 @@ static kaldo_status load_fc3(kaldo_ctx ctx, const kaldo_fc3* f) {
   for (int64_t b = 0; b < nb; ++b) {
     auto key = std::make_tuple(f->R2[3 * b] - f->R1[3 * b], f->R2[3 * b + 1] - f->R1[3 * b + 1],
                                f->R2[3 * b + 2] - f->R1[3 * b + 2]);
-    dmap.emplace(key, 0);
+    dmap.emplace(key, -1);
   }
   Fc3Layout& L = ctx->fc3;
   L.delta.clear();
+  // Slot order: pairs (Delta, -Delta), Delta != 0, in adjacent slots 2m, 2m + 1
+  // first, then every Delta whose negative is absent, and Delta = 0.  The
+  // few-branch projection sums each pair with one real phase multiply per part.
   int nd = 0;
-  for (auto& kv : dmap) {
-    kv.second = nd++;
-    L.delta.push_back(std::get<0>(kv.first));
-    L.delta.push_back(std::get<1>(kv.first));
-    L.delta.push_back(std::get<2>(kv.first));
+  auto put = [&](std::map<std::tuple<int, int, int>, int>::iterator it) {
+    it->second = nd++;
+    L.delta.push_back(std::get<0>(it->first));
+    L.delta.push_back(std::get<1>(it->first));
+    L.delta.push_back(std::get<2>(it->first));
+  };
+  const auto zero = std::make_tuple(0, 0, 0);
+  for (auto it = dmap.begin(); it != dmap.end(); ++it) {
+    if (!(zero < it->first)) continue;
+    auto neg = dmap.find(std::make_tuple(-std::get<0>(it->first), -std::get<1>(it->first), -std::get<2>(it->first)));
+    if (neg == dmap.end()) continue;
+    put(it);
+    put(neg);
   }
+  L.n_dpair = nd / 2;
+  for (auto it = dmap.begin(); it != dmap.end(); ++it)
+    if (it->second < 0) put(it);
   for (int64_t b = 0; b < nb; ++b) {
     auto key = std::make_tuple(f->R2[3 * b] - f->R1[3 * b], f->R2[3 * b + 1] - f->R1[3 * b + 1],
                                f->R2[3 * b + 2] - f->R1[3 * b + 2]);

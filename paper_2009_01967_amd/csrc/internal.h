@@ -88,6 +88,7 @@ struct DevBuf {
 struct Fc3Layout {
   int64_t n_blocks = 0;
   int n_delta = 0;
+  int n_dpair = 0;  // leading slot pairs (2m, 2m + 1) holding Delta and -Delta
   std::vector<int> delta;            // [nD][3]
   // Blocks sorted by (delta, j, l); groups (delta, j, l) -> [start, end).
   DevBuf d_group;                    // int2 [nD * N * N]
