@@ -183,7 +183,9 @@ kaldo_status kaldo_phonons(kaldo_ctx ctx, const kaldo_structure* structure, cons
  *   gamma_out  [nT][Nk][n] linewidths [rad/ps], set averaged, or NULL (kept
  *              resident for kaldo_kappa_*)
  * Every precision is accepted on every grid.  Cells with n = 3 or 6 branches
- * and grid != {1,1,1} use a few-branch VALU kernel for FP64 and FP32; all
+ * and grid != {1,1,1} use a few-branch VALU kernel for FP64 and FP32 (in
+ * FP32 it sums each (Delta, -Delta) pair of fc3 cell offsets through the sum
+ * and difference of their two terms, whose phases are conjugate); all
  * other cases run the projection as MFMA GEMMs (Gamma: real, else complex). */
 kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double* T, int32_t nT,
                               double sigma_thz, kaldo_delta delta, kaldo_stats stats,
