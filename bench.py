@@ -198,6 +198,32 @@ def run_mfma(name, steps, warmup):
         res[label] = dict(ms=ms, kern=kern, ex=ex / steps, dense=dense / steps,
                           g=g_d.cpu().numpy().copy(), k=k_d.cpu().numpy().copy())
         log(f"{name} {label}: {ms:.2f} ms/step, kernels {kern}")
+    diff = None
+    if nk == 1:
+        # mode diffusivity from the FP64 linewidths of the last step: one call
+        # is the velocity matrices (three pairs of n x n FP64 GEMMs) plus the
+        # pair sum; the pair sum reads V_d (3 n^2 doubles) once per temperature
+        d_d = torch.empty((len(T), n, 3), dtype=torch.float64, device=dev)
+        kaldo._check(ctx.h, kaldo.kaldo_mode_diffusivity(ctx.h, d_d))
+        torch.cuda.synchronize()
+        kaldo.kaldo_profile_enable(ctx.h, True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            kaldo._check(ctx.h, kaldo.kaldo_mode_diffusivity(ctx.h, d_d))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tot, cnt = kaldo.kaldo_profile_read(ctx.h, "diffusivity")
+        kaldo.kaldo_profile_enable(ctx.h, False)
+        kms = tot / max(cnt, 1)
+        nbytes = len(T) * 3.0 * n * n * 8 + len(T) * n * 3 * 8
+        diff = {"ms_per_call": e0.elapsed_time(e1) / steps, "pair_sum_ms": kms,
+                "roofline": {"bound": "hbm", "kernel": "k_qhgk_diffusivity + k_diffusivity_reduce",
+                             "achieved": nbytes / (kms * 1e-3) / 1e9 if kms else None, "peak": 8000.0,
+                             "unit": "GB/s", "frac": nbytes / (kms * 1e-3) / 8e12 if kms else None,
+                             "traffic": None, "bytes_per_launch": nbytes}}
+        log(f"{name} mode diffusivity: {diff['ms_per_call']:.3f} ms per call, pair sum {kms:.3f} ms")
     ctx.close()
     lw = nk * n * len(T)
     f_c = 16.0 * nk * nk * n ** 4 if nk > 1 else 2.0 * n ** 4  # algorithmic GEMM flops, one V for both signs
@@ -236,6 +262,8 @@ def run_mfma(name, steps, warmup):
                                "mfma_tflops_issued": ex / sec / 1e12, "mfma_issued_frac": ex / sec / peak,
                                "dense_equivalent_tflops": f_c / sec / 1e12}
         out[label] = ent
+    if diff is not None:
+        out["mode_diffusivity"] = diff
     out["speedup_bf16x3_vs_fp64"] = res["fp64"]["ms"] / res["bf16x3"]["ms"]
     out["speedup_fp32_vs_fp64"] = res["fp64"]["ms"] / res["fp32"]["ms"]
     return out

@@ -12,6 +12,7 @@
  *                      phase_space, delta_deconstructed, and Gamma^0), giving
  *                     the linewidth gamma of every mode
  *   kaldo_kappa_rta   RTA conductivity of a crystal (Sec. II.B, eq. RTA)
+ *   kaldo_mode_diffusivity  mode diffusivity at Gamma (Sec. II.C)
  *   kaldo_kappa_qhgk  QHGK conductivity at Gamma (Sec. II.C,
  *                     eq. conductivity_amorphous .. lorentzian_amorphous)
  *
@@ -221,6 +222,18 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
  * with the displacement x_i - (x_j + R.cell). */
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
 
+/* Mode diffusivity at Gamma (paper Sec. II.C, eq. diffusivity_per_mode) from
+ * the last linewidths, per Cartesian direction a:
+ *   d_out [nT][n][3]  D_{mu,a} = sum_mu' |v_{mu mu' a}|^2 tau_{mu mu'} in mm^2/s,
+ * with the generalised velocity and Lorentzian lifetime of kaldo_kappa_qhgk.
+ * The printed prefactor 1/(N_k V) is not applied (with it the result would
+ * not have a diffusivity's units); in the classical limit
+ * k_B sum_mu D_{mu,a} = V kappa_aa.  Masked modes get 0.  d_out is a host or
+ * device pointer owned by the caller.
+ * Errors: KALDO_ESTATE before kaldo_linewidths, KALDO_EINVAL for a grid other
+ * than {1,1,1} or d_out == NULL. */
+kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out);
+
 /* Batches: the linewidths of many crystals (uneven cell sizes and grids) in
  * one HIP graph launch.
  *
@@ -284,7 +297,7 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
  * the library records a pair of HIP events on the context's stream around
  * every launch of its main kernels, named
  *   "dyn_assemble", "eigensolve", "step_a", "step_b", "gamma_sparse",
- *   "project", "finalize", "kappa_rta", "kappa_qhgk", and "batch_graph"
+ *   "project", "finalize", "kappa_rta", "kappa_qhgk", "diffusivity" and "batch_graph"
  *   around a kaldo_batch_run graph launch.
  * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables
  * and clears them.

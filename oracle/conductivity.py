@@ -9,6 +9,7 @@ Paper passages followed:
   v_{mu mu' a} v_{mu mu' b} tau_{mu mu'}.
 * Sec. II.C, eq. twod_heat_capacity, generalized_velocity, lorentzian_amorphous.
 * Sec. II.D: classical limit, c = c_{mu mu'} = k_B.
+* Sec. II.C, eq. diffusivity_per_mode: D_mu = sum_mu' v_{mu mu'} tau_{mu mu'} v_{mu mu'}.
 
 Readings of points the paper leaves open:
 * The printed generalised heat capacity (hbar w w'/T)(n - n')/(w - w') is
@@ -20,6 +21,9 @@ Readings of points the paper leaves open:
 * V is the unit-cell volume and N_k the grid size for RTA; for QHGK (Gamma
   point) V is the cell volume and N_k = 1.
 * Conductivity is in W/(m K); masked modes (nu < 0.01 THz) are excluded.
+* The diffusivity is given per Cartesian direction a (|v_{mu mu' a}|^2), in
+  mm^2/s, without the printed 1/(N_k V), which does not give a diffusivity's
+  units; with c = k_B it satisfies k_B sum_mu D_mu,a = V kappa_aa.
 """
 
 from __future__ import annotations
@@ -99,6 +103,30 @@ def lorentzian_lifetime(omega, gamma):
     dw = omega[:, None] - omega[None, :]
     with np.errstate(divide='ignore', invalid='ignore'):
         return g / (dw * dw + g * g)
+
+
+def mode_diffusivity(crystal, ph, gamma):
+    """Mode diffusivity at Gamma (Sec. II.C, eq. diffusivity_per_mode), per
+    Cartesian direction: D[t][mu][a] = sum_mu' |v_{mu mu' a}|^2 tau_{mu mu'}
+    in mm^2/s, with tau the Lorentzian lifetime of the QHGK conductivity at
+    the linewidths gamma[t].  The printed prefactor 1/(N_k V) would leave a
+    diffusivity in the wrong units; it is read as the normalisation of the
+    conductivity sum, not of D, and dropped.  gamma: (nT, 1, n) [rad/ps].
+    Masked modes have D = 0 (their velocities are zero).  Within a degenerate
+    set only the sum over the set is independent of the eigenvector basis, so
+    D is averaged over each set, as the linewidths are."""
+    assert ph.n_k == 1
+    v = generalized_velocity(crystal, ph)              # (3, n, n), A/ps
+    w = ph.omega[0]
+    n = len(w)
+    out = np.zeros((gamma.shape[0], n, 3))
+    for it in range(gamma.shape[0]):
+        tau = lorentzian_lifetime(w, gamma[it, 0])     # ps
+        for a in range(3):
+            out[it, :, a] = np.sum(np.where(np.abs(v[a]) > 0, np.abs(v[a]) ** 2 * tau, 0.0), axis=1)
+        for S in ph.sets[0]:
+            out[it, S, :] = out[it, S, :].mean(axis=0)
+    return out * 1e-2                                   # A^2/ps -> mm^2/s
 
 
 def kappa_qhgk(crystal, ph, gamma, T, stats='quantum'):

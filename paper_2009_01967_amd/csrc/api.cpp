@@ -565,6 +565,19 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {
   return KALDO_OK;
 }
 
+kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_mode_diffusivity before kaldo_linewidths");
+  if (ctx->nk != 1) return fail(ctx, KALDO_EINVAL, "kaldo_mode_diffusivity needs grid {1,1,1}");
+  if (!d_out) return fail(ctx, KALDO_EINVAL, "kaldo_mode_diffusivity: d_out is required");
+  kaldo_status st;
+  if ((st = run_mode_diffusivity(ctx)) != KALDO_OK) return st;
+  return copy_out(ctx, d_out, ctx->d_diff.p, (size_t)ctx->nT * ctx->nm * 3 * sizeof(double));
+}
+
 kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,
                              const kaldo_fc3* fc3, const int32_t grid[3], int32_t* handle) {
   if (!ctx) return KALDO_EINVAL;

@@ -206,6 +206,7 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_A;                 // step-A intermediate
   kaldo::DevBuf d_partial;           // partial sums
   kaldo::DevBuf d_kappa;             // double [nT][9]
+  kaldo::DevBuf d_diff;              // double [nT][n][3] mode diffusivity (Gamma)
   kaldo::DevBuf d_scratch2;
 };
 
@@ -248,5 +249,6 @@ kaldo_status run_phase_space(kaldo_ctx ctx, const double* T, int nT, double sigm
                              double** g_dev);
 kaldo_status run_kappa_rta(kaldo_ctx ctx);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
+kaldo_status run_mode_diffusivity(kaldo_ctx ctx);
 
 }  // namespace kaldo

@@ -165,8 +165,65 @@ __global__ void __launch_bounds__(256) k_qhgk_pairs(double* __restrict__ partial
   block_sum9<256>(acc, partial + ((size_t)t * gridDim.x + blockIdx.x) * 9);
 }
 
-kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
-  const int N = ctx->n_atoms, n = ctx->nm, nT = ctx->nT;
+// Mode diffusivity (Sec. II.C, eq. diffusivity_per_mode) per direction a:
+// D[t][s][a] = sum_u v_{s u a}^2 tau_{s u} in mm^2/s (the printed 1/(N_k V) is
+// not applied: it would not leave a diffusivity).  One thread per (s, t, u
+// slice): the lanes read consecutive s of V_d (coalesced) and slice z of the
+// grid sums u in [z * ul, (z + 1) * ul) into partial[z][t][s][a].
+__global__ void __launch_bounds__(256) k_qhgk_diffusivity(double* __restrict__ partial, const double* __restrict__ Vm,
+                                                          const double* __restrict__ omega,
+                                                          const double* __restrict__ gamma, int n, int nT, int ul) {
+  const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int t = blockIdx.y, z = blockIdx.z;
+  if (s >= n) return;
+  const size_t nn = (size_t)n * n;
+  const double* g = gamma + (size_t)t * n;
+  const double ws = omega[s];
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  if (ws / kTwoPi >= kNuMinThz) {
+    const int u1 = min(n, (z + 1) * ul);
+    for (int u = z * ul; u < u1; ++u) {
+      const double wu = omega[u];
+      if (wu / kTwoPi < kNuMinThz) continue;
+      const double gs = g[s] + g[u];
+      const double dw = ws - wu;
+      const double tau = gs / (dw * dw + gs * gs);
+      const double inv = 1.0 / (4.0 * ws * wu);  // 1 / (2 sqrt(w w'))^2
+      const size_t m = (size_t)u * n + s;
+      const double v0 = Vm[m], v1 = Vm[nn + m], v2 = Vm[2 * nn + m];
+      d0 += tau * inv * v0 * v0;
+      d1 += tau * inv * v1 * v1;
+      d2 += tau * inv * v2 * v2;
+    }
+  }
+  double* o = partial + (((size_t)z * nT + t) * n + s) * 3;
+  o[0] = d0;
+  o[1] = d1;
+  o[2] = d2;
+}
+
+// D[t][s][a] = 1e-2 (A^2/ps -> mm^2/s) times the sum over the nz slices of
+// partial[z][t][s][a], averaged over the degenerate set of s (a run of equal
+// set ids): within a set only the sum is independent of the eigenvector basis.
+__global__ void k_diffusivity_reduce(double* __restrict__ D, const double* __restrict__ partial,
+                                     const int* __restrict__ setid, int n, int nz, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int a = (int)(i % 3);
+  const int s = (int)((i / 3) % n);
+  const long long base = i - 3LL * s - a;  // element (t, 0, 0)
+  int lo = s, hi = s + 1;
+  while (lo > 0 && setid[lo - 1] == setid[s]) --lo;
+  while (hi < n && setid[hi] == setid[s]) ++hi;
+  double v = 0.0;
+  for (int u = lo; u < hi; ++u)
+    for (int z = 0; z < nz; ++z) v += partial[(size_t)z * count + base + 3 * u + a];
+  D[i] = 1e-2 * v / (hi - lo);
+}
+
+// V_d = E^T M_d E for d = 0..2 (column major, n x n each) in d_scratch2
+static kaldo_status qhgk_velocity(kaldo_ctx ctx, double** Vout, double** part_out) {
+  const int N = ctx->n_atoms, n = ctx->nm;
   const size_t nn = (size_t)n * n;
   hipStream_t st = ctx->stream;
   // real eigenvectors: column s of d_dyn (Gamma path keeps them real)
@@ -190,6 +247,17 @@ kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
                       n, &zero, M + d * nn, n) != rocblas_status_success)
       return fail(ctx, KALDO_EDEVICE, "rocblas_dgemm failed");
   }
+  *Vout = M;
+  *part_out = part;
+  return KALDO_OK;
+}
+
+kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
+  const int n = ctx->nm, nT = ctx->nT;
+  hipStream_t st = ctx->stream;
+  double *M = nullptr, *part = nullptr;
+  const kaldo_status vs = qhgk_velocity(ctx, &M, &part);
+  if (vs != KALDO_OK) return vs;
   const int nslice = 64;
   double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
@@ -202,6 +270,31 @@ kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
   hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(), part, nslice, nT,
                      kKappaSI / cell_volume(ctx->cell));
   KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
+kaldo_status run_mode_diffusivity(kaldo_ctx ctx) {
+  const int n = ctx->nm, nT = ctx->nT;
+  hipStream_t st = ctx->stream;
+  double *M = nullptr, *part = nullptr;
+  const kaldo_status vs = qhgk_velocity(ctx, &M, &part);
+  if (vs != KALDO_OK) return vs;
+  // u slices so that the grid holds about 2048 blocks (each at least 16 u)
+  const int bs = (int)blocks_for(n, 256);
+  int nz = std::max(1, std::min(2048 / std::max(1, bs * nT), (n + 15) / 16));
+  const int ul = (n + nz - 1) / nz;
+  nz = (n + ul - 1) / ul;
+  const long long count = (long long)nT * n * 3;
+  KALDO_HIP(ctx, ctx->d_diff.ensure((size_t)(nz + 1) * count * sizeof(double)));
+  double* D = ctx->d_diff.as<double>();
+  prof_begin(ctx);
+  hipLaunchKernelGGL(k_qhgk_diffusivity, dim3(bs, nT, nz), dim3(256), 0, st, D + count, M, ctx->d_omega.as<double>(),
+                     ctx->d_gamma.as<double>(), n, nT, ul);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_diffusivity_reduce, dim3(blocks_for(count, 256)), dim3(256), 0, st, D, D + count,
+                     ctx->d_setid.as<int>(), n, nz, count);
+  KALDO_HIP(ctx, hipGetLastError());
+  prof_end(ctx, "diffusivity");
   return KALDO_OK;
 }
 

@@ -47,7 +47,7 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
-            "kaldo_set_workspace", "kaldo_profile_flops"]
+            "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity"]
 
 
 class kaldo_structure(C.Structure):
@@ -108,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
+    lib.kaldo_mode_diffusivity.argtypes = [C.c_void_p, C.c_void_p]
+    lib.kaldo_mode_diffusivity.restype = C.c_int
     lib.kaldo_batch_add.argtypes = [C.c_void_p, C.POINTER(kaldo_structure), C.POINTER(kaldo_fc2),
                                     C.POINTER(kaldo_fc3), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.kaldo_batch_add.restype = C.c_int
@@ -254,6 +256,10 @@ def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
 
 def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_qhgk(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_mode_diffusivity(ctx, d_out) -> int:
+    return load_library().kaldo_mode_diffusivity(ctx, _out_ptr(d_out))
 
 
 def kaldo_batch_add(ctx, structure, fc2, fc3, grid):
@@ -435,4 +441,12 @@ class Context:
         if want_host and out is None:
             out = np.zeros((self.nT, 3, 3))
         _check(self.h, kaldo_kappa_qhgk(self.h, out))
+        return out
+
+    def mode_diffusivity(self, out=None):
+        """[nT][n][3] mode diffusivity at Gamma in mm^2/s (host array unless a
+        device tensor is given)."""
+        if out is None:
+            out = np.zeros((self.nT, self.n, 3))
+        _check(self.h, kaldo_mode_diffusivity(self.h, out))
         return out

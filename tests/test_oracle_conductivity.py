@@ -8,7 +8,7 @@ import pytest
 
 from gen import diamond_si
 from gen.crystals import M_SI, M_GE
-from oracle import phonons as P, anharmonic as A, conductivity as C
+from oracle import phonons as P, anharmonic as A, conductivity as C, units
 from tests.supercell import fold
 
 HBAR = 6.582119569e-4
@@ -103,3 +103,40 @@ def test_rta_kappa_classical_capacity_is_kb():
     V = abs(np.linalg.det(c.cell))
     expect = KB / 0.02 * np.einsum('ksab->ab', ph.vv) / (ph.n_k * V) * 1.602176634e3
     assert np.allclose(kc, expect, rtol=1e-12)
+
+
+def test_diffusivity_sums_to_classical_qhgk_kappa(folded):
+    """With c = k_B for every pair (classical limit), the QHGK conductivity is
+    k_B / V times the summed mode diffusivities: k_B sum_mu D_mu,a = V kappa_aa."""
+    _, _, sc, phs = folded
+    rng = np.random.default_rng(7)
+    g = np.where(phs.mask, 0.05 + 0.2 * rng.random(phs.omega.shape), 0.0)[None]
+    D = C.mode_diffusivity(sc, phs, g)[0]                       # (n, 3) mm^2/s
+    k = C.kappa_qhgk(sc, phs, g, [300.0], stats="classical")[0]
+    lhs = units.KB * D.sum(axis=0) * 1e2 * units.KAPPA_TO_SI   # back to A^2/ps
+    rhs = C.volume(sc) * np.diag(k)
+    assert np.allclose(lhs, rhs, rtol=1e-12), (lhs, rhs)
+    assert (D >= 0).all()
+    assert np.all(D[~phs.mask[0]] == 0.0)
+
+
+@pytest.mark.parametrize("scale", [1e-4, 1e-6])
+def test_diffusivity_on_folded_crystal_matches_group_velocities(folded, scale):
+    """In a folded supercell with small linewidths that depend on frequency
+    only, the off-diagonal Lorentzian terms vanish as (gamma / dw)^2 and the
+    summed diffusivity tends to sum_{k,s} v_ks,a^2 / (2 gamma_ks) of the
+    primitive crystal, which its classical RTA conductivity carries:
+    sum_mu D_mu,a = N_k V kappa_RTA,aa / k_B."""
+    c, ph, sc, phs = folded
+
+    def gfun(w):
+        return scale * (0.2 + 0.01 * w + 1e-3 * w * w)
+
+    g_c = np.where(ph.mask, gfun(ph.omega), 0.0)[None]
+    g_s = np.where(phs.mask, gfun(phs.omega), 0.0)[None]
+    D = C.mode_diffusivity(sc, phs, g_s)[0]
+    k_rta = C.kappa_rta(c, ph, g_c, [300.0], stats="classical")[0]
+    lhs = D.sum(axis=0) * 1e2
+    rhs = c.n_k * C.volume(c) * np.diag(k_rta) / (units.KB * units.KAPPA_TO_SI)
+    tol = 50 * scale + 1e-9
+    assert np.allclose(lhs, rhs, rtol=tol), (lhs, rhs)
