@@ -279,9 +279,10 @@ kaldo_status run_mode_diffusivity(kaldo_ctx ctx) {
   double *M = nullptr, *part = nullptr;
   const kaldo_status vs = qhgk_velocity(ctx, &M, &part);
   if (vs != KALDO_OK) return vs;
-  // u slices so that the grid holds about 2048 blocks (each at least 16 u)
+  // u slices so that the grid holds about 1024 blocks (each at least 32 u):
+  // more slices make the reduction below latency-bound
   const int bs = (int)blocks_for(n, 256);
-  int nz = std::max(1, std::min(2048 / std::max(1, bs * nT), (n + 15) / 16));
+  int nz = std::max(1, std::min(1024 / std::max(1, bs * nT), (n + 31) / 32));
   const int ul = (n + nz - 1) / nz;
   nz = (n + ul - 1) / ul;
   const long long count = (long long)nT * n * 3;
