@@ -254,8 +254,11 @@ kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out);
  * The context's stream must not be the null stream (pass NULL to kaldo_create
  * to get an owned one).  gamma_out, if not NULL, holds one pointer per crystal
  * in handle order, each to [nT][Nk_i][n_i] doubles (host or device memory) or
- * NULL to skip that crystal.  Returns KALDO_ESTATE for an empty batch and the
- * first failing crystal's status otherwise.
+ * NULL to skip that crystal.  Returns KALDO_ESTATE for an empty batch, and for
+ * arguments other than those the batch's graph was captured with (a context
+ * captures one graph per batch: kaldo_batch_clear and add the crystals again,
+ * or use a second context, for other arguments); the first failing crystal's
+ * status otherwise.
  *
  * kaldo_batch_clear releases every crystal of the batch and the graph. */
 kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,

@@ -408,9 +408,19 @@ kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream) {
   return KALDO_OK;
 }
 
-static void batch_release(kaldo_ctx ctx) {
-  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+// Destroy the captured batch graph once the stream has drained (a launch of it
+// may still be in flight).
+static void batch_drop_graph(kaldo_ctx ctx) {
+  if (ctx->batch_exec) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipGraphExecDestroy(ctx->batch_exec);
+  }
   ctx->batch_exec = nullptr;
+  ctx->batch_key.clear();
+}
+
+static void batch_release(kaldo_ctx ctx) {
+  batch_drop_graph(ctx);
   ctx->batch_key.clear();
   for (kaldo_ctx sub : ctx->batch) kaldo_destroy(sub);
   ctx->batch.clear();
@@ -597,9 +607,7 @@ kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, co
     kaldo_destroy(sub);
     return fail(ctx, st, msg);
   }
-  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
-  ctx->batch_exec = nullptr;
-  ctx->batch_key.clear();
+  batch_drop_graph(ctx);
   ctx->batch.push_back(sub);
   *handle = (int32_t)ctx->batch.size() - 1;
   return KALDO_OK;
@@ -667,10 +675,11 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
     sub->delta = KALDO_DELTA_GAUSS;
     sub->have_gamma = false;
   }
-  if (!ctx->batch_exec || key != ctx->batch_key) {
-    if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
-    ctx->batch_exec = nullptr;
-    ctx->batch_key.clear();
+  if (ctx->batch_exec && key != ctx->batch_key)
+    return fail(ctx, KALDO_ESTATE,
+                "kaldo_batch_run: the batch holds a graph captured with other arguments; re-capturing on the same "
+                "context is not supported (kaldo_batch_clear, or a new context, for other arguments)");
+  if (!ctx->batch_exec) {
     if ((st = batch_capture(ctx, sigma_thz, precision)) != KALDO_OK) return st;
     ctx->batch_key = key;
   }
@@ -731,9 +740,7 @@ kaldo_status kaldo_batch_set_k_range(kaldo_ctx ctx, int32_t handle, int32_t k_be
     return fail(ctx, KALDO_EINVAL, "kaldo_batch_set_k_range: need 0 <= k_begin < min(k_end, N_k)");
   sub->k_begin = k_begin;
   sub->k_end = k_end;
-  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);  // the captured launches change
-  ctx->batch_exec = nullptr;
-  ctx->batch_key.clear();
+  batch_drop_graph(ctx);  // the captured launches change
   return KALDO_OK;
 }
 

@@ -92,6 +92,12 @@ def test_batch_errors():
         ctx.batch_add(c)
         st = kaldo.kaldo_batch_run(ctx.h, T, -1.0, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
         assert st == kaldo.KALDO_EINVAL
+        # a graph captured with one set of arguments is not re-captured with
+        # others on the same context
+        kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None))
+        st = kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP64, None)
+        assert st == kaldo.KALDO_ESTATE
+        kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None))
         kaldo._check(ctx.h, kaldo.kaldo_batch_clear(ctx.h))
         st = kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
         assert st == kaldo.KALDO_ESTATE

@@ -140,3 +140,82 @@ def test_diffusivity_on_folded_crystal_matches_group_velocities(folded, scale):
     rhs = c.n_k * C.volume(c) * np.diag(k_rta) / (units.KB * units.KAPPA_TO_SI)
     tol = 50 * scale + 1e-9
     assert np.allclose(lhs, rhs, rtol=tol), (lhs, rhs)
+
+
+# ---- the Lorentzian generalised lifetime off the diagonal (Sec. II.C, eq. lorentzian_amorphous)
+
+def test_lorentzian_half_maximum_at_summed_linewidths():
+    """As a function of the frequency gap, tau_{mu mu'} peaks at 1/(gamma + gamma')
+    and falls to half of that where |w - w'| = gamma + gamma': this fixes the
+    scale of the gap against the linewidths."""
+    for a, b in ((0.3, 0.1), (0.05, 2.0), (1.0, 1.0)):
+        g = a + b
+        w = np.array([7.0, 7.0, 7.0 + g, 7.0 - g])
+        gam = np.array([a, b, b, b])
+        tau = C.lorentzian_lifetime(w, gam)
+        assert tau[0, 1] == pytest.approx(1.0 / g, rel=1e-14)       # zero gap: the peak
+        assert tau[0, 2] == pytest.approx(0.5 / g, rel=1e-14)       # gap +g: half maximum
+        assert tau[0, 3] == pytest.approx(0.5 / g, rel=1e-14)       # gap -g
+        assert np.allclose(tau, tau.T, rtol=1e-15)
+
+
+def test_lorentzian_area_over_the_gap_is_pi():
+    """Integrated over the gap w - w' on a dense grid, tau_{mu mu'} has area
+    2 arctan(L / g) over [-L, L] (-> pi): its normalisation as a line shape."""
+    a, b = 0.2, 0.35
+    g = a + b
+    L = 50.0 * g
+    x = np.linspace(-L, L, 4001)
+    w = np.concatenate(([0.0], x))
+    gam = np.concatenate(([a], np.full(x.size, b)))
+    tau = C.lorentzian_lifetime(w, gam)[0, 1:]
+    h = x[1] - x[0]
+    area = h * (tau.sum() - 0.5 * (tau[0] + tau[-1]))              # trapezoid rule
+    assert area == pytest.approx(2.0 * np.arctan(L / g), rel=1e-9)
+    assert area == pytest.approx(np.pi, rel=2.0 / 50.0)
+
+
+def _two_mode_cell():
+    """One atom (mass 4 amu) in a cubic 5 A cell with fc2 blocks on the +x and
+    -x images: B = 0.3 eV/A^2 in entry (x, y) for R = +x, its transpose for
+    R = -x.  The displacement Hessian of the generalised velocity is then
+    M_x[0][1] = -5 * 0.3 / 4 and M_x[1][0] = +5 * 0.3 / 4 (in eV/(A amu)),
+    and zero elsewhere."""
+    from gen.crystals import Crystal
+    B = np.zeros((3, 3))
+    B[0, 1] = 0.3
+    return Crystal(
+        name="two-mode", cell=5.0 * np.eye(3), positions=np.zeros((1, 3)), masses=np.array([4.0]),
+        fc2_i=np.array([0, 0], np.int32), fc2_j=np.array([0, 0], np.int32),
+        fc2_R=np.array([[1, 0, 0], [-1, 0, 0]], np.int32), fc2_val=np.stack([B, B.T]),
+        fc3_i=np.zeros(0, np.int32), fc3_j=np.zeros(0, np.int32), fc3_l=np.zeros(0, np.int32),
+        fc3_R1=np.zeros((0, 3), np.int32), fc3_R2=np.zeros((0, 3), np.int32),
+        fc3_val=np.zeros((0, 3, 3, 3)), grid=(1, 1, 1))
+
+
+def _two_mode_phonons():
+    """Modes 10, 12 and 30 rad/ps with the unit vectors as eigenvectors."""
+    w = np.array([[10.0, 12.0, 30.0]])
+    return P.Phonons(grid=(1, 1, 1), q=np.zeros((1, 3)), omega=w, eigvec=np.eye(3, dtype=complex)[None],
+                     mask=np.ones((1, 3), bool), sets=[[np.array([0]), np.array([1]), np.array([2])]],
+                     velocity=np.zeros((1, 3, 3)), vv=np.zeros((1, 3, 3, 3)))
+
+
+def test_hand_worked_two_mode_qhgk_and_diffusivity():
+    """Worked by hand: v_{01x} = M_x[0][1] / (2 sqrt(10 * 12)) = -1.5 eV / (8 sqrt(120)),
+    with gamma = (0.5, 1.5, 0.2) rad/ps the pair lifetime is
+    tau_01 = 2 / ((10 - 12)^2 + 2^2) = 0.25 ps (the gap equals the summed
+    linewidths, so the off-diagonal Lorentzian is at half maximum).  The only
+    nonzero velocities are v_01 = -v_10, so in the classical limit
+    kappa_xx = 2 k_B tau_01 v_01^2 / V and D_0x = D_1x = v_01^2 tau_01."""
+    c, ph = _two_mode_cell(), _two_mode_phonons()
+    g = np.array([[[0.5, 1.5, 0.2]]])
+    v01 = 1.5 * units.EV_IN_AMU_A2_PS2 / (8.0 * np.sqrt(120.0))      # A/ps
+    k = C.kappa_qhgk(c, ph, g, [300.0], stats="classical")[0]
+    expect = 2.0 * units.KB * 0.25 * v01 ** 2 / 125.0 * units.KAPPA_TO_SI
+    assert k[0, 0] == pytest.approx(expect, rel=1e-13)
+    assert np.abs(k.ravel()[1:]).max() < 1e-13 * expect
+    D = C.mode_diffusivity(c, ph, g)[0]
+    assert D[0, 0] == pytest.approx(v01 ** 2 * 0.25 * 1e-2, rel=1e-13)
+    assert D[1, 0] == pytest.approx(v01 ** 2 * 0.25 * 1e-2, rel=1e-13)
+    assert np.abs(D[2]).max() == 0.0 and np.abs(D[:, 1:]).max() == 0.0
