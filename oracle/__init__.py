@@ -23,8 +23,14 @@ Disordered Solids" (arXiv:2009.01967) literally, in float64, with NumPy/LAPACK:
                       eqs. conductivity_amorphous .. lorentzian_amorphous), and
                       the classical limit (Sec. II.D).
 
+* ``scattering``   -- the full linearised BTE: the off-diagonal operator
+                      Gamma^1 (Sec. II.B), the conductivity by direct inversion
+                      (eqs. inversemeanfreepath, full_conductivity) and by the
+                      self-consistent series (eqs. mfp_from_scattering_inv,
+                      self-consistent).
+
 Readings of points the paper leaves open are listed in each module's header.
 Every function here is pinned by tests that do not re-type its formula.
 """
 
-from . import units, phonons, anharmonic, conductivity  # noqa: F401
+from . import units, phonons, anharmonic, conductivity, scattering  # noqa: F401
