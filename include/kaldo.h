@@ -215,6 +215,22 @@ kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, doubl
  * Requires a grid other than {1,1,1}. */
 kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
 
+/* kaldo_kappa_rta without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result as kaldo_kappa_rta, computed by the same
+ * kernels, but the partial sums and the reduced kappa live in a static device
+ * array of the library (KALDO_MAX_T * 65 * 9 doubles, 37 KB, one per device,
+ * held until the process ends) instead of context buffers; nothing is
+ * allocated or freed and no context buffer is touched.
+ *   kappa_out [nT][3][3] W/(m K), host or device memory, required.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (several host threads, or several streams in flight) race; calls in
+ * order on one stream do not.  Each call writes every entry it later reads.
+ * Errors: KALDO_ESTATE before kaldo_linewidths, KALDO_EINVAL for a grid
+ * {1,1,1}, kappa_out == NULL or more scratch than the array holds,
+ * KALDO_EDEVICE if the array's device address could not be obtained. */
+kaldo_status kaldo_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
+
 /* QHGK conductivity (paper Sec. II.C) at Gamma from the last linewidths:
  *   kappa_out [nT][3][3] W/(m K).  Requires grid {1,1,1}; V is the cell volume.
  * Generalised heat capacity with the sign that makes it positive,

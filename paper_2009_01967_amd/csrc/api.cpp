@@ -404,6 +404,9 @@ kaldo_status kaldo_create(kaldo_ctx* out, int device, void* hip_stream) {
     return KALDO_EDEVICE;
   }
   rocblas_set_stream(ctx->blas, ctx->stream);
+  // device address of the allocation-free entry point's scratch array (its
+  // failure only disables kaldo_kappa_rta_noalloc, which then reports it)
+  (void)noalloc_setup(device);
   *out = ctx;
   return KALDO_OK;
 }
@@ -560,6 +563,16 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
   if ((st = run_kappa_rta(ctx)) != KALDO_OK) return st;
   if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
   return KALDO_OK;
+}
+
+kaldo_status kaldo_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_gamma) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_rta_noalloc before kaldo_linewidths");
+  if (ctx->nk == 1) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_rta_noalloc needs a grid other than {1,1,1}");
+  if (!kappa_out) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_rta_noalloc: kappa_out is required");
+  return run_kappa_rta_noalloc(ctx, kappa_out);
 }
 
 kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out) {

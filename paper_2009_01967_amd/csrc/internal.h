@@ -248,6 +248,10 @@ kaldo_status run_linewidths_crystal(kaldo_ctx ctx, double sigma_thz, int precisi
 kaldo_status run_phase_space(kaldo_ctx ctx, const double* T, int nT, double sigma_thz, int delta, int stats,
                              double** g_dev);
 kaldo_status run_kappa_rta(kaldo_ctx ctx);
+// allocation-free RTA: the device address of the static scratch array of the
+// current device (once per device), and the entry point's work
+hipError_t noalloc_setup(int device);
+kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 kaldo_status run_mode_diffusivity(kaldo_ctx ctx);
 

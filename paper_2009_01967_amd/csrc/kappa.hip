@@ -4,6 +4,8 @@
 // All accumulation is FP64 with fixed-order (deterministic) reductions.
 #include <rocblas/rocblas.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "internal.h"
 
@@ -98,6 +100,70 @@ kaldo_status run_kappa_rta(kaldo_ctx ctx) {
                      ctx->d_partial.as<double>(), nslice, nT, scale);
   KALDO_HIP(ctx, hipGetLastError());
   return KALDO_OK;
+}
+
+// ---- RTA without allocation ----------------------------------------------------------
+// kaldo_kappa_rta_noalloc keeps its slice partials and the reduced kappa in
+// this file-scope device array instead of context buffers.  Each device the
+// library runs on holds its own copy for the life of the process.  In host
+// code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current (noalloc_setup, called by kaldo_create) and kept below.
+constexpr int kNoAllocSlices = 64;
+constexpr size_t kNoAllocDoubles = (size_t)KALDO_MAX_T * (kNoAllocSlices + 1) * 9;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_err[device];
+}
+
+kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out) {
+  const int nT = ctx->nT;
+  const size_t need = (size_t)nT * (kNoAllocSlices + 1) * 9;
+  if (need > kNoAllocDoubles)
+    return fail(ctx, KALDO_EINVAL,
+                "kaldo_kappa_rta_noalloc: " + std::to_string(need) + " doubles of scratch needed, at most " +
+                    std::to_string(kNoAllocDoubles));
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices && g_scratch_done[ctx->device])
+      base = static_cast<double*>(g_scratch_ptr[ctx->device]);
+  }
+  if (!base) return fail(ctx, KALDO_EDEVICE, "kaldo_kappa_rta_noalloc: no device address of the scratch array");
+  double* partial = base;                                       // [nT][slices][9]
+  double* kappa = base + (size_t)KALDO_MAX_T * kNoAllocSlices * 9;  // [nT][9]
+  const int nmode = ctx->nk * ctx->nm;
+  hipStream_t st = ctx->stream;
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  // every slice of every temperature is written by the first kernel, every
+  // kappa entry by the second: nothing left from an earlier call is read
+  hipLaunchKernelGGL(k_kappa_rta, dim3(kNoAllocSlices, nT), dim3(256), 0, st, partial, ctx->d_gamma.as<double>(),
+                     ctx->d_omega.as<double>(), ctx->d_vv.as<double>(), nmode, ctx->g_lo * ctx->nm,
+                     ctx->g_hi * ctx->nm, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  const double scale = kKappaSI / (ctx->nk * cell_volume(ctx->cell));
+  hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, kappa, partial, kNoAllocSlices, nT, scale);
+  KALDO_HIP(ctx, hipGetLastError());
+  return copy_out(ctx, kappa_out, kappa, (size_t)nT * 9 * sizeof(double));
 }
 
 // ---- QHGK ---------------------------------------------------------------------------

@@ -47,7 +47,8 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
-            "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity"]
+            "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity",
+            "kaldo_kappa_rta_noalloc"]
 
 
 class kaldo_structure(C.Structure):
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_phase_space.restype = C.c_int
     lib.kaldo_kappa_rta.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_rta.restype = C.c_int
+    lib.kaldo_kappa_rta_noalloc.argtypes = [C.c_void_p, C.c_void_p]
+    lib.kaldo_kappa_rta_noalloc.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
     lib.kaldo_mode_diffusivity.argtypes = [C.c_void_p, C.c_void_p]
@@ -252,6 +255,10 @@ def kaldo_phase_space(ctx, T: Sequence[float], sigma_thz: float, delta: int = KA
 
 def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
     return load_library().kaldo_kappa_rta(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_kappa_rta_noalloc(ctx, kappa_out) -> int:
+    return load_library().kaldo_kappa_rta_noalloc(ctx, _out_ptr(kappa_out))
 
 
 def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
