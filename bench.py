@@ -428,6 +428,45 @@ def run_next2(steps=3):
     return out
 
 
+def run_next1(methods=("inverse", "self-consistent"), max_terms=200):
+    """The full linearised BTE on the headline workload (kaldo_kappa_bte): the
+    FP64 off-diagonal scattering operator of all 24 576 modes at the three
+    temperatures, solved by LU on the time-reversal-odd set vectors and by the
+    self-consistent series, beside the RTA of the same linewidths."""
+    import torch
+    from gen import workload, WORKLOADS
+    from paper_2009_01967_amd import kaldo
+    w = WORKLOADS[WORKLOAD]
+    c = workload(WORKLOAD)
+    T, sigma = list(w["T"]), w["sigma_thz"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    out = {"workload": WORKLOAD, "T_K": T, "operator": "fp64"}
+    with kaldo.Context(0, stream.cuda_stream) as ctx:
+        ctx.phonons(c)
+        ctx.linewidths(c, T=T, sigma_thz=sigma, precision="fp64", want_host=False)
+        k_rta = ctx.kappa_rta()
+        out["kappa_rta_diag"] = [list(np.diag(k)) for k in k_rta]
+        for m in methods:
+            kaldo.kaldo_profile_enable(ctx.h, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k, terms, ok = ctx.kappa_bte(m, max_terms=max_terms, tol=1e-12)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            kern = {}
+            for name in ("bte_scatter", "bte_operator", "bte_solve"):
+                tot, cnt = kaldo.kaldo_profile_read(ctx.h, name)
+                kern[name] = tot
+            kaldo.kaldo_profile_enable(ctx.h, False)
+            out[m] = {"ms_per_call": wall, "kernels_ms": kern, "terms": terms, "converged": ok,
+                      "kappa_diag": [list(np.diag(x)) for x in k],
+                      "kappa_over_rta_xx": [float(x[0, 0] / r[0, 0]) for x, r in zip(k, k_rta)]}
+            log(f"next1 {m}: {wall:.1f} ms, terms {terms}, converged {ok}, kernels {kern}, "
+                f"kappa/rta {out[m]['kappa_over_rta_xx']}")
+    return out
+
+
 def run_section(flags, key):
     """One optional section of the benchmark (the MFMA workloads or the batch)
     in a child process, so that a failure there costs that section only.  The
@@ -516,6 +555,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
     ap.add_argument("--no-next2", action="store_true",
                     help="skip the Lorentzian/triangle linewidths and the phase space on the headline workload")
+    ap.add_argument("--no-next1", action="store_true",
+                    help="skip the full linearised BTE (inverse and self-consistent) on the headline workload")
     ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
     ap.add_argument("--plain", metavar="WORKLOAD", help="run one workload through the library alone "
                     "(torch initialises the GPU but hands the library no stream or tensor; for rocprofv3 "
@@ -613,6 +654,8 @@ def main():
     }
     if not args.no_next2:
         out["next2"] = run_next2()
+    if not args.no_next1:
+        out["next1"] = run_next1()
     for key, (val, why) in sections.items():
         if val is not None:
             out[key] = val

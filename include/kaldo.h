@@ -71,7 +71,8 @@ typedef enum {
   KALDO_ENOMEM = -2,    /* device allocation failed */
   KALDO_EDEVICE = -3,   /* HIP / rocSOLVER runtime error */
   KALDO_ESTATE = -4,    /* call out of order (no phonons / linewidths yet) */
-  KALDO_EUNSTABLE = -5  /* imaginary mode below -0.05 THz (offending k, s in error text) */
+  KALDO_EUNSTABLE = -5, /* imaginary mode below -0.05 THz (offending k, s in error text) */
+  KALDO_ENOCONV = -6    /* the self-consistent series of kaldo_kappa_bte did not converge */
 } kaldo_status;
 
 typedef enum {
@@ -100,6 +101,15 @@ typedef enum {
   KALDO_TUNE_FIXED = 1, /* fixed tile shapes: results bitwise reproducible across contexts */
   KALDO_TUNE_SHAPE0 = 2 /* KALDO_TUNE_SHAPE0 + v: tile shape v (0 .. 15) of every GEMM (for tests) */
 } kaldo_tuning;
+
+/* How kaldo_kappa_bte solves the full linearised BTE (paper Sec. II.B):
+ * direct inversion of the scattering operator (eqs. inversemeanfreepath,
+ * full_conductivity) or the self-consistent series (eqs.
+ * mfp_from_scattering_inv, self-consistent). */
+typedef enum {
+  KALDO_BTE_INVERSE = 0,
+  KALDO_BTE_SELF_CONSISTENT = 1
+} kaldo_bte_method;
 
 /* At most this many temperatures per kaldo_linewidths call. */
 #define KALDO_MAX_T 8
@@ -214,6 +224,39 @@ kaldo_status kaldo_phase_space(kaldo_ctx ctx, const double* T, int32_t nT, doubl
  *   invariant Re Tr(W_a W_b) / (4 omega^2), W = E_set^H dD/dq E_set.
  * Requires a grid other than {1,1,1}. */
 kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out);
+
+/* Conductivity of the full linearised BTE (paper Sec. II.B) with the
+ * off-diagonal scattering operator, for the temperatures, delta, statistics
+ * and grid of the last kaldo_linewidths call (its fc3 resident):
+ *   Gamma^1_mu nu = (w_nu / w_mu) (1/N_k) sum_mu'' [Gamma+_mu nu mu'' - Gamma+_mu mu'' nu
+ *                   - 1/2 Gamma-_mu nu mu'' - 1/2 Gamma-_mu mu'' nu],
+ * the coefficients of the linearised scattering term of Sec. II.B (with the
+ * 1/N_k and the 1/2 on creation that the linewidth Gamma^0 carries), and
+ *   kappa = 1/(N_k V) sum c_mu v_mu [2 (Gamma^0 + Gamma^1)]^-1_mu nu v_nu,
+ * the factor 2 making Gamma^1 = 0 the RTA of kaldo_kappa_rta (tau = 1/(2 gamma)).
+ * Within each degenerate set only set sums of the operator are basis
+ * independent: it acts on the set means of the deviation (block sums over
+ * the row and column sets) and the rest of each set relaxes with its linewidth
+ * (RTA); heat capacity and Gamma^0 are set averages.  The set means are solved
+ * on the vectors odd under k -> -k (the velocity is odd; this halves the system
+ * and leaves out the near-zero mode of uniform deviations).
+ *   method     KALDO_BTE_INVERSE: LU factorisation (rocSOLVER), or
+ *              KALDO_BTE_SELF_CONSISTENT: partial sums of
+ *              sum_n (-Gamma^1 / Gamma^0)^n v / (2 Gamma^0) until the last term
+ *              is at most tol times the sum (largest entries), at most
+ *              max_terms terms (>= 1)
+ *   kappa_out  [nT][3][3] W/(m K), host or device memory, required
+ *   terms_out  terms of the series (the most over the temperatures), 0 for
+ *              the inverse; may be NULL
+ * The operator is computed in FP64 whatever the precision of the last
+ * linewidths; it takes 3 N_k^2 n^2 doubles per temperature.  Cells with 1 or
+ * 2 atoms (n = 3 or 6) on grids other than {1,1,1}, without a k range.
+ * Errors: KALDO_ESTATE before kaldo_linewidths; KALDO_EINVAL for other cells,
+ * a k range, bad arguments; KALDO_EUNSTABLE for a singular operator;
+ * KALDO_ENOCONV when the series has not converged after max_terms terms
+ * (kappa_out then holds the last partial sum). */
+kaldo_status kaldo_kappa_bte(kaldo_ctx ctx, kaldo_bte_method method, int32_t max_terms, double tol,
+                             double* kappa_out, int32_t* terms_out);
 
 /* kaldo_kappa_rta without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that

@@ -20,7 +20,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkaldo.so")
 PEAKS = os.path.join(HERE, "libpeaks.so")
 
-SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip", "phase.hip"]
+SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip", "phase.hip",
+           "bte.hip"]
 
 ARCH = "gfx950"
 COMMON = [

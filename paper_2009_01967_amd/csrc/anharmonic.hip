@@ -524,6 +524,47 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   return KALDO_OK;
 }
 
+// FP64 tables of the few-branch path (the same layout as linewidths_small),
+// for the scattering operator of the full BTE.
+kaldo_status small_tables_fp64(kaldo_ctx ctx, SmallTables* t) {
+  const int n = ctx->nm, nk = ctx->nk, nT = ctx->nT, nd = ctx->fc3.n_delta;
+  hipStream_t st = ctx->stream;
+  const int TB = 256;
+  const size_t nmode = (size_t)nk * n;
+  const size_t tab_bytes = (2 + (size_t)nT) * nmode * sizeof(double);
+  const size_t ph_bytes = (size_t)nd * nk * sizeof(cplx<double>);
+  const size_t et_bytes = (size_t)n * n * nk * sizeof(cplx<double>);
+  KALDO_HIP(ctx, ctx->d_tabs.ensure(tab_bytes + ph_bytes + et_bytes + 256));
+  t->OM = ctx->d_tabs.as<double>();
+  t->IW = t->OM + nmode;
+  t->OCC = t->IW + nmode;
+  t->PH = reinterpret_cast<cplx<double>*>(t->OCC + (size_t)nT * nmode);
+  t->ET = t->PH + (size_t)nd * nk;
+  double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
+  double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
+  hipLaunchKernelGGL(k_tables, dim3(blocks_for((long long)nmode, TB)), dim3(TB), 0, st, t->OM, t->IW, t->OCC,
+                     ctx->d_omega.as<double>(), nk, n, nT, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL((k_delta_phase<double>), dim3(blocks_for((long long)nd * nk, TB)), dim3(TB), 0, st, t->PH,
+                     ctx->fc3.d_delta.as<int>(), nd, ctx->grid[0], ctx->grid[1], ctx->grid[2]);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL((k_evec_transpose<double>), dim3(blocks_for((long long)n * n * nk, TB)), dim3(TB), 0, st,
+                     t->ET, ctx->d_evec.as<cplx<double>>(), nk, n);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
+// Step A (FP64, single Delta slots) of first-mode points [k0, k0 + kc) into A.
+kaldo_status small_step_a_fp64(kaldo_ctx ctx, cplx<double>* A, int k0, int kc) {
+  const int N = ctx->n_atoms, n = ctx->nm, nd = ctx->fc3.n_delta;
+  hipLaunchKernelGGL((k_step_a<double>), dim3(blocks_for((long long)n * nd * N * N * kc, 256)), dim3(256), 0,
+                     ctx->stream, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(),
+                     ctx->fc3.d_blk_i.as<int>(), ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd,
+                     ctx->grid[0], ctx->grid[1], ctx->grid[2], k0, kc);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
 // Mode tables and the Delta phase table (FP64) for the many-branch crystal path.
 kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double** OCC, cplx<double>** PH) {
   const int n = ctx->nm, nk = ctx->nk, nT = ctx->nT, nd = ctx->fc3.n_delta;

@@ -525,6 +525,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
   for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
   ctx->stats = stats;
   ctx->delta = delta;
+  ctx->sigma_thz = sigma_thz;
   ctx->have_gamma = false;
   if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
   ctx->g_lo = k_lo(ctx);
@@ -563,6 +564,29 @@ kaldo_status kaldo_kappa_rta(kaldo_ctx ctx, double* kappa_out) {
   if ((st = run_kappa_rta(ctx)) != KALDO_OK) return st;
   if (kappa_out) return copy_out(ctx, kappa_out, ctx->d_kappa.p, (size_t)ctx->nT * 9 * sizeof(double));
   return KALDO_OK;
+}
+
+kaldo_status kaldo_kappa_bte(kaldo_ctx ctx, kaldo_bte_method method, int32_t max_terms, double tol,
+                             double* kappa_out, int32_t* terms_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (terms_out) *terms_out = 0;
+  if (!ctx->have_gamma || !ctx->have_fc3) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_bte before kaldo_linewidths");
+  if (method != KALDO_BTE_INVERSE && method != KALDO_BTE_SELF_CONSISTENT)
+    return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: unknown method");
+  if (method == KALDO_BTE_SELF_CONSISTENT && (max_terms < 1 || !(tol > 0.0) || !std::isfinite(tol)))
+    return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: need max_terms >= 1 and tol > 0");
+  if (!kappa_out) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: kappa_out is required");
+  if (ctx->nk == 1) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte needs a grid other than {1,1,1}");
+  if (ctx->nm != 3 && ctx->nm != 6)
+    return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: implemented for cells of 1 or 2 atoms");
+  if (k_partial(ctx)) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: needs the whole grid (no k range)");
+  int terms = 0;
+  const kaldo_status st = run_kappa_bte(ctx, method, max_terms, tol, kappa_out, &terms);
+  if (terms_out) *terms_out = terms;
+  return st;
 }
 
 kaldo_status kaldo_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out) {

@@ -197,6 +197,7 @@ struct kaldo_ctx_s {
   double T[KALDO_MAX_T] = {0};
   int stats = 0;
   int delta = KALDO_DELTA_GAUSS;
+  double sigma_thz = 0.0;               // delta width of the last linewidths
   kaldo::Arena arena;                   // caller's workspace (kaldo_set_workspace), if any
   int k_begin = 0, k_end = 0x7fffffff;  // first-mode grid points computed (kaldo_set_k_range)
   int g_lo = 0, g_hi = 0;                // the points the resident gamma covers
@@ -208,6 +209,7 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_kappa;             // double [nT][9]
   kaldo::DevBuf d_diff;              // double [nT][n][3] mode diffusivity (Gamma)
   kaldo::DevBuf d_scratch2;
+  kaldo::DevBuf d_bte;               // full BTE: scattering operator pieces, set tables, solve
 };
 
 namespace kaldo {
@@ -240,6 +242,19 @@ inline bool k_partial(const kaldo_ctx_s* c) { return k_lo(c) > 0 || k_hi(c) < c-
 // copy a device result into a caller pointer that may be host or device memory
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
 
+template <typename R>
+struct cplx;
+
+// FP64 tables of the few-branch path: OM, IW [n][nk], OCC [nT][n][nk],
+// PH [nDelta][nk] = e^{2 pi i q_p.Delta}, ET [n][n][nk] = eta (in d_tabs)
+struct SmallTables {
+  double *OM, *IW, *OCC;
+  cplx<double>* PH;
+  cplx<double>* ET;
+};
+kaldo_status small_tables_fp64(kaldo_ctx ctx, SmallTables* t);
+kaldo_status small_step_a_fp64(kaldo_ctx ctx, cplx<double>* A, int k0, int kc);
+
 // stages ------------------------------------------------------------------------
 kaldo_status run_phonons(kaldo_ctx ctx, bool want_velocity);
 kaldo_status run_linewidths(kaldo_ctx ctx, double sigma_thz, int precision);
@@ -254,5 +269,6 @@ hipError_t noalloc_setup(int device);
 kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 kaldo_status run_mode_diffusivity(kaldo_ctx ctx);
+kaldo_status run_kappa_bte(kaldo_ctx ctx, int method, int max_terms, double tol, double* kappa_out, int* terms_out);
 
 }  // namespace kaldo

@@ -23,6 +23,10 @@ KALDO_ENOMEM = -2
 KALDO_EDEVICE = -3
 KALDO_ESTATE = -4
 KALDO_EUNSTABLE = -5
+KALDO_ENOCONV = -6
+KALDO_BTE_INVERSE = 0
+KALDO_BTE_SELF_CONSISTENT = 1
+BTE_METHODS = {"inverse": KALDO_BTE_INVERSE, "self-consistent": KALDO_BTE_SELF_CONSISTENT}
 
 KALDO_FP64 = 0
 KALDO_FP32 = 1
@@ -41,14 +45,14 @@ KALDO_TUNE_FIXED = 1
 KALDO_TUNE_SHAPE0 = 2
 
 STATUS_NAMES = {0: "KALDO_OK", -1: "KALDO_EINVAL", -2: "KALDO_ENOMEM", -3: "KALDO_EDEVICE",
-                -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE"}
+                -4: "KALDO_ESTATE", -5: "KALDO_EUNSTABLE", -6: "KALDO_ENOCONV"}
 
 EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons",
             "kaldo_linewidths", "kaldo_kappa_rta", "kaldo_kappa_qhgk", "kaldo_batch_add",
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
             "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity",
-            "kaldo_kappa_rta_noalloc"]
+            "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte"]
 
 
 class kaldo_structure(C.Structure):
@@ -109,6 +113,9 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_rta.restype = C.c_int
     lib.kaldo_kappa_rta_noalloc.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_rta_noalloc.restype = C.c_int
+    lib.kaldo_kappa_bte.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_double, C.c_void_p,
+                                    C.POINTER(C.c_int32)]
+    lib.kaldo_kappa_bte.restype = C.c_int
     lib.kaldo_kappa_qhgk.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_kappa_qhgk.restype = C.c_int
     lib.kaldo_mode_diffusivity.argtypes = [C.c_void_p, C.c_void_p]
@@ -259,6 +266,12 @@ def kaldo_kappa_rta(ctx, kappa_out=None) -> int:
 
 def kaldo_kappa_rta_noalloc(ctx, kappa_out) -> int:
     return load_library().kaldo_kappa_rta_noalloc(ctx, _out_ptr(kappa_out))
+
+
+def kaldo_kappa_bte(ctx, method: int, max_terms: int, tol: float, kappa_out, terms_out=None) -> int:
+    """terms_out: a one-element int32 numpy array, or None."""
+    tp = None if terms_out is None else terms_out.ctypes.data_as(C.POINTER(C.c_int32))
+    return load_library().kaldo_kappa_bte(ctx, int(method), int(max_terms), float(tol), _out_ptr(kappa_out), tp)
 
 
 def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
@@ -437,6 +450,18 @@ class Context:
                                          DELTAS[delta] if isinstance(delta, str) else int(delta),
                                          KALDO_CLASSICAL if classical else KALDO_QUANTUM, out))
         return out
+
+    def kappa_bte(self, method="inverse", max_terms=500, tol=1e-14):
+        """Full linearised BTE conductivity [nT][3][3] W/(m K) for the last
+        linewidths: returns (kappa, terms, converged).  A series that has not
+        converged returns its last partial sum with converged False."""
+        out = np.zeros((self.nT, 3, 3))
+        terms = np.zeros(1, dtype=np.int32)
+        st = kaldo_kappa_bte(self.h, BTE_METHODS[method] if isinstance(method, str) else int(method),
+                             max_terms, tol, out, terms)
+        if st not in (KALDO_OK, KALDO_ENOCONV):
+            _check(self.h, st)
+        return out, int(terms[0]), st == KALDO_OK
 
     def kappa_rta(self, out=None, want_host=True):
         if want_host and out is None:
