@@ -46,30 +46,49 @@ MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 # scaled by what the counter reads for a plain 1 GiB device copy
 # (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Taken on the
 # current k_project_small; set to None when that kernel changes.
-HEADLINE_TRAFFIC = {"kernel": "k_project_small<float,6,3,true,0>", "fetch_kib": 96612.7, "write_kib": 10212.3,
-                    "fetch_scale": 2.0, "write_scale": 1.0}
+HEADLINE_TRAFFIC = None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_flops(nk, n, nd):
-    """Projection work of one linewidth pass (steps B and C, one V for both signs)."""
-    f_b = 8.0 * nk * nk * nd * n ** 3
-    f_c = 16.0 * nk * nk * n ** 4
+def computed_points(grid):
+    """First-mode points a whole-grid linewidth pass computes: one of each pair
+    (k, -k) (the linewidth is even under time reversal; the library copies the
+    values to the other point), i.e. (N_k + number of points with k = -k) / 2."""
+    g = [int(x) for x in grid]
+    self_mirror = 1
+    for x in g:
+        self_mirror *= 2 if x % 2 == 0 else 1
+    return (int(np.prod(g)) + self_mirror) // 2
+
+
+def algorithmic_flops(nk, n, nd, npts=None):
+    """Projection work of one linewidth pass over npts first-mode points (steps
+    B and C, one V for both signs): per point 8 N_k N_Delta n^3 + 16 N_k n^4."""
+    npts = nk if npts is None else npts
+    f_b = 8.0 * npts * nk * nd * n ** 3
+    f_c = 16.0 * npts * nk * n ** 4
     return f_b, f_c
 
 
-def algorithmic_bytes(nk, n, nd, nT):
-    """Unique bytes the projection kernel must read and write once (FP32 path):
-    the step-A tensor, eigenvectors, Delta phases, mode tables and the partial sums."""
-    a = nk * n * nd * n * n * 8          # A_k[s][Delta][a'][a''] complex float
+def intermediate_bytes(nk, n, nd, nT, npts):
+    """Bytes the projection kernel reads and writes once (FP32 path): its step-A
+    intermediate, eigenvectors, Delta phases, mode tables and the partial sums
+    (the implementation's traffic, not the method's unique inputs)."""
+    a = npts * n * nd * n * n * 8        # A_k[s][Delta][a'][a''] complex float
     et = n * n * nk * 8                  # eigenvectors, complex float
     ph = nd * nk * 8                     # phases, complex float
     tab = (2 + nT) * n * nk * 8          # omega, 1/omega, occupations (double)
-    part = nk * (nk // 256) * nT * n * 8  # per-tile partial sums (double)
+    part = npts * (nk // 256) * nT * n * 8  # per-tile partial sums (double)
     return float(a + et + ph + tab + part)
+
+
+def survey_algorithmic_bytes(c, nT):
+    """The method's unique inputs and outputs: eigenvectors (complex double),
+    fc3 blocks and the linewidths."""
+    return float(c.n_k * c.n_modes ** 2 * 16 + len(c.fc3_i) * 27 * 8 + nT * c.n_k * c.n_modes * 8)
 
 
 def run_gpu(args):
@@ -226,7 +245,8 @@ def run_mfma(name, steps, warmup):
         log(f"{name} mode diffusivity: {diff['ms_per_call']:.3f} ms per call, pair sum {kms:.3f} ms")
     ctx.close()
     lw = nk * n * len(T)
-    f_c = 16.0 * nk * nk * n ** 4 if nk > 1 else 2.0 * n ** 4  # algorithmic GEMM flops, one V for both signs
+    # algorithmic GEMM flops of the computed first-mode points, one V for both signs
+    f_c = 16.0 * computed_points(c.grid) * nk * n ** 4 if nk > 1 else 2.0 * n ** 4
     g64 = res["fp64"]["g"]
     floor = 1e-6 * np.abs(g64).max()
     err = float(np.max(np.abs(res["bf16x3"]["g"] - g64) / np.maximum(np.abs(g64), floor)))
@@ -608,7 +628,8 @@ def main():
     r = run_gpu(args)
     nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
     lw = nk * n * nT
-    f_b, f_c = algorithmic_flops(nk, n, nd)
+    npts = computed_points(r["c"].grid)
+    f_b, f_c = algorithmic_flops(nk, n, nd, npts)
     value = lw / (r["ms32"] * 1e-3)
     proj32 = r["kern32"]["project"]["avg_ms"]
     proj64 = r["kern64"]["project"]["avg_ms"]
@@ -635,15 +656,18 @@ def main():
         "speedup_fp32_vs_fp64": r["ms64"] / r["ms32"],
         "kernels_ms": {k: v["avg_ms"] for k, v in r["kern32"].items()},
         "roofline": {
-            "bound": "alu", "kernel": HEADLINE_TRAFFIC["kernel"],
+            "bound": "alu", "kernel": "k_project_small<float,6,3,true,0>",
             "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
-            "traffic": (HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
-                        HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0,
+            "traffic": ((HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
+                         HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0
+                        if HEADLINE_TRAFFIC else None),
             "traffic_unit": "HBM bytes per launch (scaled rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-            "algorithmic_bytes": algorithmic_bytes(nk, n, nd, nT),
+            "intermediate_bytes": intermediate_bytes(nk, n, nd, nT, npts),
+            "algorithmic_bytes": survey_algorithmic_bytes(r["c"], nT),
             "flops_per_launch": f_b + f_c,
+            "first_mode_points_computed": npts,
             # arithmetic the kernel runs: step B over nd - npair slot groups
             # (each (Delta, -Delta) pair costs one Delta), before the column skip
             "flops_executed_per_launch": f_b * (nd - r["npair"]) / nd + f_c,

@@ -34,6 +34,7 @@ struct ProjArgs {
   double rc;     // 1 / (scale of the delta): frequencies are scaled by it
   int kind;      // kaldo_delta (selects the kernel instance)
   int npair;     // leading slot pairs (2m, 2m + 1) of A_k in sum/difference form
+  const int* klist;  // first-mode point of block row kl: klist[k0 + kl] (null: k0 + kl)
 };
 
 // ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
@@ -112,7 +113,7 @@ __global__ void k_evec_transpose(cplx<R>* __restrict__ ET, const cplx<double>* _
 template <typename R>
 __global__ void __launch_bounds__(256) k_step_a(cplx<R>* __restrict__ A, const cplx<double>* __restrict__ E, const int2* __restrict__ group,
                          const int* __restrict__ bi, const int* __restrict__ bR2, const double* __restrict__ bval,
-                         int N, int nd, int G0, int G1, int G2, int k0, int kcount) {
+                         int N, int nd, int G0, int G1, int G2, const int* __restrict__ klist, int k0, int kcount) {
   // one thread per (k, s, Delta, j, l): all 9 (beta, gamma) elements of the
   // 3 x 3 block share the eigenvector loads and the phase of every fc3 block
   const int n = 3 * N;
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(256) k_step_a(cplx<R>* __restrict__ A, const c
   r /= N;
   const int d = r % nd;
   const int s = r / nd;
-  const int k = k0 + kl;
+  const int k = klist ? klist[k0 + kl] : k0 + kl;
   const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
   const long long Gt = (long long)G0 * G1 * G2;
   const int2 g = group[((size_t)d * N + j) * N + l];
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(256)
     pchunk = tile % (int)gridDim.x;
     kl = tile / (int)gridDim.x;
   }
-  const int k = P.k0 + kl;
+  const int k = P.klist ? P.klist[P.k0 + kl] : P.k0 + kl;
   const int nk = P.nk;
   const int km0 = k / (P.G1 * P.G2), km1 = (k / P.G2) % P.G1, km2 = k % P.G2;
   // per-wave partial sums [wave][s][t]
@@ -359,15 +360,19 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// gamma[t][k][s] = C / w_ks * sum_chunks partial, then the mean over each degenerate set.
+// gamma[t][k][s] = C / w_ks * sum_chunks partial, then the mean over each
+// degenerate set, stored at k and at -k (time reversal) where these lie in the
+// k range [klo, khi).
 __global__ void k_finalize(double* __restrict__ gamma, const double* __restrict__ partial, const double* __restrict__ IW,
-                           const int* __restrict__ setid, int nk, int n, int nT, int nchunk, int k0, int kcount,
-                           double C) {
+                           const int* __restrict__ setid, int nk, int n, int nT, int nchunk, const int* __restrict__ klist,
+                           int k0, int kcount, double C, int klo, int khi, int G0, int G1, int G2) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)kcount * nT) return;
   const int kl = (int)(idx % kcount);
   const int t = (int)(idx / kcount);
-  const int k = k0 + kl;
+  const int k = klist[k0 + kl];
+  const int km = k_mirror(k, G0, G1, G2);
+  const bool in_k = k >= klo && k < khi, in_km = km >= klo && km < khi;
   double g[64];
   for (int s = 0; s < n; ++s) {
     double v = 0.0;
@@ -381,7 +386,10 @@ __global__ void k_finalize(double* __restrict__ gamma, const double* __restrict_
     double m = 0.0;
     for (int u = s; u < e; ++u) m += g[u];
     m /= (e - s);
-    for (int u = s; u < e; ++u) gamma[((size_t)t * nk + k) * n + u] = m;
+    for (int u = s; u < e; ++u) {
+      if (in_k) gamma[((size_t)t * nk + k) * n + u] = m;
+      if (in_km) gamma[((size_t)t * nk + km) * n + u] = m;
+    }
     s = e;
   }
 }
@@ -488,18 +496,23 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   cplx<R>* A = ctx->d_A.as<cplx<R>>();
   double* partial = ctx->d_partial.as<double>();
-  const int kb = k_lo(ctx), ke = k_hi(ctx);
+  // the first-mode points to compute (one of each pair k, -k on the whole grid)
+  int npts = 0;
+  kaldo_status ks = upload_linewidth_points(ctx, &npts);
+  if (ks != KALDO_OK) return ks;
+  P.klist = ctx->d_klist.as<int>();
   if (k_partial(ctx) && !planning(ctx)) {
     const kaldo_status fs = fill_zero(ctx, ctx->d_gamma.p, (size_t)nT * nmode * sizeof(double));
     if (fs != KALDO_OK) return fs;
   }
-  for (int k0 = kb; k0 < ke && !planning(ctx); k0 += kchunk) {
-    const int kc = std::min(kchunk, ke - k0);
+  for (int k0 = 0; k0 < npts && !planning(ctx); k0 += kchunk) {
+    const int kc = std::min(kchunk, npts - k0);
     P.k0 = k0;
     prof_begin(ctx);
     hipLaunchKernelGGL((k_step_a<R>), dim3(blocks_for((long long)n * nd * N * N * kc, TB)), dim3(TB), 0,
                        st, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(), ctx->fc3.d_blk_i.as<int>(),
-                       ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, k0, kc);
+                       ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd, P.G0, P.G1, P.G2, P.klist,
+                       k0, kc);
     KALDO_HIP(ctx, hipGetLastError());
     if (P.npair > 0) {
       const long long cnt = (long long)kc * n * P.npair * n * n;
@@ -517,7 +530,8 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
     prof_end(ctx, "project");
     prof_begin(ctx);
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for((long long)kc * nT, TB)), dim3(TB), 0, st,
-                       ctx->d_gamma.as<double>(), partial, IW, ctx->d_setid.as<int>(), nk, n, nT, nchunk, k0, kc, C);
+                       ctx->d_gamma.as<double>(), partial, IW, ctx->d_setid.as<int>(), nk, n, nT, nchunk, P.klist, k0,
+                       kc, C, k_lo(ctx), k_hi(ctx), P.G0, P.G1, P.G2);
     KALDO_HIP(ctx, hipGetLastError());
     prof_end(ctx, "finalize");
   }
@@ -560,7 +574,7 @@ kaldo_status small_step_a_fp64(kaldo_ctx ctx, cplx<double>* A, int k0, int kc) {
   hipLaunchKernelGGL((k_step_a<double>), dim3(blocks_for((long long)n * nd * N * N * kc, 256)), dim3(256), 0,
                      ctx->stream, A, ctx->d_evec.as<cplx<double>>(), ctx->fc3.d_group.as<int2>(),
                      ctx->fc3.d_blk_i.as<int>(), ctx->fc3.d_blk_R2.as<int>(), ctx->fc3.d_blk_val.as<double>(), N, nd,
-                     ctx->grid[0], ctx->grid[1], ctx->grid[2], k0, kc);
+                     ctx->grid[0], ctx->grid[1], ctx->grid[2], nullptr, k0, kc);
   KALDO_HIP(ctx, hipGetLastError());
   return KALDO_OK;
 }

@@ -8,6 +8,7 @@
 #include <sstream>
 #include <tuple>
 
+#include "common.h"
 #include "internal.h"
 #include "tune.h"
 
@@ -101,6 +102,29 @@ int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const 
   (void)hipEventDestroy(e1);
   owner->tuned[key] = best;
   return best;
+}
+
+std::vector<int> linewidth_points(const kaldo_ctx_s* c) {
+  std::vector<char> take(c->nk, 0);
+  for (int k = k_lo(c); k < k_hi(c); ++k) take[std::min(k, k_mirror(k, c->grid[0], c->grid[1], c->grid[2]))] = 1;
+  std::vector<int> out;
+  for (int k = 0; k < c->nk; ++k)
+    if (take[k]) out.push_back(k);
+  return out;
+}
+
+kaldo_status upload_linewidth_points(kaldo_ctx ctx, int* npts) {
+  std::vector<int> pts = linewidth_points(ctx);
+  *npts = (int)pts.size();
+  if (ctx->mode == kCapture) {
+    if (pts != ctx->klist_host) return fail(ctx, KALDO_ESTATE, "first-mode points changed after planning");
+    return KALDO_OK;
+  }
+  KALDO_HIP(ctx, ctx->d_klist.ensure(pts.size() * sizeof(int)));
+  ctx->klist_host = std::move(pts);
+  KALDO_HIP(ctx, hipMemcpyAsync(ctx->d_klist.p, ctx->klist_host.data(), ctx->klist_host.size() * sizeof(int),
+                                hipMemcpyHostToDevice, ctx->stream));
+  return KALDO_OK;
 }
 
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {

@@ -48,4 +48,10 @@ __device__ __forceinline__ int imod(int a, int m) {
 
 inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// Index of -q_k on the Gamma-centred grid (k = (m0 G1 + m1) G2 + m2).
+__host__ __device__ inline int k_mirror(int k, int G0, int G1, int G2) {
+  const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
+  return (((G0 - m0) % G0) * G1 + (G1 - m1) % G1) * G2 + (G2 - m2) % G2;
+}
+
 }  // namespace kaldo

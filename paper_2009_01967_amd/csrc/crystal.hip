@@ -333,13 +333,17 @@ __global__ void k_cr_collect(double* __restrict__ gacc, const double* __restrict
   if (threadIdx.x == 0) gacc[(size_t)t * n + s] = (first ? 0.0 : gacc[(size_t)t * n + s]) + red[0];
 }
 
-// graw[t][k][s] = C / w_ks * gacc[t][s]
+// graw[t][k][s] = C / w_ks * gacc[t][s], stored at k and at km = -k (time
+// reversal) where these lie in the k range [klo, khi)
 __global__ void k_cr_finish(double* __restrict__ graw, const double* __restrict__ gacc,
-                            const double* __restrict__ IW, int n, int nk, int nT, int k, double C) {
+                            const double* __restrict__ IW, int n, int nk, int nT, int k, int km, int klo, int khi,
+                            double C) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * nT) return;
   const int s = idx % n, t = idx / n;
-  graw[((size_t)t * nk + k) * n + s] = C * IW[(size_t)s * nk + k] * gacc[(size_t)t * n + s];
+  const double v = C * IW[(size_t)s * nk + k] * gacc[(size_t)t * n + s];
+  if (k >= klo && k < khi) graw[((size_t)t * nk + k) * n + s] = v;
+  if (km >= klo && km < khi) graw[((size_t)t * nk + km) * n + s] = v;
 }
 
 // kmap[k][p] = index of k + p on the grid
@@ -448,12 +452,18 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
   // planning visits one first-mode point and the batches whose GEMM shapes differ
   const bool plan = planning(ctx);
-  const int kb = k_lo(ctx), ke = k_hi(ctx);
+  // the first-mode points to compute (one of each pair k, -k on the whole grid)
+  int npts = 0;
+  kaldo_status ks = upload_linewidth_points(ctx, &npts);
+  if (ks != KALDO_OK) return ks;
+  const std::vector<int> pts = ctx->klist_host;
   if (k_partial(ctx) && !plan) {
     const kaldo_status fs = fill_zero(ctx, gr, graw_n * sizeof(double));
     if (fs != KALDO_OK) return fs;
   }
-  for (int k = kb; k < (plan ? kb + 1 : ke); ++k) {
+  for (int ik = 0; ik < (plan ? 1 : npts); ++ik) {
+    const int k = pts[ik];
+    const int km = k_mirror(k, ctx->grid[0], ctx->grid[1], ctx->grid[2]);
     prof_begin(ctx);
     if (!plan)
       hipLaunchKernelGGL((k_cr_zg<RZ>), dim3(blocks_for((long long)z_elems, TB)), dim3(TB), 0, st, Z,
@@ -532,7 +542,8 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       KALDO_HIP(ctx, hipGetLastError());
     }
     if (plan) continue;
-    hipLaunchKernelGGL(k_cr_finish, dim3(blocks_for(n * nT, TB)), dim3(TB), 0, st, gr, gacc, IW, n, nk, nT, k, C);
+    hipLaunchKernelGGL(k_cr_finish, dim3(blocks_for(n * nT, TB)), dim3(TB), 0, st, gr, gacc, IW, n, nk, nT, k, km,
+                       k_lo(ctx), k_hi(ctx), C);
     KALDO_HIP(ctx, hipGetLastError());
   }
   if (plan) return KALDO_OK;

@@ -210,6 +210,8 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_diff;              // double [nT][n][3] mode diffusivity (Gamma)
   kaldo::DevBuf d_scratch2;
   kaldo::DevBuf d_bte;               // full BTE: scattering operator pieces, set tables, solve
+  kaldo::DevBuf d_klist;             // first-mode points a linewidth run computes (int)
+  std::vector<int> klist_host;       // its host copy (kept alive for the stream-ordered upload)
 };
 
 namespace kaldo {
@@ -238,6 +240,19 @@ inline bool planning(kaldo_ctx ctx) { return ctx->mode == kPlan; }
 inline int k_lo(const kaldo_ctx_s* c) { return c->k_begin < c->nk ? c->k_begin : c->nk; }
 inline int k_hi(const kaldo_ctx_s* c) { return c->k_end < c->nk ? c->k_end : c->nk; }
 inline bool k_partial(const kaldo_ctx_s* c) { return k_lo(c) > 0 || k_hi(c) < c->nk; }
+
+// First-mode grid points of the next linewidth run.  The linewidth is even
+// under time reversal, gamma(-k, s) = gamma(k, s) (D(-q) = conj D(q): the same
+// frequencies, conjugate eigenvectors, and the momentum-conserving triples of
+// -k are those of k reversed), so only one point of each pair (k, -k) is
+// computed, the one with the smaller index, and its values go to both points
+// of the pair that lie in the k range (kaldo_set_k_range; the whole grid by
+// default).  A shard thus computes exactly what the whole run computes for
+// its points.  Returns the sorted representatives.
+std::vector<int> linewidth_points(const kaldo_ctx_s* c);
+// the same list uploaded to ctx->d_klist (stream ordered; under capture the
+// list uploaded by the planning pass is used); returns its length
+kaldo_status upload_linewidth_points(kaldo_ctx ctx, int* npts);
 
 // copy a device result into a caller pointer that may be host or device memory
 kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
