@@ -1,20 +1,19 @@
 """Benchmark of the three-phonon linewidth path on one MI355X.
 
-One step = the whole hot path on resident inputs: harmonic modes on the grid
-(D(q) assembly + FP64 eigensolve + mode tables + velocities), the three-phonon
-projection and scattering-rate sum for every mode and temperature, and the RTA
-conductivity.  Inputs (structure, fc2, fc3) are uploaded once before timing;
-outputs stay in device memory.  The mixed-precision (FP32 projection) path
-gives ``value``; the FP64 path is timed beside it.
+Headline (one step): the linewidths of every mode of the 32-crystal batch
+(cells of 2..54 atoms, grids 4^3..10^3, Si/Ge masses, T = 300 K, Gaussian
+delta of 0.1 THz) in FP32, as one launch of the batch's HIP graph: a single
+persistent kernel works through the cost-sorted table of (crystal, first-mode
+point, partner range) rounds of every many-branch crystal.  Inputs are resident
+(harmonic modes computed and the graph planned and captured before timing).
+FP64 is timed beside it on a share of each crystal's first-mode points.
 
-The many-branch workloads that run the projection as MFMA GEMMs (the 46-atom
-cage cell on 5x5x5 and the 1000-atom SiGe cell at Gamma) are timed beside it
-(in a child process, like the batch, so that a failure there costs only that
-section, reported as ``mfma_paths_error`` / ``batched_path_error``),
-BF16X3 and FP32 beside FP64, and reported under ``mfma_paths`` with the roofline of
-their GEMMs (``--no-mfma`` skips them).  The 32-crystal batch (one HIP graph
-launch, FP32 beside FP64) is timed on a share of each crystal's first-mode
-points and reported under ``batched_path`` (``--no-batch`` skips it).
+Sections beside the headline: the 2-atom diamond cell on 16^3 (the few-branch
+VALU kernel, FP32 and FP64 steps with phonons and RTA conductivity), the
+many-branch workloads (46-atom cage cell on 5x5x5 and the 1000-atom SiGe cell
+at Gamma; BF16X3, FP32 and FP64 in a child process), the full linearised BTE
+and the delta/phase-space variants on the diamond cell, the attainable unit
+peaks and the CPU oracle on a sample of the batch.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: one GPU only.
 """
@@ -34,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOAD = "diamond-2at-16x16x16-shell3"
+BATCH_WORKLOAD = "batch-32-crystals-2..54at-4^3..10^3"
 METRIC = "phonon linewidths/s + projection TFLOP/s, mixed vs FP64, at rel err ≤1e-4"
 FP32_VECTOR_PEAK = 157.3e12     # MI355X published vector FP32 (FLOP/s)
 FP64_VECTOR_PEAK = 78.6e12
@@ -64,6 +64,18 @@ def computed_points(grid):
     return (int(np.prod(g)) + self_mirror) // 2
 
 
+def shared_points(grid, m):
+    """First-mode points computed for the range [0, m) of a grid: the distinct
+    representatives min(k, -k) of its points."""
+    g = [int(x) for x in grid]
+    reps = set()
+    for k in range(m):
+        m0, m1, m2 = k // (g[1] * g[2]), (k // g[2]) % g[1], k % g[2]
+        km = (((-m0) % g[0]) * g[1] + (-m1) % g[1]) * g[2] + (-m2) % g[2]
+        reps.add(min(k, km))
+    return len(reps)
+
+
 def algorithmic_flops(nk, n, nd, npts=None):
     """Projection work of one linewidth pass over npts first-mode points (steps
     B and C, one V for both signs): per point 8 N_k N_Delta n^3 + 16 N_k n^4."""
@@ -91,7 +103,9 @@ def survey_algorithmic_bytes(c, nT):
     return float(c.n_k * c.n_modes ** 2 * 16 + len(c.fc3_i) * 27 * 8 + nT * c.n_k * c.n_modes * 8)
 
 
-def run_gpu(args):
+def run_c2(steps=20, warmup=3):
+    """The 2-atom diamond cell on 16^3 (few-branch VALU kernel): FP32 and FP64
+    steps of phonons + linewidths + RTA conductivity on resident inputs."""
     import torch
     from gen import workload, WORKLOADS
     from paper_2009_01967_amd import kaldo
@@ -144,9 +158,9 @@ def run_gpu(args):
         kaldo.kaldo_profile_enable(ctx.h, False)
         return ms, wall, kern, g_d.cpu().numpy().copy(), k_d.cpu().numpy().copy()
 
-    ms32, wall32, kern32, g32, k32 = timed(kaldo.KALDO_FP32, args.steps, args.warmup)
+    ms32, wall32, kern32, g32, k32 = timed(kaldo.KALDO_FP32, steps, warmup)
     log(f"fp32: {ms32:.3f} ms/step (wall {wall32:.3f}), kernels {kern32}")
-    ms64, wall64, kern64, g64, k64 = timed(kaldo.KALDO_FP64, max(2, args.steps // 2), 1)
+    ms64, wall64, kern64, g64, k64 = timed(kaldo.KALDO_FP64, max(2, steps // 2), 1)
     log(f"fp64: {ms64:.3f} ms/step (wall {wall64:.3f}), kernels {kern64}")
     dset = {tuple(int(v) for v in x) for x in (c.fc3_R2 - c.fc3_R1)}
     nd = len(dset)
@@ -289,12 +303,19 @@ def run_mfma(name, steps, warmup):
     return out
 
 
-def run_batch(div=64, steps=1, warmup=1):
-    """The 32-crystal batch (cells of 2..54 atoms, grids 4^3..10^3): linewidths
-    of every crystal in one HIP graph launch, FP32 beside FP64, on the first
-    ceil(N_k / div) first-mode points of each crystal (kaldo_batch_set_k_range:
-    one GPU's share of a k-sharded run).  The full draw is extrapolated with
-    the GEMM flops of each crystal as weights."""
+def batch_flops(c, npts):
+    """Algorithmic flops (F_A, F_B, F_C) of npts first-mode points of crystal c."""
+    n, nk = c.n_modes, c.n_k
+    nd = len({tuple(int(v) for v in x) for x in (c.fc3_R2 - c.fc3_R1)})
+    nnz = 27 * len(c.fc3_i)
+    return 4.0 * npts * n * nnz, 8.0 * npts * nk * nd * n ** 3, 16.0 * npts * nk * n ** 4
+
+
+def run_batch_headline(steps, warmup, div=64, share=1):
+    """The headline: linewidths of every mode of the 32-crystal batch in FP32,
+    one graph launch (the persistent kernel) per step (share > 1: only the
+    first ceil(N_k / share) first-mode points of each crystal, for a shorter
+    run); FP64 beside it on the first ceil(N_k / div) points of each crystal."""
     import torch
     from gen import batch_crystals
     from paper_2009_01967_amd import kaldo
@@ -305,80 +326,96 @@ def run_batch(div=64, steps=1, warmup=1):
     T, sigma = [300.0], 0.1
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    sub = [max(1, -(-c.n_k // div)) for c in crystals]
-    outs = [torch.empty((len(T), c.n_k, c.n_modes), dtype=torch.float64, device=dev) for c in crystals]
-    res = {}
-    for label, prec in (("fp32", kaldo.KALDO_FP32), ("fp64", kaldo.KALDO_FP64)):
-        # one context per precision: each graph is captured once, on a context
-        # that has captured nothing before
-        ctx = kaldo.Context(0, stream.cuda_stream)
-        t0 = time.perf_counter()
-        for i, (c, m) in enumerate(zip(crystals, sub)):
-            ctx.batch_add(c)
-            ctx.batch_set_k_range(i, 0, m)
-        torch.cuda.synchronize()
-        log(f"batch {label}: phonons of {len(crystals)} crystals in {time.perf_counter() - t0:.1f} s")
-        t0 = time.perf_counter()
-        for _ in range(warmup):  # the first call plans, tunes and captures the graph
-            kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, prec, outs))
-        torch.cuda.synchronize()
-        log(f"batch {label}: planned, captured and launched once in {time.perf_counter() - t0:.1f} s")
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, prec, outs))
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        res[label] = dict(ms=ms, g=[o[:, :m].cpu().numpy().copy() for o, m in zip(outs, sub)])
-        log(f"batch {label}: {ms:.1f} ms per graph launch")
-        ctx.close()
-    # the fraction of the tiled GEMM work that runs (tiles beyond the delta cut
-    # are skipped): one eager FP32 pass per crystal on the same points, with the
-    # library's flop tally (captured graphs carry no tally)
+    out = {}
+    # ---- FP32, every first-mode point
+    ctx = kaldo.Context(0, stream.cuda_stream)
     t0 = time.perf_counter()
-    ex_all = dense_all = 0.0
-    for c, m in zip(crystals, sub):
-        with kaldo.Context(0, stream.cuda_stream) as one:
-            one.phonons(c)
-            one.set_k_range(0, m)
-            one.linewidths(c, T=T, sigma_thz=sigma, precision="fp32", want_host=False)
-            kaldo.kaldo_profile_enable(one.h, True)
-            one.linewidths(None, T=T, sigma_thz=sigma, precision="fp32", want_host=False)
-            ex, dense = kaldo.kaldo_profile_flops(one.h)
-            ex_all += ex
-            dense_all += dense
-    ran = ex_all / dense_all if dense_all else 1.0
-    log(f"batch: {1.0 - ran:.3f} of the tiled GEMM work skipped (eager tally, {time.perf_counter() - t0:.1f} s)")
-    # accuracy of FP32 against FP64 on the computed points (unmasked modes)
+    share_pts = [c.n_k if share == 1 else max(1, -(-c.n_k // share)) for c in crystals]
+    for i, c in enumerate(crystals):
+        ctx.batch_add(c)
+        if share != 1:
+            ctx.batch_set_k_range(i, 0, share_pts[i])
+    torch.cuda.synchronize()
+    phonon_s = time.perf_counter() - t0
+    log(f"batch fp32: phonons of {len(crystals)} crystals in {phonon_s:.1f} s")
+    g32 = [np.zeros((len(T), c.n_k, c.n_modes)) for c in crystals]
+    t0 = time.perf_counter()
+    kaldo._check(ctx.h, kaldo.kaldo_batch_plan(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"batch fp32: planned and captured in {setup_s:.1f} s")
+    for _ in range(warmup):
+        kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None))
+    torch.cuda.synchronize()
+    kaldo.kaldo_profile_enable(ctx.h, True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32,
+                                                   g32 if i == steps - 1 else None))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / steps
+    ms = e0.elapsed_time(e1) / steps
+    graph_ms, launches = kaldo.kaldo_profile_read(ctx.h, "batch_graph")
+    phases = {}
+    for name in ("batch_a_collect", "batch_step_b", "batch_gemm1", "batch_gemm2", "batch_barrier_wait",
+                 "batch_set_average"):
+        tot, cnt = kaldo.kaldo_profile_read(ctx.h, name)
+        phases[name] = tot / max(cnt, 1)
+    log(f"batch fp32 phases (ms per launch, workgroup 0): {phases}")
+    ex, dense = kaldo.kaldo_profile_flops(ctx.h)
+    kaldo.kaldo_profile_enable(ctx.h, False)
+    ctx.close()
+    log(f"batch fp32: {ms:.1f} ms per launch (wall {wall:.1f}), graph {graph_ms / max(launches, 1):.1f} ms, "
+        f"tiles run {ex / dense if dense else 1.0:.3f}")
+    # ---- FP64 beside it on a share of the points
+    sub = [max(1, -(-c.n_k // div)) for c in crystals]
+    ctx = kaldo.Context(0, stream.cuda_stream)
+    for i, (c, m) in enumerate(zip(crystals, sub)):
+        ctx.batch_add(c)
+        ctx.batch_set_k_range(i, 0, m)
+    g64 = [np.zeros((len(T), c.n_k, c.n_modes)) for c in crystals]
+    kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP64, g64))
+    torch.cuda.synchronize()
+    f0 = torch.cuda.Event(enable_timing=True)
+    f1 = torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP64, None))
+    f1.record(stream)
+    torch.cuda.synchronize()
+    ms64 = f0.elapsed_time(f1)
+    ctx.close()
+    log(f"batch fp64 (first ceil(N_k/{div}) points): {ms64:.1f} ms per launch")
     err = 0.0
-    for g32, g64 in zip(res["fp32"]["g"], res["fp64"]["g"]):
-        on = g64 > 0
-        floor = 1e-6 * np.abs(g64).max()
-        err = max(err, float(np.max(np.abs(g32[on] - g64[on]) / np.maximum(g64[on], floor))))
-    lw = sum(m * c.n_modes for c, m in zip(crystals, sub)) * len(T)
-    gemm = [16.0 * m * c.n_k * c.n_modes ** 4 for c, m in zip(crystals, sub)]
-    gemm_full = [16.0 * c.n_k * c.n_k * c.n_modes ** 4 for c in crystals]
-    out = {"workload": "batch-32-crystals-2..54at-4^3..10^3", "crystals": len(crystals), "T_K": T,
-           "sigma_thz": sigma, "step": "one kaldo_batch_run graph launch on resident phonons",
-           "first_mode_points": f"ceil(N_k/{div}) per crystal, {sum(sub)} of {sum(c.n_k for c in crystals)}",
-           "gemm_flops_per_launch": sum(gemm), "gemm_flops_full_draw": sum(gemm_full),
-           "gamma_rel_err_fp32_vs_fp64": err}
-    for label, peak in (("fp32", FP32_MFMA_PEAK), ("fp64", FP64_MFMA_PEAK)):
-        ms = res[label]["ms"]
-        out[label] = {"ms_per_launch": ms, "value": lw / (ms * 1e-3), "unit": "linewidths/s",
-                      "extrapolated_full_draw_s": ms * 1e-3 * sum(gemm_full) / sum(gemm),
-                      "roofline": {"bound": "mfma", "kernel": "whole graph (all crystals, every kernel)",
-                                   "achieved": sum(gemm) * ran / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
-                                   "unit": "TFLOP/s", "frac": sum(gemm) * ran / (ms * 1e-3) / peak,
-                                   "traffic": None,
-                                   "basis": "algorithmic GEMM flops of the computed points times the fraction "
-                                            "of tiled work that ran (eager FP32 tally)",
-                                   "tiles_skipped_frac": 1.0 - ran,
-                                   "dense_equivalent_tflops": sum(gemm) / (ms * 1e-3) / 1e12}}
-    out["speedup_fp32_vs_fp64"] = res["fp64"]["ms"] / res["fp32"]["ms"]
-    return out
+    for a, b, m in zip(g32, g64, sub):
+        x, y = a[:, :m], b[:, :m]
+        on = y > 0
+        floor = 1e-6 * np.abs(y).max()
+        err = max(err, float(np.max(np.abs(x[on] - y[on]) / np.maximum(y[on], floor))))
+    # ---- work accounting (computed first-mode points: one of each pair k, -k)
+    pts = [computed_points(c.grid) if share == 1 else shared_points(c.grid, m) for c, m in zip(crystals, share_pts)]
+    fa = fb = fc = 0.0
+    for c, p in zip(crystals, pts):
+        a, b, cc = batch_flops(c, p)
+        fa, fb, fc = fa + a, fb + b, fc + cc
+    pts64 = sub
+    fc64 = sum(batch_flops(c, p)[2] for c, p in zip(crystals, pts64))
+    lw = sum(m * c.n_modes for c, m in zip(crystals, share_pts)) * len(T)
+    lw64 = sum(m * c.n_modes for c, m in zip(crystals, sub)) * len(T)
+    ran = ex / dense if dense else 1.0
+    kernel_ms = graph_ms / max(launches, 1)
+    return dict(phases=phases, crystals=crystals, share=share, share_pts=share_pts, T=T, sigma=sigma, ms=ms, wall=wall, kernel_ms=kernel_ms, ran=ran, ex=ex / steps,
+                dense=dense / steps, fa=fa, fb=fb, fc=fc, lw=lw, pts=sum(pts), phonon_s=phonon_s, setup_s=setup_s,
+                g32=g32, fp64={"ms_per_launch": ms64, "value": lw64 / (ms64 * 1e-3), "unit": "linewidths/s",
+                               "first_mode_points": f"ceil(N_k/{div}) per crystal, {sum(sub)} of "
+                                                    f"{sum(c.n_k for c in crystals)}",
+                               "gemm_tflops_algorithmic": fc64 / (ms64 * 1e-3) / 1e12,
+                               "frac_of_fp64_mfma_peak": fc64 / (ms64 * 1e-3) / FP64_MFMA_PEAK},
+                err_fp32_vs_fp64=err)
 
 
 def run_plain(name, precision, passes=2):
@@ -488,7 +525,7 @@ def run_next1(methods=("inverse", "self-consistent"), max_terms=200):
 
 
 def run_section(flags, key):
-    """One optional section of the benchmark (the MFMA workloads or the batch)
+    """One optional section of the benchmark (the many-branch MFMA workloads)
     in a child process, so that a failure there costs that section only.  The
     child's progress goes to this process's stderr; its JSON line is parsed.
     Returns (value, None) or (None, reason)."""
@@ -528,62 +565,103 @@ def measured_peaks():
     return out
 
 
-def cpu_baseline(r, budget_s=20.0):
-    """The FP64 oracle on the host, on a bounded sample of first-mode k points."""
+def c2_section(r):
+    """The few-branch workload's JSON (the VALU kernel's roofline)."""
+    nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
+    lw = nk * n * nT
+    npts = computed_points(r["c"].grid)
+    f_b, f_c = algorithmic_flops(nk, n, nd, npts)
+    proj32 = r["kern32"]["project"]["avg_ms"]
+    proj64 = r["kern64"]["project"]["avg_ms"]
+    return {
+        "workload": WORKLOAD, "n_k": nk, "n_modes": n, "n_T": nT, "T_K": r["T"], "sigma_thz": r["sigma"],
+        "fc3_blocks": int(len(r["c"].fc3_i)), "n_delta": nd,
+        "step": "kaldo_phonons + kaldo_linewidths + kaldo_kappa_rta on resident inputs",
+        "fp32": {"ms_per_step": r["ms32"], "value": lw / (r["ms32"] * 1e-3), "unit": "linewidths/s",
+                 "projection_tflops": (f_b + f_c) / (r["ms32"] * 1e-3) / 1e12},
+        "fp64": {"ms_per_step": r["ms64"], "value": lw / (r["ms64"] * 1e-3), "unit": "linewidths/s",
+                 "projection_tflops": (f_b + f_c) / (r["ms64"] * 1e-3) / 1e12, "project_kernel_ms": proj64},
+        "speedup_fp32_vs_fp64": r["ms64"] / r["ms32"],
+        "kernels_ms": {k: v["avg_ms"] for k, v in r["kern32"].items()},
+        "roofline": {
+            "bound": "alu", "kernel": "k_project_small<float,6,3,true,0>",
+            "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
+            "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
+            "traffic": ((HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
+                         HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0
+                        if HEADLINE_TRAFFIC else None),
+            "intermediate_bytes": intermediate_bytes(nk, n, nd, nT, npts),
+            "algorithmic_bytes": survey_algorithmic_bytes(r["c"], nT),
+            "flops_per_launch": f_b + f_c,
+            "first_mode_points_computed": npts,
+            "flops_executed_per_launch": f_b * (nd - r["npair"]) / nd + f_c,
+            "executed_frac": ((f_b * (nd - r["npair"]) / nd + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK
+                              if proj32 else None),
+            "delta_pairs": r["npair"],
+        },
+    }
+
+
+def cpu_baseline_batch(b, budget_s=20.0):
+    """The FP64 oracle on the host on a sample of the batch: first-mode points
+    of the 36-branch crystal (12 atoms on 9^3) until the budget is spent; the
+    whole batch's time is extrapolated with each crystal's cost per point
+    (16 N_k n^4, the oracle evaluates every point) and compared with the
+    library's FP32 values at the sampled points."""
     from oracle import phonons as P, anharmonic as A
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    c, w, T = r["c"], r["w"], r["T"]
+    crystals, T, sigma = b["crystals"], b["T"], b["sigma"]
+    ci = min(range(len(crystals)), key=lambda i: (abs(crystals[i].n_modes - 36), crystals[i].n_k))
+    c = crystals[ci]
     ph = P.phonons(c, velocities=False)
-    rng = np.random.default_rng(7)
-    cand = [0, 1, 17, 273, 2080] + list(rng.choice(c.n_k, size=64, replace=False))
-    done = []
-    g_ref = []
     t0 = time.perf_counter()
-    for k in cand:
-        g_ref.append(A.linewidths(c, ph, T, r["sigma"], k_subset=[int(k)])[:, 0])
-        done.append(int(k))
-        if time.perf_counter() - t0 > budget_s and len(done) >= 4:
+    done, ref = [], []
+    for k in (1, 2, 3, 5, 7, 11, 13):
+        ref.append(A.linewidths(c, ph, T, sigma, k_subset=[k])[:, 0])
+        done.append(k)
+        if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    g_ref = np.stack(g_ref, axis=1)               # (nT, nsample, n)
+    per_flop = el / (len(done) * 16.0 * c.n_k * c.n_modes ** 4)
+    full_s = per_flop * sum(16.0 * x.n_k * x.n_k * x.n_modes ** 4 for x in crystals)
+    g = np.stack(ref, axis=1)
     mask = ph.mask[done]
-    ref = g_ref[:, mask]
-    floor = 1e-6 * np.abs(ref).max()
-
-    def err(g):
-        gs = g[:, done][:, mask]
-        return float(np.max(np.abs(gs - ref) / np.maximum(np.abs(ref), floor)))
-
-    lw = len(done) * c.n_modes * len(T)
-    return {"value": lw / el, "unit": "linewidths/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(done)} of {c.n_k} first-mode k points x {c.n_modes} modes x {len(T)} T "
-                      f"({el:.1f} s, numpy float64, host cores {os.cpu_count()})"}, \
-        {"fp32": err(r["g32"]), "fp64": err(r["g64"]), "k_sample": len(done)}
+    gs = b["g32"][ci][:, done]
+    floor = 1e-6 * np.abs(g[:, mask]).max()
+    err = float(np.max(np.abs(gs[:, mask] - g[:, mask]) / np.maximum(np.abs(g[:, mask]), floor)))
+    return {"value": b["lw"] / full_s, "unit": "linewidths/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(done)} first-mode points of {c.name} ({c.n_modes} branches, {c.n_k} points) in "
+                      f"{el:.1f} s, numpy float64 on {os.cpu_count()} host cores; the 32-crystal batch "
+                      f"extrapolated by 16 N_k^2 n^4 per crystal to {full_s:.3e} s"}, err
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1, help="timed launches of the batch graph (headline)")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed launches of the batch graph before timing")
+    ap.add_argument("--batch-share", type=int, default=1,
+                    help="time the batch on the first ceil(N_k / S) first-mode points of each crystal (default 1: "
+                         "every point, the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-mfma", action="store_true", help="skip the many-branch MFMA workloads")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 32-crystal batch")
+    ap.add_argument("--no-c2", action="store_true", help="skip the few-branch diamond workload and its variants")
     ap.add_argument("--no-next2", action="store_true",
-                    help="skip the Lorentzian/triangle linewidths and the phase space on the headline workload")
+                    help="skip the Lorentzian/triangle linewidths and the phase space on the diamond workload")
     ap.add_argument("--no-next1", action="store_true",
-                    help="skip the full linearised BTE (inverse and self-consistent) on the headline workload")
+                    help="skip the full linearised BTE (inverse and self-consistent) on the diamond workload")
     ap.add_argument("--peaks", action="store_true", help="only measure the attainable unit peaks")
     ap.add_argument("--plain", metavar="WORKLOAD", help="run one workload through the library alone "
                     "(torch initialises the GPU but hands the library no stream or tensor; for rocprofv3 "
                     "counters) with --precision, then exit")
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--no-main", action="store_true",
-                    help="skip the headline workload (prints only the MFMA workloads; for profiling)")
+                    help="only the many-branch workloads (prints their JSON; for profiling and the child section)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -611,28 +689,19 @@ def main():
         print(json.dumps({"measured_peaks": measured_peaks()}))
         return
     if args.no_main:
-        extra = {}
-        if not args.no_mfma:
-            extra["mfma_paths"] = [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]
-        if not args.no_batch:
-            extra["batched_path"] = run_batch()
-        print(json.dumps(extra))
+        print(json.dumps({"mfma_paths": [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]}))
         return
-    # the MFMA workloads and the batch run first, each in a child process
-    # started before this process touches the GPU
+    # the many-branch workloads run first, in a child process started before
+    # this process touches the GPU
     sections = {}
     if not args.no_mfma:
-        sections["mfma_paths"] = run_section(["--no-batch"], "mfma_paths")
-    if not args.no_batch:
-        sections["batched_path"] = run_section(["--no-mfma"], "batched_path")
-    r = run_gpu(args)
-    nk, n, nd, nT = r["nk"], r["n"], r["nd"], len(r["T"])
-    lw = nk * n * nT
-    npts = computed_points(r["c"].grid)
-    f_b, f_c = algorithmic_flops(nk, n, nd, npts)
-    value = lw / (r["ms32"] * 1e-3)
-    proj32 = r["kern32"]["project"]["avg_ms"]
-    proj64 = r["kern64"]["project"]["avg_ms"]
+        sections["mfma_paths"] = run_section([], "mfma_paths")
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    b = run_batch_headline(args.steps, args.warmup, share=args.batch_share)
+    value = b["lw"] / (b["ms"] * 1e-3)
+    kms = b["kernel_ms"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -640,46 +709,47 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms32"],
+        "ms_per_step": b["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n_k": nk, "n_modes": n, "n_T": nT, "T_K": r["T"],
-                   "sigma_thz": r["sigma"], "fc3_blocks": int(len(r["c"].fc3_i)), "n_delta": nd,
-                   "projection": "fp32", "accumulation": "fp64"},
-        "projection_tflops": (f_b + f_c) / (r["ms32"] * 1e-3) / 1e12,
-        "fp64": {"ms_per_step": r["ms64"], "value": lw / (r["ms64"] * 1e-3),
-                 "projection_tflops": (f_b + f_c) / (r["ms64"] * 1e-3) / 1e12,
-                 "project_kernel_ms": proj64},
-        "speedup_fp32_vs_fp64": r["ms64"] / r["ms32"],
-        "kernels_ms": {k: v["avg_ms"] for k, v in r["kern32"].items()},
+        "config": {"workload": BATCH_WORKLOAD + ("" if b["share"] == 1 else f", first ceil(N_k/{b['share']}) points"),
+                   "crystals": len(b["crystals"]),
+                   "modes": int(sum(m * c.n_modes for c, m in zip(b["crystals"], b["share_pts"]))), "T_K": b["T"],
+                   "sigma_thz": b["sigma"], "projection": "fp32", "accumulation": "fp64",
+                   "first_mode_points_computed": b["pts"],
+                   "launch": "one HIP graph launch: one persistent kernel over the cost-sorted rounds"},
+        "wall_ms_per_step": b["wall"],
+        "setup_s": {"phonons": b["phonon_s"], "plan_and_capture": b["setup_s"]},
+        "projection_tflops": b["fc"] / (b["ms"] * 1e-3) / 1e12,
         "roofline": {
-            "bound": "alu", "kernel": "k_project_small<float,6,3,true,0>",
-            "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
-            "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
-            "traffic": ((HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
-                         HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0
-                        if HEADLINE_TRAFFIC else None),
-            "traffic_unit": "HBM bytes per launch (scaled rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-            "intermediate_bytes": intermediate_bytes(nk, n, nd, nT, npts),
-            "algorithmic_bytes": survey_algorithmic_bytes(r["c"], nT),
-            "flops_per_launch": f_b + f_c,
-            "first_mode_points_computed": npts,
-            # arithmetic the kernel runs: step B over nd - npair slot groups
-            # (each (Delta, -Delta) pair costs one Delta), before the column skip
-            "flops_executed_per_launch": f_b * (nd - r["npair"]) / nd + f_c,
-            "executed_frac": ((f_b * (nd - r["npair"]) / nd + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK
-                              if proj32 else None),
-            "delta_pairs": r["npair"],
+            "bound": "mfma", "kernel": "k_batch_persistent<1,1> (FP32, one temperature)",
+            "achieved": b["fc"] / (kms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": b["fc"] / (kms * 1e-3) / FP32_MFMA_PEAK,
+            "traffic": None,
+            "basis": "algorithmic GEMM flops F_C = 16 N_k n^4 per computed first-mode point, summed over the "
+                     "crystals, per launch, over the launch's duration (library events on the stream)",
+            "flops_per_launch": b["fc"],
+            "step_a_b_flops_per_launch": b["fa"] + b["fb"],
+            "useful_frac": b["fc"] * b["ran"] / (kms * 1e-3) / FP32_MFMA_PEAK,
+            "tiles_skipped_frac": 1.0 - b["ran"],
+            "mfma_tflops_issued": b["ex"] / (kms * 1e-3) / 1e12,
+            "kernel_ms": kms,
+            "phases_ms": b["phases"],
         },
+        "fp64": b["fp64"],
+        "speedup_fp32_vs_fp64_per_flop": (b["fc"] / b["ms"]) / (b["fp64"]["gemm_tflops_algorithmic"] * 1e9),
+        "gamma_rel_err_fp32_vs_fp64": b["err_fp32_vs_fp64"],
     }
-    if not args.no_next2:
-        out["next2"] = run_next2()
-    if not args.no_next1:
-        out["next1"] = run_next1()
+    if not args.no_c2:
+        r = run_c2()
+        out["fewbranch_c2"] = c2_section(r)
+        if not args.no_next2:
+            out["next2"] = run_next2()
+        if not args.no_next1:
+            out["next1"] = run_next1()
     for key, (val, why) in sections.items():
         if val is not None:
             out[key] = val
@@ -687,9 +757,9 @@ def main():
             out[key + "_error"] = why
     out["measured_peaks"] = measured_peaks()
     if not args.no_cpu:
-        base, err = cpu_baseline(r)
+        base, err = cpu_baseline_batch(b)
         out["cpu_baseline"] = base
-        out["err_vs_oracle"] = err
+        out["err_vs_oracle"] = {"fp32": err}
     print(json.dumps(out), flush=True)
 
 

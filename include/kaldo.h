@@ -306,10 +306,18 @@ kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out);
  * kaldo_batch_run computes the linewidths (paper Sec. II.B, as
  * kaldo_linewidths with the Gaussian delta) of every mode of every crystal for
  * nT temperatures.  The first call with a given (T, sigma, statistics,
- * precision) plans the batch (sizes every device buffer, settles the tile shape
- * of each GEMM problem, shared by all crystals of the context), then captures
- * the linewidth kernels of all crystals on the context's stream into one HIP
- * graph; that and later calls with the same arguments launch the graph once.
+ * precision) plans the batch (sizes every device buffer, builds the static
+ * operands), then captures on the context's stream into one HIP graph: one
+ * persistent kernel for every crystal that takes the MFMA GEMM path, working
+ * through a table of rounds (crystal, first-mode point k, range of partners)
+ * with the crystals in order of decreasing cost (points x N_k x n^4) and the
+ * stages of each round (step A of a new k, step B, the two GEMMs with the
+ * fused linewidth epilogue, the collection) separated by grid barriers; the
+ * few-branch crystals (1 or 2 atoms, FP32 or FP64) add their own kernels.  The
+ * persistent grid holds the workgroups that fit on the device at once; a
+ * barrier that waits for more than about a second returns KALDO_EDEVICE (and
+ * leaves the results incomplete) instead of hanging.  That and later calls with
+ * the same arguments launch the graph once and wait for it.
  * The context's stream must not be the null stream (pass NULL to kaldo_create
  * to get an owned one).  gamma_out, if not NULL, holds one pointer per crystal
  * in handle order, each to [nT][Nk_i][n_i] doubles (host or device memory) or
@@ -324,6 +332,11 @@ kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, co
                              const kaldo_fc3* fc3, const int32_t grid[3], int32_t* handle);
 kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
                              kaldo_precision precision, double* const* gamma_out);
+/* kaldo_batch_plan does the planning and capture of kaldo_batch_run for these
+ * arguments (when the batch holds no graph yet) without launching it; errors
+ * as kaldo_batch_run. */
+kaldo_status kaldo_batch_plan(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                              kaldo_precision precision);
 kaldo_status kaldo_batch_clear(kaldo_ctx ctx);
 
 /* One GPU's share of a run sharded over first-mode grid points.  The
@@ -360,7 +373,11 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
  * every launch of its main kernels, named
  *   "dyn_assemble", "eigensolve", "step_a", "step_b", "gamma_sparse",
  *   "project", "finalize", "kappa_rta", "kappa_qhgk", "diffusivity" and "batch_graph"
- *   around a kaldo_batch_run graph launch.
+ *   around a kaldo_batch_run graph launch, and the phases of the persistent
+ *   batch kernel as workgroup 0 sees them (its own work in each stage, summed
+ *   over the rounds): "batch_a_collect" (step A, collection, Y padding),
+ *   "batch_step_b", "batch_gemm1", "batch_gemm2", "batch_barrier_wait" (its
+ *   waits at grid barriers) and "batch_set_average".
  * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables
  * and clears them.
  * kaldo_profile_read synchronises the stream and returns, for one kernel
@@ -371,7 +388,8 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
  * the many-branch path, the Gamma-point GEMM) since enabling: `executed` counts the block tiles that ran (BF16X3
  * counts its three bf16 products), `dense` every tile launched, including the
  * tiles skipped because all their outputs lie beyond the delta cut.  The
- * few-branch kernel and captured batch graphs are not counted.  Either
+ * persistent kernel of kaldo_batch_run counts its GEMM tiles the same way
+ * (read after each launch); the few-branch kernel is not counted.  Either
  * pointer may be NULL.  Enabling allocates the 8-byte device counter with
  * hipMalloc, outside any workspace set by kaldo_set_workspace. */
 kaldo_status kaldo_profile_enable(kaldo_ctx ctx, int enable);

@@ -2,6 +2,7 @@
 // structure and force constants, and dispatch to the device stages.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -20,6 +21,17 @@ kaldo_status fail(kaldo_ctx ctx, kaldo_status s, const std::string& msg) {
 }
 
 thread_local Arena* g_arena = nullptr;
+
+// Step-B and GEMM-1 output per partner batch of a crystal in the persistent
+// batch kernel (one pool shared by the crystals, which run one after the
+// other): larger rounds than an eager call's (256 MB), so that each GEMM phase
+// has many block tiles per resident workgroup and the rounds are few.
+// (KALDO_BATCH_XY_MB in the environment overrides it, for tuning.)
+static size_t batch_xy_budget() {
+  const char* e = std::getenv("KALDO_BATCH_XY_MB");
+  const long v = e ? std::atol(e) : 0;
+  return v > 0 ? (size_t)v << 20 : (size_t)4 << 30;
+}
 
 kaldo_status hip_fail(kaldo_ctx ctx, hipError_t e, const char* what) {
   std::ostringstream os;
@@ -67,6 +79,7 @@ void prof_clear(kaldo_ctx ctx) {
   prof_collect(ctx);
   ctx->prof_tab.clear();
   ctx->prof_dense = 0.0;
+  ctx->prof_batch_executed = 0.0;
 }
 
 int autotune(kaldo_ctx ctx, const std::string& key, int nv, int fallback, const std::function<void(int)>& launch) {
@@ -683,19 +696,31 @@ kaldo_status kaldo_batch_clear(kaldo_ctx ctx) {
   return KALDO_OK;
 }
 
-// Capture the linewidth kernels of every crystal of the batch into one graph.
+// Capture the linewidths of every crystal of the batch into one graph: the
+// many-branch crystals as one persistent kernel over a cost-sorted table of
+// rounds (crystal, k, partner range), the few-branch crystals as their own
+// per-chunk kernels.
 static kaldo_status batch_capture(kaldo_ctx ctx, double sigma_thz, int precision) {
   kaldo_status st = KALDO_OK;
-  // plan: size every buffer and settle every tile shape outside the capture
+  // plan: size every buffer, build the static operands and record each
+  // many-branch crystal's plan, outside the capture
+  std::vector<kaldo_ctx> pers, eager;
   for (kaldo_ctx sub : ctx->batch) {
     sub->mode = kPlan;
+    sub->cplan.valid = 0;
+    sub->xy_budget = batch_xy_budget();
+    sub->xy_shared = true;
     st = run_linewidths(sub, sigma_thz, precision);
+    sub->xy_shared = false;
     sub->mode = kRun;
     if (st != KALDO_OK) return fail(ctx, st, "kaldo_batch_run (plan): " + sub->err);
+    if (sub->cplan.valid && sub->cplan.precision == precision) pers.push_back(sub);
+    else eager.push_back(sub);
   }
+  if ((st = batch_persistent_prepare(ctx, pers, precision)) != KALDO_OK) return st;
   KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
   KALDO_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-  for (kaldo_ctx sub : ctx->batch) {
+  for (kaldo_ctx sub : eager) {
     sub->mode = kCapture;
     st = run_linewidths(sub, sigma_thz, precision);
     sub->mode = kRun;
@@ -704,6 +729,7 @@ static kaldo_status batch_capture(kaldo_ctx ctx, double sigma_thz, int precision
       break;
     }
   }
+  if (st == KALDO_OK) st = batch_persistent_launch(ctx);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
   if (st == KALDO_OK && e != hipSuccess) st = hip_fail(ctx, e, "hipStreamEndCapture");
@@ -718,12 +744,9 @@ static kaldo_status batch_capture(kaldo_ctx ctx, double sigma_thz, int precision
   return st;
 }
 
-kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
-                             kaldo_precision precision, double* const* gamma_out) {
-  if (!ctx) return KALDO_EINVAL;
-  ArenaScope arena_scope(&ctx->arena);
-  ctx->err.clear();
-  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+// Plan and capture the batch graph for these arguments unless it exists.
+static kaldo_status batch_prepare(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                                  kaldo_precision precision) {
   if (ctx->batch.empty()) return fail(ctx, KALDO_ESTATE, "kaldo_batch_run: the batch is empty");
   kaldo_status st;
   if ((st = check_linewidth_args(ctx, T, nT, sigma_thz, KALDO_DELTA_GAUSS, stats, precision)) != KALDO_OK) return st;
@@ -734,6 +757,7 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
     for (int t = 0; t < nT; ++t) sub->T[t] = T[t];
     sub->stats = stats;
     sub->delta = KALDO_DELTA_GAUSS;
+    sub->sigma_thz = sigma_thz;
     sub->have_gamma = false;
   }
   if (ctx->batch_exec && key != ctx->batch_key)
@@ -744,9 +768,30 @@ kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double 
     if ((st = batch_capture(ctx, sigma_thz, precision)) != KALDO_OK) return st;
     ctx->batch_key = key;
   }
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_batch_plan(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                              kaldo_precision precision) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  return batch_prepare(ctx, T, nT, sigma_thz, stats, precision);
+}
+
+kaldo_status kaldo_batch_run(kaldo_ctx ctx, const double* T, int32_t nT, double sigma_thz, kaldo_stats stats,
+                             kaldo_precision precision, double* const* gamma_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  kaldo_status st;
+  if ((st = batch_prepare(ctx, T, nT, sigma_thz, stats, precision)) != KALDO_OK) return st;
   prof_begin(ctx);
   KALDO_HIP(ctx, hipGraphLaunch(ctx->batch_exec, ctx->stream));
   prof_end(ctx, "batch_graph");
+  if ((st = batch_persistent_check(ctx)) != KALDO_OK) return st;
   for (size_t i = 0; i < ctx->batch.size(); ++i) {
     kaldo_ctx sub = ctx->batch[i];
     sub->g_lo = k_lo(sub);
@@ -846,7 +891,7 @@ kaldo_status kaldo_profile_flops(kaldo_ctx ctx, double* executed, double* dense)
     KALDO_HIP(ctx, hipMemcpyAsync(&run, ctx->d_prof_flops.p, sizeof(run), hipMemcpyDeviceToHost, ctx->stream));
     KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
   }
-  if (executed) *executed = (double)run;
+  if (executed) *executed = (double)run + ctx->prof_batch_executed;
   if (dense) *dense = ctx->prof_dense;
   return KALDO_OK;
 }

@@ -46,11 +46,10 @@ __host__ __device__ __forceinline__ int cr_rows(int n) {
 // Z[s][g][e9] for one first-mode k (formed in FP64, stored as RZ: FP64 for the
 // FP64 path, FP32 for the mixed ones)
 template <typename RZ>
-__global__ void k_cr_zg(cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ E,
-                        const int2* __restrict__ cgb, const int* __restrict__ bi, const int* __restrict__ bR2,
-                        const double* __restrict__ bval, int n, int ng, int G0, int G1, int G2, int k) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n * ng * 9) return;
+__device__ __forceinline__ void cr_zg_elem(cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ E,
+                                           const int2* __restrict__ cgb, const int* __restrict__ bi,
+                                           const int* __restrict__ bR2, const double* __restrict__ bval, int n, int ng,
+                                           int G0, int G1, int G2, int k, long long idx) {
   const int e9 = (int)(idx % 9);
   const int g = (int)((idx / 9) % ng);
   const int s = (int)(idx / (9LL * ng));
@@ -73,6 +72,15 @@ __global__ void k_cr_zg(cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict
     im += sr * sn + si * c;
   }
   Z[idx] = {(RZ)re, (RZ)im};
+}
+
+template <typename RZ>
+__global__ void k_cr_zg(cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ E,
+                        const int2* __restrict__ cgb, const int* __restrict__ bi, const int* __restrict__ bR2,
+                        const double* __restrict__ bval, int n, int ng, int G0, int G1, int G2, int k) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * ng * 9) return;
+  cr_zg_elem<RZ>(Z, E, cgb, bi, bR2, bval, n, ng, G0, G1, G2, k, idx);
 }
 
 // Realified eigenvector operands for every grid point, rows cr_row(i, c), K = ldk:
@@ -113,15 +121,13 @@ __global__ void k_cr_realify(typename Operand<P>::T* __restrict__ Ach, typename 
 // partners p = p0 + z.  One thread serves up to ZT partners of the same
 // element, so each Z value is read once per ZT partners.
 template <int P, int ZT, typename RZ>
-__global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand<P>::T* __restrict__ Xl,
-                       const cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ PH,
-                       const int* __restrict__ cg_delta, const int* __restrict__ cg_order,
-                       const int4* __restrict__ cpair, const int* __restrict__ pairmap, int n, int N, int nk, int ng,
-                       int ldk, int p0, int zb) {
+__device__ __forceinline__ void cr_x_elem(typename Operand<P>::T* __restrict__ Xh, typename Operand<P>::T* __restrict__ Xl,
+                                          const cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ PH,
+                                          const int* __restrict__ cg_delta, const int* __restrict__ cg_order,
+                                          const int4* __restrict__ cpair, const int* __restrict__ pairmap, int n,
+                                          int N, int nk, int ng, int ldk, int p0, int zb, long long idx) {
   const int half = ldk / 2;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nn = (long long)n * n;
-  if (idx >= nn * half) return;
   const int a2 = (int)(idx % half);
   const long long row = idx / half;  // s * n + a'
   const int a1 = (int)(row % n);
@@ -154,6 +160,17 @@ __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand
       if (z0 + u < zb)
         store_operand2<P>(Xh, Xl, ((size_t)(z0 + u) * nn + row) * ldk + 2 * (size_t)a2, (double)re[u], (double)im[u]);
   }
+}
+
+template <int P, int ZT, typename RZ>
+__global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand<P>::T* __restrict__ Xl,
+                       const cplx<RZ>* __restrict__ Z, const cplx<double>* __restrict__ PH,
+                       const int* __restrict__ cg_delta, const int* __restrict__ cg_order,
+                       const int4* __restrict__ cpair, const int* __restrict__ pairmap, int n, int N, int nk, int ng,
+                       int ldk, int p0, int zb) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n * (ldk / 2)) return;
+  cr_x_elem<P, ZT, RZ>(Xh, Xl, Z, PH, cg_delta, cg_order, cpair, pairmap, n, N, nk, ng, ldk, p0, zb, idx);
 }
 
 // the realified pair h (0, 1) of a lane's 4 accumulator rows inside a 16-row tile at row m
@@ -313,11 +330,10 @@ struct EpiCrystal {
   }
 };
 
-// gacc[t][s] (+)= sum over batch items, row tiles and s'' (one block per (s, t))
-__global__ void k_cr_collect(double* __restrict__ gacc, const double* __restrict__ partial, int n, int nT,
-                             int m_tiles, int zb, int first) {
-  __shared__ double red[256];
-  const int s = blockIdx.x, t = blockIdx.y;
+// Sum of partial over batch items, row tiles and s'' for one (s, t), by a
+// 256-thread block (fixed order); the result is valid in thread 0.
+__device__ __forceinline__ double cr_collect_sum(const double* __restrict__ partial, int n, int nT, int m_tiles,
+                                                 int zb, int s, int t, double* red) {
   const long long nn = (long long)n * n;
   double v = 0.0;
   for (int z = 0; z < zb; ++z)
@@ -330,7 +346,16 @@ __global__ void k_cr_collect(double* __restrict__ gacc, const double* __restrict
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) gacc[(size_t)t * n + s] = (first ? 0.0 : gacc[(size_t)t * n + s]) + red[0];
+  return red[0];
+}
+
+// gacc[t][s] (+)= sum over batch items, row tiles and s'' (one block per (s, t))
+__global__ void k_cr_collect(double* __restrict__ gacc, const double* __restrict__ partial, int n, int nT,
+                             int m_tiles, int zb, int first) {
+  __shared__ double red[256];
+  const int s = blockIdx.x, t = blockIdx.y;
+  const double v = cr_collect_sum(partial, n, nT, m_tiles, zb, s, t, red);
+  if (threadIdx.x == 0) gacc[(size_t)t * n + s] = (first ? 0.0 : gacc[(size_t)t * n + s]) + v;
 }
 
 // graw[t][k][s] = C / w_ks * gacc[t][s], stored at k and at km = -k (time
@@ -356,10 +381,8 @@ __global__ void k_cr_kmap(int* __restrict__ kmap, int nk, int G0, int G1, int G2
   kmap[idx] = ((km0 + pm0) % G0 * G1 + (km1 + pm1) % G1) * G2 + (km2 + pm2) % G2;
 }
 
-__global__ void k_cr_set_average(double* __restrict__ gamma, const double* __restrict__ graw,
-                                 const int* __restrict__ setid, int n, int nk, int nT) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n * nk * nT) return;
+__device__ __forceinline__ void cr_set_average_elem(double* __restrict__ gamma, const double* __restrict__ graw,
+                                                    const int* __restrict__ setid, int n, int nk, long long idx) {
   const int s = (int)(idx % n);
   const int k = (int)((idx / n) % nk);
   const int t = (int)(idx / ((long long)n * nk));
@@ -373,7 +396,21 @@ __global__ void k_cr_set_average(double* __restrict__ gamma, const double* __res
   gamma[idx] = m / (last - first + 1);
 }
 
+__global__ void k_cr_set_average(double* __restrict__ gamma, const double* __restrict__ graw,
+                                 const int* __restrict__ setid, int n, int nk, int nT) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * nk * nT) return;
+  cr_set_average_elem(gamma, graw, setid, n, nk, idx);
+}
+
 kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double** OCC, cplx<double>** PH);
+
+// lo plane of an operand at an offset (BF16X3 only; null otherwise)
+template <int P>
+__device__ __forceinline__ const void* S_lo(const void* lo, size_t off) {
+  if constexpr (Operand<P>::split == 2) return static_cast<const typename Operand<P>::T*>(lo) + off;
+  else return nullptr;
+}
 
 template <int P, class Epi>
 static int cr_gemm(kaldo_ctx ctx, const std::string& key, const GemmOps& g, const Epi& e) {
@@ -406,12 +443,15 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   if (rs != KALDO_OK) return rs;
   // partners per batch: X and Y of a batch sized to stay in the last-level cache
   const size_t per_z = 2 * (size_t)nn * ldk * S * sizeof(T);
-  const int zb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ((size_t)256 << 20) / per_z));
+  const int zb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ctx->xy_budget / per_z));
   const int mt_max = (mrows + 63) / 64;  // the smallest candidate block tile has 64 rows
   // d_A: [Ac | Ap | X | Y], planes hi then lo of each
   const size_t a_elems = (size_t)nk * mrows * ldk;
   const size_t xy_elems = (size_t)zb * nn * ldk;
-  KALDO_HIP(ctx, ctx->d_A.ensure((2 * a_elems + 2 * xy_elems) * S * sizeof(T)));
+  // a batch plan leaves X and Y out: the persistent kernel runs every crystal
+  // in one shared pool (batch_persistent_prepare)
+  const bool shared_xy = planning(ctx) && ctx->xy_shared;
+  KALDO_HIP(ctx, ctx->d_A.ensure((2 * a_elems + (shared_xy ? 0 : 2 * xy_elems)) * S * sizeof(T)));
   T* Ach = ctx->d_A.as<T>();
   T* Acl = S == 2 ? Ach + a_elems : nullptr;
   T* Aph = Ach + a_elems * S;
@@ -436,7 +476,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   int* kmap = reinterpret_cast<int*>(gr + graw_n);
   KALDO_HIP(ctx, ctx->d_gamma.ensure((size_t)nT * nk * n * sizeof(double)));
   // the K padding of Y (columns >= 2n) is never written by GEMM 1: clear once
-  if (ldk > 2 * n) {
+  if (ldk > 2 * n && !shared_xy) {
     const kaldo_status fs = fill_zero(ctx, Yh, xy_elems * S * sizeof(T));
     if (fs != KALDO_OK) return fs;
   }
@@ -450,6 +490,66 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   delta_scale(ctx->delta, sig, dscale, dnorm);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
+  if (planning(ctx)) {
+    // everything the persistent batch kernel needs to run this crystal
+    CrystalPlan& cp = ctx->cplan;
+    cp = CrystalPlan{};
+    cp.valid = 1;
+    cp.precision = P;
+    cp.n = n;
+    cp.N = N;
+    cp.nk = nk;
+    cp.ng = ng;
+    cp.nT = nT;
+    cp.ldk = ldk;
+    cp.mrows = mrows;
+    cp.zb = zb;
+    cp.G0 = ctx->grid[0];
+    cp.G1 = ctx->grid[1];
+    cp.G2 = ctx->grid[2];
+    cp.klo = k_lo(ctx);
+    cp.khi = k_hi(ctx);
+    cp.m_tiles2 = gemm_m_tiles<P>(0, mrows);
+    cp.xy_elems = (long long)xy_elems;
+    cp.C = C;
+    cp.rs = 1.0 / dscale;
+    cp.Z = Z;
+    cp.Xh = shared_xy ? nullptr : Xh;
+    cp.Xl = shared_xy ? nullptr : Xl;
+    cp.Yh = shared_xy ? nullptr : Yh;
+    cp.Yl = shared_xy ? nullptr : Yl;
+    cp.Ach = Ach;
+    cp.Acl = Acl;
+    cp.Aph = Aph;
+    cp.Apl = Apl;
+    cp.E = ctx->d_evec.p;
+    cp.cgb = L.d_cg_block.p;
+    cp.bi = L.d_blk_i.p;
+    cp.bR2 = L.d_blk_R2.p;
+    cp.bval = L.d_blk_val.p;
+    cp.PH = PH;
+    cp.cg_delta = L.d_cg_delta.p;
+    cp.cg_order = L.d_cg_order.p;
+    cp.cpair = L.d_cpair.p;
+    cp.pairmap = L.d_cpairmap.p;
+    cp.kmap = kmap;
+    cp.OM = OM;
+    cp.IW = IW;
+    cp.OCC = OCC;
+    cp.partial = partial;
+    cp.gacc = gacc;
+    cp.graw = gr;
+    cp.gamma = ctx->d_gamma.as<double>();
+    cp.setid = ctx->d_setid.as<int>();
+    // X and Y do not exist in this context (they come from the shared pool):
+    // nothing below may launch on them, the autotuner's trial GEMMs included
+    // (the persistent kernel uses fixed tile shapes); the first-mode points
+    // are recorded for its rounds
+    if (shared_xy) {
+      int npts = 0;
+      return upload_linewidth_points(ctx, &npts);
+    }
+  }
   // planning visits one first-mode point and the batches whose GEMM shapes differ
   const bool plan = planning(ctx);
   // the first-mode points to compute (one of each pair k, -k on the whole grid)
@@ -550,6 +650,474 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   hipLaunchKernelGGL(k_cr_set_average, dim3(blocks_for((long long)n * nk * nT, TB)), dim3(TB), 0, st,
                      ctx->d_gamma.as<double>(), gr, ctx->d_setid.as<int>(), n, nk, nT);
   KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
+// ---- persistent batch kernel ----------------------------------------------------------
+// One launch runs the linewidths of every planned many-branch crystal of a
+// batch.  Its work queue is a table of rounds (crystal, first-mode point k,
+// partners p0 .. p0 + cnt), the crystals in order of decreasing cost (points x
+// N_k x n^4); each round takes the stages of the per-launch path (step A for a
+// new k, step B, GEMM 1, GEMM 2 with the linewidth epilogue, the collection)
+// as phases over all workgroups, separated by grid barriers.  The grid holds
+// exactly the workgroups that fit on the device at once.  A barrier that waits
+// longer than about two seconds (a workgroup that never became resident) sets
+// an abort flag; every workgroup then leaves, and the host reports the error.
+struct BatchRound {
+  int c, k, km, p0, cnt, first, last, first_crystal;
+};
+struct GridSync {
+  unsigned count, gen, abort, pad;
+  unsigned long long flops;     // MFMA flops of the GEMM block tiles that ran (not skipped)
+  unsigned long long phase[6];  // block 0's constant-rate clock ticks: step A with the collection
+                                // and Y padding, step B, GEMM 1, GEMM 2, waits at grid barriers,
+                                // set average
+};
+
+// block 0 adds the ticks since *t0 to phase p and restarts the clock
+__device__ __forceinline__ void phase_mark(GridSync* gs, int b, unsigned long long& t0, int p) {
+  if (b == 0 && threadIdx.x == 0) {
+    const unsigned long long t = wall_clock64();
+    gs->phase[p] += t - t0;
+    t0 = t;
+  }
+}
+
+// Returns true when the kernel is to be abandoned.
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned nblocks) {
+  __shared__ unsigned s_abort;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned ab = __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ab) {
+      const unsigned g = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();  // this block's writes (all its waves passed the block barrier) reach memory
+      if (__hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1) {
+        __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&gs->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned it = 0;
+        while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          __builtin_amdgcn_s_sleep(4);
+          if ((++it & 1023u) == 0) {
+            if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              ab = 1;
+              break;
+            }
+            if (it >= (1u << 23)) {  // ~2^23 x 256 cycles
+              __hip_atomic_store(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ab = 1;
+              break;
+            }
+          }
+        }
+      }
+      __threadfence();  // the other blocks' writes are visible from here on
+    }
+    s_abort = ab;
+  }
+  __syncthreads();
+  return s_abort != 0;
+}
+
+// The tiles of one GEMM phase over the persistent grid: XCD x (= block % 8)
+// takes a contiguous run of the logical tiles, as a launch of k_gemm would.
+template <int P, int FM, int FN, class Epi>
+__device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int b, int G) {
+  g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
+  g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
+  g.group_m = g.m_tiles < 8 ? g.m_tiles : 8;
+  g.group_n = g.n_tiles;
+  const int total = g.m_tiles * g.n_tiles * g.nz;
+  const int x = b & 7, per = G >> 3, l = b >> 3;
+  const int q = total >> 3, r8 = total & 7;
+  const int start = x * q + (x < r8 ? x : r8), len = q + (x < r8 ? 1 : 0);
+  for (int i = l; i < len; i += per) {
+    int mt, nt, z;
+    gemm_tile_coords(g, start + i, mt, nt, z);
+    gemm_tile<P, FM, FN, Epi>(g, e, mt, nt, z, lds);
+    __syncthreads();
+  }
+}
+
+// Row tiles of the persistent kernel's GEMMs: 32 FM rows, FM chosen per
+// crystal (2, 3 or 4 for FP32 and BF16X3, 2 for FP64) to pad the 2n realified
+// rows least; 32 FN = 128 columns.
+template <int P>
+struct BatchShape {
+  static constexpr int FN = 4;
+  static constexpr bool kFmChoice = P != KALDO_FP64;
+};
+
+inline int batch_fm(int precision, int mrows) {
+  if (precision == KALDO_FP64) return 2;
+  int best = 4;
+  long long best_rows = 1LL << 40;
+  for (int fm = 4; fm >= 2; --fm) {
+    const long long rows = (long long)((mrows + 32 * fm - 1) / (32 * fm)) * 32 * fm;
+    if (rows < best_rows) {
+      best_rows = rows;
+      best = fm;
+    }
+  }
+  return best;
+}
+
+// The stages of one round, each over every workgroup of the grid (grid-stride
+// elements or the XCD-aware tile runs of the GEMMs).
+template <int P, int NT>
+struct BatchStages {
+  using T = typename Operand<P>::T;
+  using RZ = typename std::conditional<P == KALDO_FP64, double, float>::type;
+  using E1 = EpiStoreY<P>;
+  using E2 = EpiCrystal<NT, KALDO_DELTA_GAUSS>;
+  static constexpr int FN = BatchShape<P>::FN;
+  const CrystalPlan* plans;
+  const BatchRound* rounds;
+  GridSync* gs;
+  char* lds;
+  int b, G;
+  long long gtid, gthreads;
+
+  // K padding of the crystal's Y layout in the shared pool (never written by
+  // GEMM 1, read as zeros by GEMM 2)
+  __device__ void zero_pad(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const int n = C.n, ldk = C.ldk;
+    if (ldk <= 2 * n) return;
+    const int pad = ldk - 2 * n;
+    const long long rows = (long long)C.zb * n * n;
+    for (long long i = gtid; i < rows * pad; i += gthreads) {
+      const size_t o = (size_t)(i / pad) * ldk + 2 * n + (size_t)(i % pad);
+      static_cast<T*>(C.Yh)[o] = T{};
+      if constexpr (Operand<P>::split == 2) static_cast<T*>(C.Yl)[o] = T{};
+    }
+  }
+  // step A of a new first-mode point
+  __device__ void step_a(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const long long cnt = (long long)C.n * C.ng * 9;
+    for (long long i = gtid; i < cnt; i += gthreads)
+      cr_zg_elem<RZ>(static_cast<cplx<RZ>*>(C.Z), static_cast<const cplx<double>*>(C.E),
+                     static_cast<const int2*>(C.cgb), static_cast<const int*>(C.bi), static_cast<const int*>(C.bR2),
+                     static_cast<const double*>(C.bval), C.n, C.ng, C.G0, C.G1, C.G2, R.k, i);
+  }
+  __device__ void step_b(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const long long cnt = (long long)C.n * C.n * (C.ldk / 2);
+    for (long long i = gtid; i < cnt; i += gthreads)
+      cr_x_elem<P, 8, RZ>(static_cast<T*>(C.Xh), static_cast<T*>(C.Xl), static_cast<const cplx<RZ>*>(C.Z),
+                          static_cast<const cplx<double>*>(C.PH), static_cast<const int*>(C.cg_delta),
+                          static_cast<const int*>(C.cg_order), static_cast<const int4*>(C.cpair),
+                          static_cast<const int*>(C.pairmap), C.n, C.N, C.nk, C.ng, C.ldk, R.p0, R.cnt, i);
+  }
+  __device__ GemmOps gemm1_ops(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const long long nn = (long long)C.n * C.n;
+    GemmOps g{};
+    g.a_hi = C.Ach;
+    g.a_lo = C.Acl;
+    g.b_hi = C.Xh;
+    g.b_lo = C.Xl;
+    g.lda = g.ldb = C.ldk;
+    g.a_z = (long long)C.mrows * C.ldk;
+    g.b_z = nn * C.ldk;
+    g.a_map = C.kmap + (size_t)R.k * C.nk + R.p0;
+    g.K = C.ldk;
+    g.nz = R.cnt;
+    g.m_valid = C.mrows;
+    g.c_valid = nn;
+    g.tally = &gs->flops;
+    return g;
+  }
+  template <int FM>
+  __device__ void gemm1_fm(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const long long nn = (long long)C.n * C.n;
+    GemmOps g = gemm1_ops(R);
+    g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)C.ldk * (P == KALDO_BF16X3 ? 3 : 1);
+    const E1 e{static_cast<T*>(C.Yh), static_cast<T*>(C.Yl), nn * C.ldk, nn, C.n, C.ldk};
+    gemm_persistent<P, FM, FN>(g, e, lds, b, G);
+  }
+  template <int FM>
+  __device__ void gemm2_fm(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const long long nn = (long long)C.n * C.n;
+    GemmOps g = gemm1_ops(R);
+    g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)C.ldk * (P == KALDO_BF16X3 ? 3 : 1);
+    g.a_hi = static_cast<const T*>(C.Aph) + (size_t)R.p0 * C.mrows * C.ldk;
+    g.a_lo = S_lo<P>(C.Apl, (size_t)R.p0 * C.mrows * C.ldk);
+    g.b_hi = C.Yh;
+    g.b_lo = C.Yl;
+    g.a_map = nullptr;
+    const E2 e{C.OM, C.IW, C.OCC, C.kmap + (size_t)R.k * C.nk + R.p0, C.partial, nn, C.n, C.nk, C.nT, R.k, R.p0,
+               C.m_tiles2, C.rs};
+    gemm_persistent<P, FM, FN>(g, e, lds, b, G);
+  }
+  __device__ void gemm1(const BatchRound& R) const {
+    const int fm = plans[R.c].fm;
+    if constexpr (BatchShape<P>::kFmChoice) {
+      if (fm == 3) gemm1_fm<3>(R);
+      else if (fm == 4) gemm1_fm<4>(R);
+      else gemm1_fm<2>(R);
+    } else {
+      gemm1_fm<2>(R);
+    }
+  }
+  __device__ void gemm2(const BatchRound& R) const {
+    const int fm = plans[R.c].fm;
+    if constexpr (BatchShape<P>::kFmChoice) {
+      if (fm == 3) gemm2_fm<3>(R);
+      else if (fm == 4) gemm2_fm<4>(R);
+      else gemm2_fm<2>(R);
+    } else {
+      gemm2_fm<2>(R);
+    }
+  }
+  // the partial sums of the round into gacc (first round of k: overwrite),
+  // after the last round of k the raw linewidths of k and -k
+  __device__ void collect(const BatchRound& R) const {
+    const CrystalPlan& C = plans[R.c];
+    const int n = C.n, nk = C.nk;
+    for (int st = b; st < n * C.nT; st += G) {
+      const int s = st % n, t = st / n;
+      const double v = cr_collect_sum(C.partial, n, C.nT, C.m_tiles2, R.cnt, s, t, reinterpret_cast<double*>(lds));
+      if (threadIdx.x == 0) {
+        double* ga = C.gacc + (size_t)t * n + s;
+        const double acc = (R.first ? 0.0 : *ga) + v;
+        *ga = acc;
+        if (R.last) {
+          const double w = C.C * C.IW[(size_t)s * nk + R.k] * acc;
+          if (R.k >= C.klo && R.k < C.khi) C.graw[((size_t)t * nk + R.k) * n + s] = w;
+          if (R.km >= C.klo && R.km < C.khi) C.graw[((size_t)t * nk + R.km) * n + s] = w;
+        }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// The rounds run as a two-phase pipeline: phase X of round r holds GEMM 1 of
+// r with step A of r + 1 (a new point), the collection of r - 1 and, at a new
+// crystal, the zeroing of its Y padding; phase Y holds GEMM 2 of r with step
+// B of r + 1.  Every pair of stages in one phase touches disjoint buffers
+// (GEMM 1 reads X and writes Y; step A writes Z, read by step B one phase
+// later; the collection reads the partial sums that GEMM 2 writes one phase
+// later; step B writes X, read by GEMM 1 one phase later), so two grid
+// barriers per round suffice.
+template <int P, int NT>
+__global__ void __launch_bounds__(256)
+    k_batch_persistent(const CrystalPlan* __restrict__ plans, int nplans, const BatchRound* __restrict__ rounds,
+                       int nrounds, GridSync* __restrict__ gs) {
+  using S = BatchStages<P, NT>;
+  constexpr int FN = BatchShape<P>::FN;
+  constexpr int L1 = GemmLds<P, 4, FN, typename S::E1>::bytes, L2 = GemmLds<P, 4, FN, typename S::E2>::bytes;
+  constexpr int LM = L1 > L2 ? L1 : L2;
+  constexpr int LB = LM > 2048 ? LM : 2048;
+  __shared__ __attribute__((aligned(16))) char lds[LB];
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  const S st{plans, rounds, gs, lds, b, G, (long long)b * 256 + threadIdx.x, (long long)G * 256};
+  // points outside a crystal's k range keep gamma = 0
+  for (int c = 0; c < nplans; ++c) {
+    const CrystalPlan& C = plans[c];
+    if (C.klo > 0 || C.khi < C.nk) {
+      const long long cnt = (long long)C.nT * C.nk * C.n;
+      for (long long i = st.gtid; i < cnt; i += st.gthreads) C.graw[i] = 0.0;
+    }
+  }
+  unsigned long long t0 = wall_clock64();
+  if (nrounds > 0) {
+    st.step_a(rounds[0]);
+    if (grid_barrier(gs, G)) return;
+    phase_mark(gs, b, t0, 0);
+    st.step_b(rounds[0]);
+    if (grid_barrier(gs, G)) return;
+    phase_mark(gs, b, t0, 1);
+  }
+  for (int r = 0; r < nrounds; ++r) {
+    const BatchRound R = rounds[r];
+    // phase X
+    st.gemm1(R);
+    phase_mark(gs, b, t0, 2);
+    if (R.first_crystal) st.zero_pad(R);
+    if (r + 1 < nrounds && rounds[r + 1].first) st.step_a(rounds[r + 1]);
+    if (r > 0) st.collect(rounds[r - 1]);
+    phase_mark(gs, b, t0, 0);
+    if (grid_barrier(gs, G)) return;
+    phase_mark(gs, b, t0, 4);
+    // phase Y
+    st.gemm2(R);
+    phase_mark(gs, b, t0, 3);
+    if (r + 1 < nrounds) st.step_b(rounds[r + 1]);
+    phase_mark(gs, b, t0, 1);
+    if (grid_barrier(gs, G)) return;
+    phase_mark(gs, b, t0, 4);
+  }
+  if (nrounds > 0) {
+    st.collect(rounds[nrounds - 1]);
+    if (grid_barrier(gs, G)) return;
+  }
+  // degenerate-set averages of every crystal
+  for (int c = 0; c < nplans; ++c) {
+    const CrystalPlan& C = plans[c];
+    const long long cnt = (long long)C.n * C.nk * C.nT;
+    for (long long i = st.gtid; i < cnt; i += st.gthreads) cr_set_average_elem(C.gamma, C.graw, C.setid, C.n, C.nk, i);
+  }
+  phase_mark(gs, b, t0, 5);
+}
+
+// MFMA flops of every GEMM block tile of the rounds (run or skipped), for the tally.
+template <int P>
+static double batch_dense_flops(const std::vector<CrystalPlan>& plans, const std::vector<BatchRound>& rounds) {
+  constexpr int FN = BatchShape<P>::FN;
+  double total = 0.0;
+  for (const BatchRound& r : rounds) {
+    const CrystalPlan& C = plans[r.c];
+    const int FM = C.fm;
+    const double tiles = (double)((C.mrows + 32 * FM - 1) / (32 * FM)) *
+                         (double)(((long long)C.n * C.n + 32 * FN - 1) / (32 * FN)) * r.cnt;
+    total += 2.0 * tiles * 2.0 * (32 * FM) * (32 * FN) * C.ldk * (P == KALDO_BF16X3 ? 3.0 : 1.0);
+  }
+  return total;
+}
+
+template <int P, int NT>
+static const void* batch_kernel() {
+  return reinterpret_cast<const void*>(&k_batch_persistent<P, NT>);
+}
+
+static const void* batch_kernel_for(int precision, int nt) {
+  if (precision == KALDO_FP64) return nt == 1 ? batch_kernel<KALDO_FP64, 1>() : nt == 4 ? batch_kernel<KALDO_FP64, 4>() : batch_kernel<KALDO_FP64, 8>();
+  if (precision == KALDO_FP32) return nt == 1 ? batch_kernel<KALDO_FP32, 1>() : nt == 4 ? batch_kernel<KALDO_FP32, 4>() : batch_kernel<KALDO_FP32, 8>();
+  return nt == 1 ? batch_kernel<KALDO_BF16X3, 1>() : nt == 4 ? batch_kernel<KALDO_BF16X3, 4>() : batch_kernel<KALDO_BF16X3, 8>();
+}
+
+kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_ctx>& subs, int precision) {
+  parent->batch_nplans = parent->batch_nrounds = 0;
+  std::vector<CrystalPlan> plans;
+  std::vector<std::vector<int>> points;
+  std::vector<double> cost;
+  for (kaldo_ctx sub : subs) {
+    plans.push_back(sub->cplan);
+    points.push_back(sub->klist_host);
+    const double n = sub->cplan.n;
+    cost.push_back((double)sub->klist_host.size() * sub->cplan.nk * n * n * n * n);
+  }
+  if (plans.empty()) return KALDO_OK;
+  std::vector<int> order(plans.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<CrystalPlan> sorted;
+  std::vector<BatchRound> rounds;
+  size_t pool = 0;  // elements of X (and of Y) of the largest crystal's partner batch
+  for (int idx : order) {
+    const CrystalPlan& cp = plans[idx];
+    const int c = (int)sorted.size();
+    sorted.push_back(cp);
+    pool = std::max(pool, (size_t)cp.xy_elems);
+    bool fc = true;
+    for (int k : points[idx]) {
+      const int km = k_mirror(k, cp.G0, cp.G1, cp.G2);
+      for (int p0 = 0; p0 < cp.nk; p0 += cp.zb) {
+        const int cnt = std::min(cp.zb, cp.nk - p0);
+        rounds.push_back(BatchRound{c, k, km, p0, cnt, p0 == 0 ? 1 : 0, p0 + cnt >= cp.nk ? 1 : 0, fc ? 1 : 0});
+        fc = false;
+      }
+    }
+  }
+  // the shared X and Y pool: planes hi then lo of X, then of Y
+  const int split = precision == KALDO_BF16X3 ? 2 : 1;
+  const size_t esz = precision == KALDO_FP64 ? 8 : (precision == KALDO_FP32 ? 4 : 2);
+  const size_t plane = (pool * esz + 255) & ~(size_t)255;
+  KALDO_HIP(parent, parent->d_batch_xy.ensure(2 * split * plane));
+  char* xy = parent->d_batch_xy.as<char>();
+  // KALDO_TUNE_FIXED keeps the fixed tile shape of eager calls (variant 0), so
+  // that batch and eager results agree bit for bit
+  const bool fixed = parent->tuning == KALDO_TUNE_FIXED;
+  for (CrystalPlan& cp : sorted) {
+    cp.fm = fixed ? (precision == KALDO_FP64 ? 2 : 4) : batch_fm(precision, cp.mrows);
+    cp.m_tiles2 = (cp.mrows + 32 * cp.fm - 1) / (32 * cp.fm);
+    cp.Xh = xy;
+    cp.Xl = split == 2 ? xy + plane : nullptr;
+    cp.Yh = xy + split * plane;
+    cp.Yl = split == 2 ? xy + 3 * plane : nullptr;
+  }
+  const size_t pb = (sorted.size() * sizeof(CrystalPlan) + 255) & ~(size_t)255;
+  const size_t rb = (rounds.size() * sizeof(BatchRound) + 255) & ~(size_t)255;
+  KALDO_HIP(parent, parent->d_batch.ensure(pb + rb + 256));
+  char* base = parent->d_batch.as<char>();
+  KALDO_HIP(parent, hipMemcpy(base, sorted.data(), sorted.size() * sizeof(CrystalPlan), hipMemcpyHostToDevice));
+  KALDO_HIP(parent, hipMemcpy(base + pb, rounds.data(), rounds.size() * sizeof(BatchRound), hipMemcpyHostToDevice));
+  int nT = sorted[0].nT;
+  const int nt = nT <= 1 ? 1 : (nT <= 4 ? 4 : 8);
+  // the grid: every workgroup that fits on the device at once, a multiple of 8 (one run per XCD)
+  int per_cu = 0, cus = 0;
+  KALDO_HIP(parent, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(precision, nt), 256, 0));
+  KALDO_HIP(parent, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, parent->device));
+  const int grid = (per_cu * cus) & ~7;
+  if (grid < 8) return fail(parent, KALDO_EDEVICE, "persistent batch kernel: no resident workgroups");
+  parent->batch_grid = grid;
+  parent->batch_nplans = (int)sorted.size();
+  parent->batch_nrounds = (int)rounds.size();
+  parent->batch_precision = precision;
+  parent->batch_nt = nt;
+  parent->batch_rounds_off = pb;
+  parent->batch_sync_off = pb + rb;
+  parent->batch_dense = precision == KALDO_FP64    ? batch_dense_flops<KALDO_FP64>(sorted, rounds)
+                        : precision == KALDO_FP32 ? batch_dense_flops<KALDO_FP32>(sorted, rounds)
+                                                  : batch_dense_flops<KALDO_BF16X3>(sorted, rounds);
+  return KALDO_OK;
+}
+
+kaldo_status batch_persistent_launch(kaldo_ctx parent) {
+  if (parent->batch_nplans == 0) return KALDO_OK;
+  char* base = parent->d_batch.as<char>();
+  const CrystalPlan* plans = reinterpret_cast<const CrystalPlan*>(base);
+  const BatchRound* rounds = reinterpret_cast<const BatchRound*>(base + parent->batch_rounds_off);
+  GridSync* gs = reinterpret_cast<GridSync*>(base + parent->batch_sync_off);
+  kaldo_status st = fill_zero(parent, gs, sizeof(GridSync));
+  if (st != KALDO_OK) return st;
+  const dim3 grid(parent->batch_grid), block(256);
+  const int np = parent->batch_nplans, nr = parent->batch_nrounds;
+  hipStream_t s = parent->stream;
+#define KALDO_BP(PV, NTV) hipLaunchKernelGGL((k_batch_persistent<PV, NTV>), grid, block, 0, s, plans, np, rounds, nr, gs)
+  const int nt = parent->batch_nt;
+  if (parent->batch_precision == KALDO_FP64) {
+    if (nt == 1) KALDO_BP(KALDO_FP64, 1); else if (nt == 4) KALDO_BP(KALDO_FP64, 4); else KALDO_BP(KALDO_FP64, 8);
+  } else if (parent->batch_precision == KALDO_FP32) {
+    if (nt == 1) KALDO_BP(KALDO_FP32, 1); else if (nt == 4) KALDO_BP(KALDO_FP32, 4); else KALDO_BP(KALDO_FP32, 8);
+  } else {
+    if (nt == 1) KALDO_BP(KALDO_BF16X3, 1); else if (nt == 4) KALDO_BP(KALDO_BF16X3, 4); else KALDO_BP(KALDO_BF16X3, 8);
+  }
+#undef KALDO_BP
+  KALDO_HIP(parent, hipGetLastError());
+  return KALDO_OK;
+}
+
+kaldo_status batch_persistent_check(kaldo_ctx parent) {
+  if (parent->batch_nplans == 0) return KALDO_OK;
+  GridSync h{};
+  KALDO_HIP(parent, hipMemcpyAsync(&h, parent->d_batch.as<char>() + parent->batch_sync_off, sizeof(h),
+                                   hipMemcpyDeviceToHost, parent->stream));
+  KALDO_HIP(parent, hipStreamSynchronize(parent->stream));
+  if (h.abort)
+    return fail(parent, KALDO_EDEVICE,
+                "persistent batch kernel: a grid barrier timed out (not every workgroup became resident); "
+                "results are incomplete");
+  if (parent->prof) {
+    parent->prof_batch_executed += (double)h.flops;
+    parent->prof_dense += parent->batch_dense;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, parent->device) == hipSuccess && khz > 0) {
+      static const char* names[6] = {"batch_a_collect", "batch_step_b", "batch_gemm1", "batch_gemm2",
+                                     "batch_barrier_wait", "batch_set_average"};
+      for (int p = 0; p < 6; ++p) {
+        auto& e = parent->prof_tab[names[p]];
+        e.total_ms += (double)h.phase[p] / (double)khz;
+        e.launches += 1;
+      }
+    }
+  }
   return KALDO_OK;
 }
 

@@ -125,6 +125,47 @@ __device__ __forceinline__ int lds_off(int row, int slot) {
   else return row * (CB + 16) + slot * 16;
 }
 
+// LDS bytes of one block tile of k_gemm<P, FM, FN, Epi, BD, WC>.
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
+struct GemmLds {
+  using T = typename Operand<P>::T;
+  static constexpr int S = Operand<P>::split;
+  static constexpr int BM = 32 * FM, BN = 32 * FN;
+  static constexpr int CB = WC ? 128 : GemmChunk<P>::CB;
+  static constexpr int NBUF = WC ? 1 : 2;
+  static constexpr int RB = CB == 64 ? 64 : CB + 16;
+  static constexpr int ROWS = BM + (BD ? 0 : BN);
+  static constexpr int BUF = S * ROWS * RB;
+  static constexpr int bytes = NBUF * BUF;
+};
+
+// Block tile (mt, nt) of batch item z for the logical tile index `tile`:
+// within an item, tiles go in groups of GM row tiles (group_m, 8 by default),
+// M fastest inside a group: the blocks that run at the same time on one XCD
+// then cover about GM x (64 / GM) tiles and share both operand panels in L2
+// (with M fastest over all row tiles, every N tile streams the whole A panel
+// again from beyond L2).  Optionally the column panels first go in chunks of
+// GN (group_n); the ordering above then applies inside each chunk.
+__device__ __forceinline__ void gemm_tile_coords(const GemmOps& g, int tile, int& mt, int& nt, int& z) {
+  const int GM = g.group_m;
+  const int per_z = g.m_tiles * g.n_tiles;
+  z = tile / per_z;
+  int tz = tile - z * per_z;
+  const int GN = g.group_n;
+  const int chunk = tz / (g.m_tiles * GN);
+  tz -= chunk * g.m_tiles * GN;
+  const int width = min(GN, g.n_tiles - chunk * GN);
+  const int per_group = GM * width;
+  const int first_m = (tz / per_group) * GM;
+  const int gm = min(g.m_tiles - first_m, GM);
+  const int tg = tz - (tz / per_group) * per_group;
+  mt = first_m + tg % gm;
+  nt = chunk * GN + tg / gm;
+}
+
+// One block tile (mt, nt, z): skip test, staged K loop and epilogue.  `lds`
+// holds at least GemmLds<...>::bytes; the caller synchronises the block
+// before reusing it for another tile.
 // BD (BF16X3 only): B fragments go from global memory (L1/L2) straight to the
 // wavefront's registers one chunk ahead, and LDS stages A alone.  The split
 // operands make BF16X3 LDS-bound; this halves its LDS traffic.
@@ -133,7 +174,7 @@ __device__ __forceinline__ int lds_off(int row, int slot) {
 // chunk's MFMAs.  Twice the MFMA work per barrier in the same LDS space as the
 // double-buffered 64-byte chunks; faster on long contractions.
 template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
-__global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
+__device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int mt, int nt, int z, char* lds) {
   using T = typename Operand<P>::T;
   using Acc = typename Operand<P>::Acc;
   constexpr int S = Operand<P>::split;
@@ -142,7 +183,6 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   constexpr int BM = 32 * FM, BN = 32 * FN;
   constexpr int CB = WC ? 128 : GemmChunk<P>::CB;
   constexpr int KCH = CB / (int)sizeof(T);    // elements per row chunk
-  constexpr int NBUF = WC ? 1 : 2;            // LDS buffers
   constexpr int RB = CB == 64 ? 64 : CB + 16; // LDS bytes per tile row (see lds_off)
   constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
   constexpr int RPP = 256 / SLOTS;            // rows loaded per pass of the block
@@ -152,33 +192,6 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   constexpr int ROWS = BM + (BD ? 0 : BN);
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
-  __shared__ __attribute__((aligned(16))) char lds[NBUF * BUF];
-
-  // XCD-aware order: logical tile = start of this XCD's run + position in it
-  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
-  const int q = nb >> 3, r8 = nb & 7, x = b & 7;
-  const int tile = x * q + (x < r8 ? x : r8) + (b >> 3);
-  // within a batch item, tiles go in groups of GM row tiles (group_m, 8 by
-  // default), M fastest inside a group: the blocks that run at the same time
-  // on one XCD then cover about GM x (64 / GM) tiles and share both operand
-  // panels in L2 (with M fastest over all row tiles, every N tile streams the
-  // whole A panel again from beyond L2)
-  const int GM = g.group_m;
-  const int per_z = g.m_tiles * g.n_tiles;
-  const int z = tile / per_z;
-  int tz = tile - z * per_z;
-  // optionally the column panels first go in chunks of GN (group_n): the
-  // ordering above then applies inside each chunk
-  const int GN = g.group_n;
-  const int chunk = tz / (g.m_tiles * GN);
-  tz -= chunk * g.m_tiles * GN;
-  const int width = min(GN, g.n_tiles - chunk * GN);
-  const int per_group = GM * width;
-  const int first_m = (tz / per_group) * GM;
-  const int gm = min(g.m_tiles - first_m, GM);
-  const int tg = tz - (tz / per_group) * per_group;
-  const int mt = first_m + tg % gm;
-  const int nt = chunk * GN + tg / gm;
   if constexpr (SkipEmpty<Epi>::value) {
     // uniform across the block (block indices and operand-independent data only)
     if (epi.template tile_empty<P, FM, FN>(mt, nt, z)) {
@@ -416,6 +429,18 @@ __global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
   at.wn = wn;
   // the operand buffers are free after the last barrier: the epilogue may use them
   epi.template apply<P, FM, FN>(acc, at, lds);
+}
+
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
+__global__ void __launch_bounds__(256) k_gemm(GemmOps g, Epi epi) {
+  __shared__ __attribute__((aligned(16))) char lds[GemmLds<P, FM, FN, Epi, BD, WC>::bytes];
+  // XCD-aware order: logical tile = start of this XCD's run + position in it
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = nb >> 3, r8 = nb & 7, x = b & 7;
+  const int tile = x * q + (x < r8 ? x : r8) + (b >> 3);
+  int mt, nt, z;
+  gemm_tile_coords(g, tile, mt, nt, z);
+  gemm_tile<P, FM, FN, Epi, BD, WC>(g, epi, mt, nt, z, lds);
 }
 
 // Per-column partial sums of a linewidth epilogue, in two steps.  column_put

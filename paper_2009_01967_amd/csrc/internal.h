@@ -119,6 +119,25 @@ struct Fc3Layout {
 }  // namespace kaldo
 
 namespace kaldo {
+// Device pointers and sizes of a planned many-branch linewidth run of one
+// crystal (recorded by the planning pass; the persistent batch kernel runs the
+// crystal from them).  Plain data, copied to the device as is.
+struct CrystalPlan {
+  int valid, precision;
+  int n, N, nk, ng, nT, ldk, mrows, zb, G0, G1, G2, klo, khi;
+  int m_tiles2;     // row tiles of GEMM 2 in the persistent kernel's tile shape
+  int fm;           // that shape's rows / 32
+  long long xy_elems;  // elements of X (and of Y) for one partner batch
+  double C, rs;     // linewidth prefactor / N_k with the delta's normalisation; 1 / delta scale
+  void *Z, *Xh, *Xl, *Yh, *Yl;
+  const void *Ach, *Acl, *Aph, *Apl;
+  const void *E, *cgb, *bi, *bR2, *bval, *PH, *cg_delta, *cg_order, *cpair, *pairmap;
+  const int* kmap;
+  const double *OM, *IW, *OCC;
+  double *partial, *gacc, *graw, *gamma;
+  const int* setid;
+};
+
 // How a stage runs: kRun launches everything; kPlan sizes every buffer, builds
 // the mode tables and settles the tile shape of each GEMM problem, but skips
 // the heavy launches; kCapture launches everything with no allocation, no
@@ -211,6 +230,16 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_scratch2;
   kaldo::DevBuf d_bte;               // full BTE: scattering operator pieces, set tables, solve
   kaldo::DevBuf d_klist;             // first-mode points a linewidth run computes (int)
+  kaldo::CrystalPlan cplan{};        // the last planning pass of the many-branch path
+  size_t xy_budget = (size_t)256 << 20;  // bytes of step-B and GEMM-1 outputs per partner batch
+  bool xy_shared = false;                // planning a batch: X and Y come from the parent's shared pool
+  // persistent batch kernel: plans, rounds and barrier state (parent context)
+  kaldo::DevBuf d_batch;
+  kaldo::DevBuf d_batch_xy;          // the persistent kernel's shared X and Y pool
+  int batch_grid = 0, batch_nplans = 0, batch_nrounds = 0, batch_precision = -1, batch_nt = 1;
+  size_t batch_rounds_off = 0, batch_sync_off = 0;
+  double batch_dense = 0.0;          // MFMA flops of every tile of one launch of the persistent kernel
+  double prof_batch_executed = 0.0;  // tallied flops of persistent launches since profiling was enabled
   std::vector<int> klist_host;       // its host copy (kept alive for the stream-ordered upload)
 };
 
@@ -285,5 +314,11 @@ kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
 kaldo_status run_mode_diffusivity(kaldo_ctx ctx);
 kaldo_status run_kappa_bte(kaldo_ctx ctx, int method, int max_terms, double tol, double* kappa_out, int* terms_out);
+// persistent batch kernel over the crystals of `subs` planned for `precision`:
+// prepare (before capture: plans and rounds to the device) and launch (on the
+// parent's stream, capturable); check reads its barrier flag after a launch
+kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_ctx>& subs, int precision);
+kaldo_status batch_persistent_launch(kaldo_ctx parent);
+kaldo_status batch_persistent_check(kaldo_ctx parent);
 
 }  // namespace kaldo

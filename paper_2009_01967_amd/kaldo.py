@@ -52,7 +52,7 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
             "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity",
-            "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte"]
+            "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte", "kaldo_batch_plan"]
 
 
 class kaldo_structure(C.Structure):
@@ -126,6 +126,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_batch_run.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int, C.c_int,
                                     C.POINTER(C.c_void_p)]
     lib.kaldo_batch_run.restype = C.c_int
+    lib.kaldo_batch_plan.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_int, C.c_int]
+    lib.kaldo_batch_plan.restype = C.c_int
     lib.kaldo_batch_clear.argtypes = [C.c_void_p]
     lib.kaldo_batch_clear.restype = C.c_int
     lib.kaldo_set_tuning.argtypes = [C.c_void_p, C.c_int]
@@ -300,6 +302,11 @@ def kaldo_batch_run(ctx, T: Sequence[float], sigma_thz: float, stats: int, preci
             p = _out_ptr(o)
             arr[i] = p.value if p is not None else None
     return load_library().kaldo_batch_run(ctx, Ts, len(T), float(sigma_thz), int(stats), int(precision), arr)
+
+
+def kaldo_batch_plan(ctx, T: Sequence[float], sigma_thz: float, stats: int, precision: int) -> int:
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    return load_library().kaldo_batch_plan(ctx, Ts, len(T), float(sigma_thz), int(stats), int(precision))
 
 
 def kaldo_batch_clear(ctx) -> int:
