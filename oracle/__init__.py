@@ -28,9 +28,12 @@ Disordered Solids" (arXiv:2009.01967) literally, in float64, with NumPy/LAPACK:
                       (eqs. inversemeanfreepath, full_conductivity) and by the
                       self-consistent series (eqs. mfp_from_scattering_inv,
                       self-consistent).
+* ``interpolation`` -- linewidths interpolated in frequency with a natural
+                      cubic spline, from a smaller cell to a larger one (Sec.
+                      II.C, Sec. IV.B).
 
 Readings of points the paper leaves open are listed in each module's header.
 Every function here is pinned by tests that do not re-type its formula.
 """
 
-from . import units, phonons, anharmonic, conductivity, scattering  # noqa: F401
+from . import units, phonons, anharmonic, conductivity, scattering, interpolation  # noqa: F401

@@ -24,6 +24,13 @@ Readings of points the paper leaves open:
 * The diffusivity is given per Cartesian direction a (|v_{mu mu' a}|^2), in
   mm^2/s, without the printed 1/(N_k V), which does not give a diffusivity's
   units; with c = k_B it satisfies k_B sum_mu D_mu,a = V kappa_aa.
+* The QHGK bandwidth option (Appendix A) replaces every mode's linewidth in the
+  Lorentzian lifetime by the one given width eta [rad/ps]: tau_{mu mu'} =
+  2 eta / ((w - w')^2 + 4 eta^2), a Lorentzian in w - w' of half width 2 eta
+  and area pi, the broadened delta of the Allen-Feldman model.
+* The QHGK energy threshold (Appendix A) is read as keeping the pairs that
+  are close in frequency: tau_{mu mu'} = 0 when |w - w'| > w_thr (the
+  printed inequality, which would drop the diagonal, is reversed).
 """
 
 from __future__ import annotations
@@ -98,14 +105,22 @@ def generalized_heat_capacity(omega, T, stats='quantum'):
     return np.where(near, cd, c)
 
 
-def lorentzian_lifetime(omega, gamma):
+def lorentzian_lifetime(omega, gamma, bandwidth=None, threshold=None):
+    """tau_{mu mu'} = (g + g') / ((w - w')^2 + (g + g')^2) (Sec. II.C, eq.
+    lorentzian_amorphous) [ps]; with a bandwidth eta every g is eta; with a
+    threshold, 0 where |w - w'| > threshold (Appendix A)."""
+    if bandwidth is not None:
+        gamma = np.full_like(np.asarray(omega, dtype=float), float(bandwidth))
     g = gamma[:, None] + gamma[None, :]
     dw = omega[:, None] - omega[None, :]
     with np.errstate(divide='ignore', invalid='ignore'):
-        return g / (dw * dw + g * g)
+        tau = g / (dw * dw + g * g)
+    if threshold is not None:
+        tau = np.where(np.abs(dw) > threshold, 0.0, tau)
+    return tau
 
 
-def mode_diffusivity(crystal, ph, gamma):
+def mode_diffusivity(crystal, ph, gamma, bandwidth=None, threshold=None):
     """Mode diffusivity at Gamma (Sec. II.C, eq. diffusivity_per_mode), per
     Cartesian direction: D[t][mu][a] = sum_mu' |v_{mu mu' a}|^2 tau_{mu mu'}
     in mm^2/s, with tau the Lorentzian lifetime of the QHGK conductivity at
@@ -114,14 +129,15 @@ def mode_diffusivity(crystal, ph, gamma):
     conductivity sum, not of D, and dropped.  gamma: (nT, 1, n) [rad/ps].
     Masked modes have D = 0 (their velocities are zero).  Within a degenerate
     set only the sum over the set is independent of the eigenvector basis, so
-    D is averaged over each set, as the linewidths are."""
+    D is averaged over each set, as the linewidths are.  bandwidth and
+    threshold are the QHGK options of lorentzian_lifetime."""
     assert ph.n_k == 1
     v = generalized_velocity(crystal, ph)              # (3, n, n), A/ps
     w = ph.omega[0]
     n = len(w)
     out = np.zeros((gamma.shape[0], n, 3))
     for it in range(gamma.shape[0]):
-        tau = lorentzian_lifetime(w, gamma[it, 0])     # ps
+        tau = lorentzian_lifetime(w, gamma[it, 0], bandwidth, threshold)     # ps
         for a in range(3):
             out[it, :, a] = np.sum(np.where(np.abs(v[a]) > 0, np.abs(v[a]) ** 2 * tau, 0.0), axis=1)
         for S in ph.sets[0]:
@@ -129,8 +145,9 @@ def mode_diffusivity(crystal, ph, gamma):
     return out * 1e-2                                   # A^2/ps -> mm^2/s
 
 
-def kappa_qhgk(crystal, ph, gamma, T, stats='quantum'):
-    """gamma: (nT, 1, n) linewidths at Gamma [rad/ps]. Returns (nT, 3, 3) W/m/K."""
+def kappa_qhgk(crystal, ph, gamma, T, stats='quantum', bandwidth=None, threshold=None):
+    """gamma: (nT, 1, n) linewidths at Gamma [rad/ps]. Returns (nT, 3, 3) W/m/K.
+    bandwidth and threshold are the QHGK options of lorentzian_lifetime."""
     assert ph.n_k == 1
     T = np.atleast_1d(np.asarray(T, dtype=float))
     V = volume(crystal)
@@ -141,7 +158,7 @@ def kappa_qhgk(crystal, ph, gamma, T, stats='quantum'):
     out = np.zeros((len(T), 3, 3))
     for it, t in enumerate(T):
         c = generalized_heat_capacity(w, t, stats)
-        tau = lorentzian_lifetime(w, gamma[it, 0])
+        tau = lorentzian_lifetime(w, gamma[it, 0], bandwidth, threshold)
         wgt = np.where(mm, c * tau, 0.0)
         out[it] = np.real(np.einsum('st,ast,bst->ab', wgt, v, v.conj())) / V
     return out * units.KAPPA_TO_SI

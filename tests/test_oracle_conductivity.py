@@ -219,3 +219,65 @@ def test_hand_worked_two_mode_qhgk_and_diffusivity():
     assert D[0, 0] == pytest.approx(v01 ** 2 * 0.25 * 1e-2, rel=1e-13)
     assert D[1, 0] == pytest.approx(v01 ** 2 * 0.25 * 1e-2, rel=1e-13)
     assert np.abs(D[2]).max() == 0.0 and np.abs(D[:, 1:]).max() == 0.0
+
+
+# ---- the QHGK options of Appendix A: a bandwidth (Allen-Feldman) and an energy threshold
+
+def test_hand_worked_bandwidth_replaces_every_linewidth():
+    """With a bandwidth eta = 0.5 rad/ps every linewidth is eta, so the pair
+    width is 2 eta = 1 and tau_01 = 1 / ((10 - 12)^2 + 1) = 0.2 ps, whatever
+    linewidths are passed; the diagonal lifetime is 1 / (2 eta) = 1 ps."""
+    c, ph = _two_mode_cell(), _two_mode_phonons()
+    v01 = 1.5 * units.EV_IN_AMU_A2_PS2 / (8.0 * np.sqrt(120.0))
+    for g in (np.array([[[0.5, 1.5, 0.2]]]), np.array([[[3.0, 0.01, 7.0]]])):
+        k = C.kappa_qhgk(c, ph, g, [300.0], stats="classical", bandwidth=0.5)[0]
+        assert k[0, 0] == pytest.approx(2.0 * units.KB * 0.2 * v01 ** 2 / 125.0 * units.KAPPA_TO_SI, rel=1e-13)
+        D = C.mode_diffusivity(c, ph, g, bandwidth=0.5)[0]
+        assert D[0, 0] == pytest.approx(v01 ** 2 * 0.2 * 1e-2, rel=1e-13)
+    tau = C.lorentzian_lifetime(np.array([1.0, 4.0]), np.array([9.0, 9.0]), bandwidth=0.25)
+    assert np.allclose(np.diag(tau), 2.0)
+    assert tau[0, 1] == pytest.approx(0.5 / (9.0 + 0.25), rel=1e-14)
+
+
+def test_hand_worked_threshold_drops_pairs_beyond_the_gap():
+    """The one coupled pair has the gap |10 - 12| = 2 rad/ps: a threshold of
+    1.5 drops it (kappa = D = 0), a threshold of exactly 2 keeps it."""
+    c, ph = _two_mode_cell(), _two_mode_phonons()
+    g = np.array([[[0.5, 1.5, 0.2]]])
+    assert np.abs(C.kappa_qhgk(c, ph, g, [300.0], stats="classical", threshold=1.5)).max() == 0.0
+    assert np.abs(C.mode_diffusivity(c, ph, g, threshold=1.5)).max() == 0.0
+    k_all = C.kappa_qhgk(c, ph, g, [300.0], stats="classical")
+    assert np.array_equal(C.kappa_qhgk(c, ph, g, [300.0], stats="classical", threshold=2.0), k_all)
+    w = np.array([1.0, 2.0, 4.5, 4.6])
+    tau = C.lorentzian_lifetime(w, np.full(4, 0.1), threshold=1.0)
+    kept = np.abs(w[:, None] - w[None, :]) <= 1.0
+    assert np.array_equal(tau > 0, kept)                 # brute force over the 16 pairs
+
+
+def test_threshold_above_the_spectrum_changes_nothing(folded):
+    """A threshold wider than the whole spectrum keeps every pair: bitwise the
+    conductivity and diffusivity without one."""
+    c, ph, sc, phs = folded
+    rng = np.random.default_rng(5)
+    g = rng.uniform(0.05, 0.5, size=(1, 1, sc.n_modes))
+    wmax = phs.omega.max() * 1.01
+    assert np.array_equal(C.kappa_qhgk(sc, phs, g, [300.0], threshold=wmax), C.kappa_qhgk(sc, phs, g, [300.0]))
+    assert np.array_equal(C.mode_diffusivity(sc, phs, g, threshold=wmax), C.mode_diffusivity(sc, phs, g))
+
+
+def test_threshold_splits_the_classical_sum_rule(folded):
+    """k_B sum_mu D_mu,a = V kappa_aa holds pair by pair, so it holds with any
+    threshold, and kappa falls monotonically as the threshold narrows (every
+    classical term c tau v^2 is >= 0)."""
+    c, ph, sc, phs = folded
+    rng = np.random.default_rng(6)
+    g = rng.uniform(0.05, 0.5, size=(1, 1, sc.n_modes))
+    prev = np.inf
+    for thr in (80.0, 10.0, 3.0, 0.5):
+        k = C.kappa_qhgk(sc, phs, g, [300.0], stats="classical", threshold=thr)[0]
+        D = C.mode_diffusivity(sc, phs, g, threshold=thr)[0]
+        lhs = units.KB * D.sum(axis=0) * 1e2
+        rhs = C.volume(sc) * np.diag(k) / units.KAPPA_TO_SI
+        assert np.allclose(lhs, rhs, rtol=1e-10)
+        assert np.trace(k) <= prev * (1 + 1e-12)
+        prev = np.trace(k)
