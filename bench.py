@@ -41,12 +41,12 @@ BF16_MFMA_PEAK = 2.5e15         # dense bf16 MFMA
 FP32_MFMA_PEAK = 157.3e12
 FP64_MFMA_PEAK = 78.6e12
 MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
-# HBM bytes per launch of the headline kernel: rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE over this benchmark (--steps 2 --warmup 1 --no-cpu --no-mfma), each
-# scaled by what the counter reads for a plain 1 GiB device copy
-# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Taken on the
-# current k_project_small; set to None when that kernel changes.
-HEADLINE_TRAFFIC = None
+# HBM bytes per launch of the headline kernel (k_batch_persistent<1,1>, the
+# full draw): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over this benchmark
+# (--no-cpu --no-mfma --no-c2), each scaled by what the counter reads for a
+# plain 1 GiB device copy (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0).  Set to None when that kernel changes.
+HEADLINE_TRAFFIC = {"fetch_bytes": 63076947573 * 1024 * 2.0, "write_bytes": 84147881386 * 1024 * 1.0}
 
 
 def log(*a):
@@ -171,6 +171,68 @@ def run_c2(steps=20, warmup=3):
                 wall64=wall64, kern32=kern32, kern64=kern64, g32=g32, g64=g64, k32=k32, k64=k64)
 
 
+def qhgk_options_section(ctx, c, T, sigma, stream, steps):
+    """The QHGK options of Appendix A on a Gamma cell whose FP64 linewidths are
+    resident: kappa_QHGK with every pair, with an energy threshold, with a
+    bandwidth (Allen-Feldman), and from linewidths interpolated in frequency
+    from the smaller cell of the same alloy (3^3 instead of 5^3 conventional
+    cells), whose linewidths the GPU computes here (FP32)."""
+    import torch
+    from gen import sige_supercell
+    from paper_2009_01967_amd import kaldo
+
+    def timed_kappa():
+        kaldo.kaldo_profile_enable(ctx.h, True)
+        for _ in range(steps):
+            k = ctx.kappa_qhgk()
+        tot, cnt = kaldo.kaldo_profile_read(ctx.h, "kappa_qhgk")
+        kaldo.kaldo_profile_enable(ctx.h, False)
+        return k, tot / max(cnt, 1)
+
+    n = c.n_modes
+    w = 2.0 * np.pi * ctx.phonons(None, grid=c.grid)[0]
+    g64 = np.zeros((len(T), 1, n))
+    kaldo._check(ctx.h, kaldo.kaldo_linewidths(ctx.h, None, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP64, g64))
+    k_all, ms_all = timed_kappa()
+    out = {"kappa_xx_all_pairs": float(k_all[0, 0, 0]), "pair_sum_ms_all": ms_all}
+    dw = np.abs(w[:, None] - w[None, :])
+    for thr in (1.0, 4.0):
+        ctx.qhgk_options(threshold=thr)
+        k, ms = timed_kappa()
+        out[f"threshold_{thr:g}_rad_ps"] = {"kappa_rel_change": float(np.abs(k - k_all).max() / np.abs(k_all).max()),
+                                            "pairs_kept_frac": float(np.mean(dw <= thr)), "pair_sum_ms": ms}
+    ctx.qhgk_options()
+    eta = 0.5
+    ctx.qhgk_options(bandwidth=eta)
+    k_af, ms = timed_kappa()
+    ctx.qhgk_options()
+    out["allen_feldman_bandwidth_0.5_rad_ps"] = {"kappa_xx": float(k_af[0, 0, 0]), "pair_sum_ms": ms}
+    # interpolation from the 216-atom cell
+    small = sige_supercell(reps=3)
+    sctx = kaldo.Context(0, stream.cuda_stream)
+    nu_s = sctx.phonons(small)
+    sctx.linewidths(small, T=T, sigma_thz=sigma, precision="fp32")   # uploads fc3, tunes the tiles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_s = sctx.linewidths(None, T=T, sigma_thz=sigma, precision="fp32")
+    small_ms = (time.perf_counter() - t0) * 1e3
+    sctx.close()
+    kaldo.kaldo_profile_enable(ctx.h, True)
+    gi = ctx.gamma_interpolate(2.0 * np.pi * nu_s.reshape(-1), g_s.reshape(len(T), -1), n_bins=48, T=T)
+    tot, cnt = kaldo.kaldo_profile_read(ctx.h, "gamma_interpolate")
+    kaldo.kaldo_profile_enable(ctx.h, False)
+    k_i, _ = timed_kappa()
+    mask = g64 > 0
+    out["interpolated_from_216_atoms"] = {
+        "n_bins": 48, "small_cell_linewidths_ms": small_ms, "interpolate_ms": tot / max(cnt, 1),
+        "kappa_rel_diff_vs_computed_gamma": float(np.abs(k_i - k_all).max() / np.abs(k_all).max()),
+        "gamma_median_rel_diff": float(np.median(np.abs(gi[mask] - g64[mask]) / g64[mask]))}
+    # leave the computed FP64 linewidths resident again
+    kaldo._check(ctx.h, kaldo.kaldo_linewidths(ctx.h, None, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP64, None))
+    log(f"qhgk options: {out}")
+    return out
+
+
 def run_mfma(name, steps, warmup):
     """Linewidths and kappa of a many-branch workload on resident phonons, BF16X3,
     FP32 and FP64, with the projection GEMMs timed through the library's hooks;
@@ -257,6 +319,7 @@ def run_mfma(name, steps, warmup):
                              "unit": "GB/s", "frac": nbytes / (kms * 1e-3) / 8e12 if kms else None,
                              "traffic": None, "bytes_per_launch": nbytes}}
         log(f"{name} mode diffusivity: {diff['ms_per_call']:.3f} ms per call, pair sum {kms:.3f} ms")
+        diff["qhgk_options"] = qhgk_options_section(ctx, c, T, sigma, stream, steps)
     ctx.close()
     lw = nk * n * len(T)
     # algorithmic GEMM flops of the computed first-mode points, one V for both signs
@@ -588,9 +651,7 @@ def c2_section(r):
             "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
-            "traffic": ((HEADLINE_TRAFFIC["fetch_kib"] * HEADLINE_TRAFFIC["fetch_scale"] +
-                         HEADLINE_TRAFFIC["write_kib"] * HEADLINE_TRAFFIC["write_scale"]) * 1024.0
-                        if HEADLINE_TRAFFIC else None),
+            "traffic": None,
             "intermediate_bytes": intermediate_bytes(nk, n, nd, nT, npts),
             "algorithmic_bytes": survey_algorithmic_bytes(r["c"], nT),
             "flops_per_launch": f_b + f_c,
@@ -728,7 +789,9 @@ def main():
             "bound": "mfma", "kernel": "k_batch_persistent<1,1> (FP32, one temperature)",
             "achieved": b["fc"] / (kms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": b["fc"] / (kms * 1e-3) / FP32_MFMA_PEAK,
-            "traffic": None,
+            "traffic": (HEADLINE_TRAFFIC["fetch_bytes"] + HEADLINE_TRAFFIC["write_bytes"]
+                        if HEADLINE_TRAFFIC and b["share"] == 1 else None),
+            "traffic_unit": "bytes per launch (HBM, calibrated FETCH_SIZE + WRITE_SIZE)",
             "basis": "algorithmic GEMM flops F_C = 16 N_k n^4 per computed first-mode point, summed over the "
                      "crystals, per launch, over the launch's duration (library events on the stream)",
             "flops_per_launch": b["fc"],

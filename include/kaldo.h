@@ -14,7 +14,13 @@
  *   kaldo_kappa_rta   RTA conductivity of a crystal (Sec. II.B, eq. RTA)
  *   kaldo_mode_diffusivity  mode diffusivity at Gamma (Sec. II.C)
  *   kaldo_kappa_qhgk  QHGK conductivity at Gamma (Sec. II.C,
- *                     eq. conductivity_amorphous .. lorentzian_amorphous)
+ *                     eq. conductivity_amorphous .. lorentzian_amorphous),
+ *                     with the bandwidth and threshold options of Appendix A
+ *                     (kaldo_qhgk_options)
+ *   kaldo_kappa_bte   full linearised BTE (Sec. II.B), inverse or
+ *                     self-consistent
+ *   kaldo_gamma_interpolate  gamma(omega) from a smaller cell by cubic
+ *                     splines (Sec. II.C, Sec. IV.B)
  *
  * Units: length A, mass amu, energy eV (fc2 in eV/A^2, fc3 in eV/A^3),
  * temperature K, frequency nu in THz, angular frequency and linewidth in
@@ -292,6 +298,58 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
  * Errors: KALDO_ESTATE before kaldo_linewidths, KALDO_EINVAL for a grid other
  * than {1,1,1} or d_out == NULL. */
 kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out);
+
+/* Options of the QHGK conductivity (paper Appendix A, the "QHGK" engine) for
+ * the later kaldo_kappa_qhgk and kaldo_mode_diffusivity calls on this context:
+ *   bandwidth  eta [rad/ps] > 0: every mode's linewidth in the Lorentzian
+ *              lifetime is eta, tau_{mu mu'} = 2 eta / ((w - w')^2 + 4 eta^2)
+ *              (the broadened delta of the Allen-Feldman model); 0: the
+ *              resident linewidths (the default)
+ *   threshold  w_thr [rad/ps] > 0: tau_{mu mu'} = 0 when |w - w'| > w_thr
+ *              (the paper prints the inequality reversed, which would drop
+ *              the diagonal); the kernels then read only the band of
+ *              frequency-close pairs of V_d; 0: every pair (the default)
+ * Errors: KALDO_EINVAL for negative or non-finite values. */
+kaldo_status kaldo_qhgk_options(kaldo_ctx ctx, double bandwidth, double threshold);
+
+/* Installs linewidths computed elsewhere as the resident gamma of the modes
+ * of the last kaldo_phonons call, with the temperatures and statistics the
+ * conductivity calls use (paper Sec. II.C: QHGK needs only gamma_mu; with a
+ * bandwidth (kaldo_qhgk_options) it needs none, the Allen-Feldman model).
+ *   T       [nT] temperatures [K], host memory, 1 <= nT <= KALDO_MAX_T
+ *   gamma   [nT][Nk][n] linewidths [rad/ps], finite and >= 0, host or device
+ *           memory; NULL installs zeros
+ * The resident gamma then serves kaldo_kappa_rta, kaldo_kappa_qhgk and
+ * kaldo_mode_diffusivity; kaldo_kappa_bte still needs kaldo_linewidths.
+ * Errors: KALDO_ESTATE before kaldo_phonons, KALDO_EINVAL for bad arguments. */
+kaldo_status kaldo_set_gamma(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats, const double* gamma);
+
+/* Linewidths interpolated in frequency (paper Sec. II.C and Sec. IV.B: gamma
+ * of a smaller cell, interpolated with third-order splines, for a larger
+ * one), installed as the resident gamma of this context's modes as
+ * kaldo_set_gamma does.  From the source modes with nu >= 0.01 THz:
+ *   1. n_bins bins of equal width between their lowest and highest omega,
+ *      bin floor((w - w_lo) / (w_hi - w_lo) n_bins) (the highest mode in the
+ *      last bin); each non-empty bin is one knot, (mean omega, mean gamma);
+ *   2. the natural cubic spline through the knots (second derivative 0 at
+ *      both ends; one knot: a constant, two: a line), per temperature;
+ *   3. every mode of this context gets the spline at its omega, the end
+ *      knot's gamma outside the knots, at least the smallest knot gamma;
+ *      masked modes 0; averaged over each degenerate set.
+ *   T          [nT] temperatures [K], host memory, 1 <= nT <= KALDO_MAX_T
+ *   omega_src  [n_src] source angular frequencies [rad/ps] (2 pi nu), host
+ *              or device memory
+ *   gamma_src  [nT][n_src] source linewidths [rad/ps], host or device memory
+ *   n_bins     1 <= n_bins <= 4096
+ *   gamma_out  [nT][Nk][n] the interpolated linewidths [rad/ps], host or
+ *              device memory, or NULL (kept resident either way)
+ * Runs on the GPU (binning, spline solve, evaluation) on the context's stream.
+ * Errors: KALDO_ESTATE before kaldo_phonons; KALDO_EINVAL for bad arguments
+ * or no source mode with nu >= 0.01 THz (found on the GPU: reported after a
+ * synchronisation of the stream). */
+kaldo_status kaldo_gamma_interpolate(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats,
+                                     const double* omega_src, const double* gamma_src, int64_t n_src,
+                                     int32_t n_bins, double* gamma_out);
 
 /* Batches: the linewidths of many crystals (uneven cell sizes and grids) in
  * one HIP graph launch.

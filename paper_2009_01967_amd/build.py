@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libkaldo.so")
 PEAKS = os.path.join(HERE, "libpeaks.so")
 
 SOURCES = ["api.cpp", "harmonic.hip", "anharmonic.hip", "gamma.hip", "crystal.hip", "kappa.hip", "phase.hip",
-           "bte.hip"]
+           "bte.hip", "interp.hip"]
 
 ARCH = "gfx950"
 COMMON = [

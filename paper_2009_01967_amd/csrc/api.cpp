@@ -160,6 +160,28 @@ kaldo_status copy_out(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {
   return KALDO_OK;
 }
 
+// src: host memory or device memory of the context's GPU; complete on the
+// context's stream in order (a host source is copied before the call returns)
+kaldo_status copy_in(kaldo_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return KALDO_OK;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  bool device = false;
+  hipError_t e = hipPointerGetAttributes(&attr, src);
+  if (e == hipSuccess) {
+    device = attr.type == hipMemoryTypeDevice;
+  } else {
+    (void)hipGetLastError();
+  }
+  if (device) {
+    KALDO_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    KALDO_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    KALDO_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return KALDO_OK;
+}
+
 template <typename T>
 static kaldo_status upload(kaldo_ctx ctx, DevBuf& buf, const T* src, size_t count) {
   KALDO_HIP(ctx, buf.ensure(count * sizeof(T)));
@@ -564,6 +586,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
   ctx->delta = delta;
   ctx->sigma_thz = sigma_thz;
   ctx->have_gamma = false;
+  ctx->gamma_external = false;
   if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
   ctx->g_lo = k_lo(ctx);
   ctx->g_hi = k_hi(ctx);
@@ -610,7 +633,8 @@ kaldo_status kaldo_kappa_bte(kaldo_ctx ctx, kaldo_bte_method method, int32_t max
   ctx->err.clear();
   KALDO_HIP(ctx, hipSetDevice(ctx->device));
   if (terms_out) *terms_out = 0;
-  if (!ctx->have_gamma || !ctx->have_fc3) return fail(ctx, KALDO_ESTATE, "kaldo_kappa_bte before kaldo_linewidths");
+  if (!ctx->have_gamma || !ctx->have_fc3 || ctx->gamma_external)
+    return fail(ctx, KALDO_ESTATE, "kaldo_kappa_bte before kaldo_linewidths");
   if (method != KALDO_BTE_INVERSE && method != KALDO_BTE_SELF_CONSISTENT)
     return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: unknown method");
   if (method == KALDO_BTE_SELF_CONSISTENT && (max_terms < 1 || !(tol > 0.0) || !std::isfinite(tol)))
@@ -660,6 +684,100 @@ kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out) {
   kaldo_status st;
   if ((st = run_mode_diffusivity(ctx)) != KALDO_OK) return st;
   return copy_out(ctx, d_out, ctx->d_diff.p, (size_t)ctx->nT * ctx->nm * 3 * sizeof(double));
+}
+
+kaldo_status kaldo_qhgk_options(kaldo_ctx ctx, double bandwidth, double threshold) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  if (!std::isfinite(bandwidth) || bandwidth < 0.0)
+    return fail(ctx, KALDO_EINVAL, "kaldo_qhgk_options: bandwidth must be finite and >= 0");
+  if (std::isnan(threshold) || threshold < 0.0)
+    return fail(ctx, KALDO_EINVAL, "kaldo_qhgk_options: threshold must be >= 0");
+  ctx->qhgk_bandwidth = bandwidth;
+  ctx->qhgk_threshold = std::isinf(threshold) ? 0.0 : threshold;
+  return KALDO_OK;
+}
+
+static kaldo_status check_temperatures(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats) {
+  if (!T || nT < 1 || nT > KALDO_MAX_T) return fail(ctx, KALDO_EINVAL, "need 1 <= nT <= KALDO_MAX_T temperatures");
+  if (stats != KALDO_QUANTUM && stats != KALDO_CLASSICAL) return fail(ctx, KALDO_EINVAL, "bad statistics");
+  for (int t = 0; t < nT; ++t) {
+    if (!std::isfinite(T[t]) || T[t] < 0.0 || (T[t] == 0.0 && stats == KALDO_CLASSICAL))
+      return fail(ctx, KALDO_EINVAL, "temperatures must be finite, >= 0 (> 0 for classical)");
+  }
+  return KALDO_OK;
+}
+
+// the temperatures and statistics of an installed gamma; the gamma itself follows
+static void install_gamma_state(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats) {
+  ctx->nT = nT;
+  for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
+  ctx->stats = stats;
+  ctx->g_lo = 0;
+  ctx->g_hi = ctx->nk;
+}
+
+kaldo_status kaldo_set_gamma(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats, const double* gamma) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_set_gamma before kaldo_phonons");
+  kaldo_status st;
+  if ((st = check_temperatures(ctx, T, nT, stats)) != KALDO_OK) return st;
+  const size_t count = (size_t)nT * ctx->nk * ctx->nm;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  bool device = false;
+  if (gamma) {
+    if (hipPointerGetAttributes(&attr, gamma) == hipSuccess)
+      device = attr.type == hipMemoryTypeDevice;
+    else
+      (void)hipGetLastError();
+    if (!device) {
+      for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(gamma[i]) || gamma[i] < 0.0)
+          return fail(ctx, KALDO_EINVAL, "kaldo_set_gamma: linewidths must be finite and >= 0");
+    }
+  }
+  ctx->have_gamma = false;
+  KALDO_HIP(ctx, ctx->d_gamma.ensure(count * sizeof(double)));
+  if (gamma) {
+    if ((st = copy_in(ctx, ctx->d_gamma.p, gamma, count * sizeof(double))) != KALDO_OK) return st;
+  } else if ((st = fill_zero(ctx, ctx->d_gamma.p, count * sizeof(double))) != KALDO_OK) {
+    return st;
+  }
+  install_gamma_state(ctx, T, nT, stats);
+  ctx->gamma_external = true;
+  ctx->have_gamma = true;
+  return KALDO_OK;
+}
+
+kaldo_status kaldo_gamma_interpolate(kaldo_ctx ctx, const double* T, int32_t nT, kaldo_stats stats,
+                                     const double* omega_src, const double* gamma_src, int64_t n_src,
+                                     int32_t n_bins, double* gamma_out) {
+  if (!ctx) return KALDO_EINVAL;
+  ArenaScope arena_scope(&ctx->arena);
+  ctx->err.clear();
+  KALDO_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->have_phonons) return fail(ctx, KALDO_ESTATE, "kaldo_gamma_interpolate before kaldo_phonons");
+  kaldo_status st;
+  if ((st = check_temperatures(ctx, T, nT, stats)) != KALDO_OK) return st;
+  if (!omega_src || !gamma_src || n_src < 1 || n_src > ((int64_t)1 << 31))
+    return fail(ctx, KALDO_EINVAL, "kaldo_gamma_interpolate: need source arrays of 1 .. 2^31 modes");
+  if (n_bins < 1 || n_bins > 4096) return fail(ctx, KALDO_EINVAL, "kaldo_gamma_interpolate: n_bins in 1 .. 4096");
+  ctx->have_gamma = false;
+  const int keep_nT = ctx->nT;
+  ctx->nT = nT;
+  st = run_gamma_interpolate(ctx, omega_src, gamma_src, n_src, n_bins);
+  if (st != KALDO_OK) {
+    ctx->nT = keep_nT;
+    return st;
+  }
+  install_gamma_state(ctx, T, nT, stats);
+  ctx->gamma_external = true;
+  ctx->have_gamma = true;
+  return copy_out(ctx, gamma_out, ctx->d_gamma.p, (size_t)nT * ctx->nk * ctx->nm * sizeof(double));
 }
 
 kaldo_status kaldo_batch_add(kaldo_ctx ctx, const kaldo_structure* structure, const kaldo_fc2* fc2,

@@ -403,6 +403,14 @@ __global__ void k_cr_set_average(double* __restrict__ gamma, const double* __res
   cr_set_average_elem(gamma, graw, setid, n, nk, idx);
 }
 
+kaldo_status launch_set_average(kaldo_ctx ctx, double* gamma, const double* graw, int nT) {
+  const int n = ctx->nm, nk = ctx->nk;
+  hipLaunchKernelGGL(k_cr_set_average, dim3(blocks_for((long long)n * nk * nT, 256)), dim3(256), 0, ctx->stream,
+                     gamma, graw, ctx->d_setid.as<int>(), n, nk, nT);
+  KALDO_HIP(ctx, hipGetLastError());
+  return KALDO_OK;
+}
+
 kaldo_status run_crystal_tables(kaldo_ctx ctx, double** OM, double** IW, double** OCC, cplx<double>** PH);
 
 // lo plane of an operand at an offset (BF16X3 only; null otherwise)

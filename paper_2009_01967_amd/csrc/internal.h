@@ -217,6 +217,9 @@ struct kaldo_ctx_s {
   int stats = 0;
   int delta = KALDO_DELTA_GAUSS;
   double sigma_thz = 0.0;               // delta width of the last linewidths
+  bool gamma_external = false;          // the resident gamma came from kaldo_set_gamma / kaldo_gamma_interpolate
+  double qhgk_bandwidth = 0.0;          // kaldo_qhgk_options: every linewidth in tau_{mu mu'} (0: off)
+  double qhgk_threshold = 0.0;          // kaldo_qhgk_options: tau = 0 beyond this |w - w'| (0: off)
   kaldo::Arena arena;                   // caller's workspace (kaldo_set_workspace), if any
   int k_begin = 0, k_end = 0x7fffffff;  // first-mode grid points computed (kaldo_set_k_range)
   int g_lo = 0, g_hi = 0;                // the points the resident gamma covers
@@ -230,6 +233,7 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_scratch2;
   kaldo::DevBuf d_bte;               // full BTE: scattering operator pieces, set tables, solve
   kaldo::DevBuf d_klist;             // first-mode points a linewidth run computes (int)
+  kaldo::DevBuf d_interp;            // gamma interpolation: source modes, bins, knots, raw values
   kaldo::CrystalPlan cplan{};        // the last planning pass of the many-branch path
   size_t xy_budget = (size_t)256 << 20;  // bytes of step-B and GEMM-1 outputs per partner batch
   bool xy_shared = false;                // planning a batch: X and Y come from the parent's shared pool
@@ -312,6 +316,11 @@ kaldo_status run_kappa_rta(kaldo_ctx ctx);
 hipError_t noalloc_setup(int device);
 kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
+kaldo_status run_gamma_interpolate(kaldo_ctx ctx, const double* omega_src, const double* gamma_src, int64_t n_src,
+                                   int n_bins);
+// gamma[t][k][s] = mean of graw over the degenerate set of (k, s), on the context's stream
+kaldo_status launch_set_average(kaldo_ctx ctx, double* gamma, const double* graw, int nT);
+kaldo_status copy_in(kaldo_ctx ctx, void* dst, const void* src, size_t bytes);
 kaldo_status run_mode_diffusivity(kaldo_ctx ctx);
 kaldo_status run_kappa_bte(kaldo_ctx ctx, int method, int max_terms, double tol, double* kappa_out, int* terms_out);
 // persistent batch kernel over the crystals of `subs` planned for `precision`:

@@ -167,6 +167,9 @@ kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out) {
 }
 
 // ---- QHGK ---------------------------------------------------------------------------
+// most (first-mode block, u slice) partial sums per temperature of k_qhgk_pairs
+constexpr int kQhgkMaxSlices = 2048;
+
 // M_a (column major): M_a[a][b] = sum_R (x_i - x_j - R.cell)_a fc2 / sqrt(m_i m_j), ps^-2 A
 __global__ void k_displacement_hessian(double* __restrict__ M, const int2* __restrict__ pair,
                                        const int* __restrict__ R, const double* __restrict__ val,
@@ -190,70 +193,124 @@ __global__ void k_displacement_hessian(double* __restrict__ M, const int2* __res
   for (int d = 0; d < 3; ++d) M[(size_t)d * n * n + (size_t)b * n + a] = acc[d] * scale;
 }
 
-// pair sum over (s, u) of c tau v_a v_b; V_d column major: V_d[u * n + s] = (E^T M_d E)[s][u]
+// The second modes u that a block of first modes s0 <= s < s1 pairs with
+// under an energy threshold: frequencies ascend at Gamma, so every u with
+// |w_s - w_u| <= thr lies in [lo, hi), found by bisection with the bounds
+// widened by a relative 1e-9 (the exact test decides each pair).  Without a
+// threshold, every u.
+__device__ __forceinline__ void qhgk_band(const double* __restrict__ omega, int n, int s0, int s1, double thr,
+                                          int* lo, int* hi) {
+  if (!(thr > 0.0)) {
+    *lo = 0;
+    *hi = n;
+    return;
+  }
+  const double slack = 1e-9 * (fabs(omega[0]) + fabs(omega[n - 1]) + thr);
+  const double wlo = omega[s0] - thr - slack, whi = omega[s1 - 1] + thr + slack;
+  int a = 0, b = n;  // first u with omega[u] >= wlo
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (omega[m] < wlo) a = m + 1; else b = m;
+  }
+  *lo = a;
+  b = n;  // first u with omega[u] > whi
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (omega[m] <= whi) a = m + 1; else b = m;
+  }
+  *hi = a;
+}
+
+// Lorentzian lifetime of a pair (Sec. II.C, eq. lorentzian_amorphous) with the
+// options of Appendix A: gs is the pair width (the two linewidths, or twice
+// the bandwidth); 0 beyond the threshold.
+__device__ __forceinline__ double qhgk_tau(double ws, double wu, double gs, double thr) {
+  const double dw = ws - wu;
+  if (thr > 0.0 && fabs(dw) > thr) return 0.0;
+  return gs / (dw * dw + gs * gs);
+}
+
+// QHGK pair sum over (s, u) of c tau v_a v_b.  V_d column major: V_d[u * n + s]
+// = (E^T M_d E)[s][u].  One thread per first mode s (lanes over consecutive s
+// read V_d coalesced) and slice z of the second modes; each block writes its
+// 9 sums to partial[t][z * gridDim.x + blockIdx.x].  With a threshold only the
+// band of u a block can pair with is read.
 __global__ void __launch_bounds__(256) k_qhgk_pairs(double* __restrict__ partial, const double* __restrict__ Vm,
                                                     const double* __restrict__ omega, const double* __restrict__ gamma,
-                                                    int n, double4 T03, double4 T47, int classical) {
-  const int t = blockIdx.y;
+                                                    int n, int ul, double4 T03, double4 T47, int classical,
+                                                    double bandwidth, double thr) {
+  const int t = blockIdx.y, z = blockIdx.z;
   const double Ts[8] = {T03.x, T03.y, T03.z, T03.w, T47.x, T47.y, T47.z, T47.w};
   const double T = Ts[t];
   const double* g = gamma + (size_t)t * n;
   const size_t nn = (size_t)n * n;
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < nn; m += (size_t)gridDim.x * blockDim.x) {
-    const int s = (int)(m % n), u = (int)(m / n);
-    const double ws = omega[s], wu = omega[u];
-    if (ws / kTwoPi < kNuMinThz || wu / kTwoPi < kNuMinThz) continue;
-    double c;
-    if (classical) {
-      c = kBoltzmann;
-    } else if (fabs(ws - wu) < 1e-9 * fmax(fabs(ws), fabs(wu))) {
-      c = heat_capacity(0.5 * (ws + wu), T, 0);
-    } else {
-      c = kHbar * ws * wu / T * (occupation(wu, T, 0) - occupation(ws, T, 0)) / (ws - wu);
+  const int s0 = blockIdx.x * blockDim.x, s1 = min(n, s0 + (int)blockDim.x);
+  const int s = s0 + threadIdx.x;
+  __shared__ int band[2];
+  if (threadIdx.x == 0) qhgk_band(omega, n, s0, s1, thr, &band[0], &band[1]);
+  __syncthreads();
+  const int u0 = max(z * ul, band[0]), u1 = min(min(n, (z + 1) * ul), band[1]);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const double ws = s < n ? omega[s] : 0.0;
+  if (s < n && ws / kTwoPi >= kNuMinThz) {
+    const double gss = bandwidth > 0.0 ? bandwidth : g[s];
+    for (int u = u0; u < u1; ++u) {
+      const double wu = omega[u];
+      if (wu / kTwoPi < kNuMinThz) continue;
+      const double tau = qhgk_tau(ws, wu, gss + (bandwidth > 0.0 ? bandwidth : g[u]), thr);
+      if (tau == 0.0) continue;
+      double c;
+      if (classical) {
+        c = kBoltzmann;
+      } else if (fabs(ws - wu) < 1e-9 * fmax(fabs(ws), fabs(wu))) {
+        c = heat_capacity(0.5 * (ws + wu), T, 0);
+      } else {
+        c = kHbar * ws * wu / T * (occupation(wu, T, 0) - occupation(ws, T, 0)) / (ws - wu);
+      }
+      const double inv = 1.0 / (2.0 * sqrt(ws * wu));
+      const size_t m = (size_t)u * n + s;
+      const double v0 = Vm[m] * inv, v1 = Vm[nn + m] * inv, v2 = Vm[2 * nn + m] * inv;
+      const double w = c * tau;
+      acc[0] += w * v0 * v0;
+      acc[1] += w * v0 * v1;
+      acc[2] += w * v0 * v2;
+      acc[3] += w * v1 * v1;
+      acc[4] += w * v1 * v2;
+      acc[5] += w * v2 * v2;
     }
-    const double gs = g[s] + g[u];
-    const double dw = ws - wu;
-    const double tau = gs / (dw * dw + gs * gs);
-    const double inv = 1.0 / (2.0 * sqrt(ws * wu));
-    const double v0 = Vm[m] * inv, v1 = Vm[nn + m] * inv, v2 = Vm[2 * nn + m] * inv;
-    const double w = c * tau;
-    acc[0] += w * v0 * v0;
-    acc[1] += w * v0 * v1;
-    acc[2] += w * v0 * v2;
-    acc[3] += w * v1 * v0;
-    acc[4] += w * v1 * v1;
-    acc[5] += w * v1 * v2;
-    acc[6] += w * v2 * v0;
-    acc[7] += w * v2 * v1;
-    acc[8] += w * v2 * v2;
   }
-  block_sum9<256>(acc, partial + ((size_t)t * gridDim.x + blockIdx.x) * 9);
+  double full[9] = {acc[0], acc[1], acc[2], acc[1], acc[3], acc[4], acc[2], acc[4], acc[5]};
+  block_sum9<256>(full, partial + ((size_t)t * gridDim.z * gridDim.x + (size_t)z * gridDim.x + blockIdx.x) * 9);
 }
 
 // Mode diffusivity (Sec. II.C, eq. diffusivity_per_mode) per direction a:
 // D[t][s][a] = sum_u v_{s u a}^2 tau_{s u} in mm^2/s (the printed 1/(N_k V) is
 // not applied: it would not leave a diffusivity).  One thread per (s, t, u
 // slice): the lanes read consecutive s of V_d (coalesced) and slice z of the
-// grid sums u in [z * ul, (z + 1) * ul) into partial[z][t][s][a].
+// grid sums u in [z * ul, (z + 1) * ul) (within the block's band under a
+// threshold) into partial[z][t][s][a].
 __global__ void __launch_bounds__(256) k_qhgk_diffusivity(double* __restrict__ partial, const double* __restrict__ Vm,
                                                           const double* __restrict__ omega,
-                                                          const double* __restrict__ gamma, int n, int nT, int ul) {
-  const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+                                                          const double* __restrict__ gamma, int n, int nT, int ul,
+                                                          double bandwidth, double thr) {
   const int t = blockIdx.y, z = blockIdx.z;
+  const int s0 = blockIdx.x * blockDim.x, s1 = min(n, s0 + (int)blockDim.x);
+  const int s = s0 + threadIdx.x;
+  __shared__ int band[2];
+  if (threadIdx.x == 0) qhgk_band(omega, n, s0, s1, thr, &band[0], &band[1]);
+  __syncthreads();
   if (s >= n) return;
   const size_t nn = (size_t)n * n;
   const double* g = gamma + (size_t)t * n;
   const double ws = omega[s];
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   if (ws / kTwoPi >= kNuMinThz) {
-    const int u1 = min(n, (z + 1) * ul);
-    for (int u = z * ul; u < u1; ++u) {
+    const double gss = bandwidth > 0.0 ? bandwidth : g[s];
+    const int u0 = max(z * ul, band[0]), u1 = min(min(n, (z + 1) * ul), band[1]);
+    for (int u = u0; u < u1; ++u) {
       const double wu = omega[u];
       if (wu / kTwoPi < kNuMinThz) continue;
-      const double gs = g[s] + g[u];
-      const double dw = ws - wu;
-      const double tau = gs / (dw * dw + gs * gs);
+      const double tau = qhgk_tau(ws, wu, gss + (bandwidth > 0.0 ? bandwidth : g[u]), thr);
       const double inv = 1.0 / (4.0 * ws * wu);  // 1 / (2 sqrt(w w'))^2
       const size_t m = (size_t)u * n + s;
       const double v0 = Vm[m], v1 = Vm[nn + m], v2 = Vm[2 * nn + m];
@@ -294,7 +351,7 @@ static kaldo_status qhgk_velocity(kaldo_ctx ctx, double** Vout, double** part_ou
   hipStream_t st = ctx->stream;
   // real eigenvectors: column s of d_dyn (Gamma path keeps them real)
   const double* E = ctx->d_dyn.as<double>();
-  KALDO_HIP(ctx, ctx->d_scratch2.ensure(3 * nn * sizeof(double) * 2 + 64 * 9 * KALDO_MAX_T * sizeof(double)));
+  KALDO_HIP(ctx, ctx->d_scratch2.ensure(3 * nn * sizeof(double) * 2 + kQhgkMaxSlices * 9 * KALDO_MAX_T * sizeof(double)));
   double* M = ctx->d_scratch2.as<double>();
   double* X = M + 3 * nn;  // X then V reuses M
   double* part = X + 3 * nn;
@@ -318,22 +375,36 @@ static kaldo_status qhgk_velocity(kaldo_ctx ctx, double** Vout, double** part_ou
   return KALDO_OK;
 }
 
+// u slices per block of 256 first modes, so that the grid holds about 1024
+// blocks (each slice at least 32 u): more slices make the reductions
+// latency-bound
+static int qhgk_slices(int n, int nT, int* ul) {
+  const int bs = (int)blocks_for(n, 256);
+  int nz = std::max(1, std::min(1024 / std::max(1, bs * nT), (n + 31) / 32));
+  *ul = (n + nz - 1) / nz;
+  return (n + *ul - 1) / *ul;
+}
+
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx) {
   const int n = ctx->nm, nT = ctx->nT;
   hipStream_t st = ctx->stream;
   double *M = nullptr, *part = nullptr;
   const kaldo_status vs = qhgk_velocity(ctx, &M, &part);
   if (vs != KALDO_OK) return vs;
-  const int nslice = 64;
+  const int bs = (int)blocks_for(n, 256);
+  int ul = 0;
+  const int nz = qhgk_slices(n, nT, &ul);
+  if (bs * nz > kQhgkMaxSlices) return fail(ctx, KALDO_EINVAL, "kaldo_kappa_qhgk: too many modes");
   double4 T03 = make_double4(ctx->T[0], ctx->T[1], ctx->T[2], ctx->T[3]);
   double4 T47 = make_double4(ctx->T[4], ctx->T[5], ctx->T[6], ctx->T[7]);
   prof_begin(ctx);
-  hipLaunchKernelGGL(k_qhgk_pairs, dim3(nslice, nT), dim3(256), 0, st, part, M, ctx->d_omega.as<double>(),
-                     ctx->d_gamma.as<double>(), n, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0);
+  hipLaunchKernelGGL(k_qhgk_pairs, dim3(bs, nT, nz), dim3(256), 0, st, part, M, ctx->d_omega.as<double>(),
+                     ctx->d_gamma.as<double>(), n, ul, T03, T47, ctx->stats == KALDO_CLASSICAL ? 1 : 0,
+                     ctx->qhgk_bandwidth, ctx->qhgk_threshold);
   KALDO_HIP(ctx, hipGetLastError());
   prof_end(ctx, "kappa_qhgk");
   KALDO_HIP(ctx, ctx->d_kappa.ensure((size_t)nT * 9 * sizeof(double)));
-  hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(), part, nslice, nT,
+  hipLaunchKernelGGL(k_reduce_slices, dim3(1), dim3(256), 0, st, ctx->d_kappa.as<double>(), part, bs * nz, nT,
                      kKappaSI / cell_volume(ctx->cell));
   KALDO_HIP(ctx, hipGetLastError());
   return KALDO_OK;
@@ -345,18 +416,15 @@ kaldo_status run_mode_diffusivity(kaldo_ctx ctx) {
   double *M = nullptr, *part = nullptr;
   const kaldo_status vs = qhgk_velocity(ctx, &M, &part);
   if (vs != KALDO_OK) return vs;
-  // u slices so that the grid holds about 1024 blocks (each at least 32 u):
-  // more slices make the reduction below latency-bound
   const int bs = (int)blocks_for(n, 256);
-  int nz = std::max(1, std::min(1024 / std::max(1, bs * nT), (n + 31) / 32));
-  const int ul = (n + nz - 1) / nz;
-  nz = (n + ul - 1) / ul;
+  int ul = 0;
+  const int nz = qhgk_slices(n, nT, &ul);
   const long long count = (long long)nT * n * 3;
   KALDO_HIP(ctx, ctx->d_diff.ensure((size_t)(nz + 1) * count * sizeof(double)));
   double* D = ctx->d_diff.as<double>();
   prof_begin(ctx);
   hipLaunchKernelGGL(k_qhgk_diffusivity, dim3(bs, nT, nz), dim3(256), 0, st, D + count, M, ctx->d_omega.as<double>(),
-                     ctx->d_gamma.as<double>(), n, nT, ul);
+                     ctx->d_gamma.as<double>(), n, nT, ul, ctx->qhgk_bandwidth, ctx->qhgk_threshold);
   KALDO_HIP(ctx, hipGetLastError());
   hipLaunchKernelGGL(k_diffusivity_reduce, dim3(blocks_for(count, 256)), dim3(256), 0, st, D, D + count,
                      ctx->d_setid.as<int>(), n, nz, count);

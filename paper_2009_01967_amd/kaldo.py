@@ -52,7 +52,8 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_batch_run", "kaldo_batch_clear", "kaldo_set_tuning", "kaldo_profile_enable",
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
             "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity",
-            "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte", "kaldo_batch_plan"]
+            "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte", "kaldo_batch_plan", "kaldo_qhgk_options",
+            "kaldo_set_gamma", "kaldo_gamma_interpolate"]
 
 
 class kaldo_structure(C.Structure):
@@ -120,6 +121,13 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_qhgk.restype = C.c_int
     lib.kaldo_mode_diffusivity.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_mode_diffusivity.restype = C.c_int
+    lib.kaldo_qhgk_options.argtypes = [C.c_void_p, C.c_double, C.c_double]
+    lib.kaldo_qhgk_options.restype = C.c_int
+    lib.kaldo_set_gamma.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int, C.c_void_p]
+    lib.kaldo_set_gamma.restype = C.c_int
+    lib.kaldo_gamma_interpolate.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int, C.c_void_p,
+                                            C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.kaldo_gamma_interpolate.restype = C.c_int
     lib.kaldo_batch_add.argtypes = [C.c_void_p, C.POINTER(kaldo_structure), C.POINTER(kaldo_fc2),
                                     C.POINTER(kaldo_fc3), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.kaldo_batch_add.restype = C.c_int
@@ -282,6 +290,34 @@ def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
 
 def kaldo_mode_diffusivity(ctx, d_out) -> int:
     return load_library().kaldo_mode_diffusivity(ctx, _out_ptr(d_out))
+
+
+def kaldo_qhgk_options(ctx, bandwidth: float = 0.0, threshold: float = 0.0) -> int:
+    return load_library().kaldo_qhgk_options(ctx, float(bandwidth), float(threshold))
+
+
+def _in_ptr(a, keep):
+    """Host array (made contiguous float64 and kept alive) or device tensor -> void*."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(keep.arr(a, np.float64).ctypes.data)
+
+
+def kaldo_set_gamma(ctx, T: Sequence[float], stats: int, gamma) -> int:
+    keep = _Keep()
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    return load_library().kaldo_set_gamma(ctx, Ts, len(T), int(stats), _in_ptr(gamma, keep))
+
+
+def kaldo_gamma_interpolate(ctx, T: Sequence[float], stats: int, omega_src, gamma_src, n_src: int,
+                            n_bins: int, gamma_out=None) -> int:
+    keep = _Keep()
+    Ts = (C.c_double * max(1, len(T)))(*[float(x) for x in T])
+    return load_library().kaldo_gamma_interpolate(ctx, Ts, len(T), int(stats), _in_ptr(omega_src, keep),
+                                                  _in_ptr(gamma_src, keep), int(n_src), int(n_bins),
+                                                  _out_ptr(gamma_out))
 
 
 def kaldo_batch_add(ctx, structure, fc2, fc3, grid):
@@ -481,6 +517,29 @@ class Context:
             out = np.zeros((self.nT, 3, 3))
         _check(self.h, kaldo_kappa_qhgk(self.h, out))
         return out
+
+    def qhgk_options(self, bandwidth=0.0, threshold=0.0):
+        """QHGK bandwidth eta and energy threshold [rad/ps] for later kappa_qhgk
+        and mode_diffusivity calls (0 turns each off)."""
+        _check(self.h, kaldo_qhgk_options(self.h, bandwidth, threshold))
+
+    def set_gamma(self, T=(300.0,), gamma=None, classical=False):
+        """Install linewidths [nT][Nk][n] (host array or device tensor; None: zeros)."""
+        _check(self.h, kaldo_set_gamma(self.h, T, KALDO_CLASSICAL if classical else KALDO_QUANTUM, gamma))
+        self.nT = len(T)
+
+    def gamma_interpolate(self, omega_src, gamma_src, n_bins=64, T=(300.0,), classical=False, gamma_out=None,
+                          want_host=True):
+        """Linewidths of this context's modes from gamma(omega) of source modes:
+        omega_src [n_src] rad/ps, gamma_src [nT][n_src] rad/ps (host arrays or
+        device tensors).  Returns the interpolated [nT][Nk][n] linewidths."""
+        n_src = int(omega_src.shape[0]) if hasattr(omega_src, "shape") else len(omega_src)
+        if want_host and gamma_out is None:
+            gamma_out = np.zeros((len(T), self.nk, self.n))
+        _check(self.h, kaldo_gamma_interpolate(self.h, T, KALDO_CLASSICAL if classical else KALDO_QUANTUM,
+                                               omega_src, gamma_src, n_src, n_bins, gamma_out))
+        self.nT = len(T)
+        return gamma_out
 
     def mode_diffusivity(self, out=None):
         """[nT][n][3] mode diffusivity at Gamma in mm^2/s (host array unless a

@@ -93,7 +93,7 @@ def cage_reference():
     _say(f"oracle: {name}: generating")
     c = cage_cell(grid=w["grid"], rc3=w["rc3"])
     ph = P.phonons(c, velocities=False)
-    ks = [0, 7]
+    ks = [0, 7, 62]
     cols = []
     for k in ks:
         _say(f"  oracle k = {k}")
@@ -101,13 +101,16 @@ def cage_reference():
     return c, w, ph, ks, np.concatenate(cols, axis=1)
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp64"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32", "fp64"])
 def test_full_size_cage_46_atoms_sampled_k(cage_reference, precision):
     """46-atom cage cell (138 branches) on 5x5x5 at full size; the oracle
-    evaluates sampled first-mode k points."""
+    evaluates sampled first-mode k points (0; 7 = (0,1,2); 62 = (2,2,2)).  The
+    GPU computes one point of each pair (k, -k) and stores it at both: the
+    mirrors 23 = (0,4,3) and 93 = (3,3,3) must hold the same values."""
     c, w, ph, ks, g = cage_reference
     _say(f"case: cage-46at-5x5x5 {precision}")
     with _ctx() as ctx:
         ctx.phonons(c)
         gg = ctx.linewidths(c, T=w["T"], sigma_thz=w["sigma_thz"], precision=precision)
     _ok(gamma_error(gg[:, ks], g, ph.mask[ks]), TOL[precision])
+    assert np.array_equal(gg[:, 23], gg[:, 7]) and np.array_equal(gg[:, 93], gg[:, 62])

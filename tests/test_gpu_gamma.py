@@ -91,7 +91,7 @@ def test_qhgk_several_temperatures_and_classical(sige64):
         _ok(kappa_error(kq, k), TOL["fp64"])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_full_size_sige_1000_atoms_sampled_modes(precision):
     """1000-atom disordered SiGe (3000 modes) at full size; the oracle
     evaluates sampled first modes one by one."""
