@@ -101,3 +101,44 @@ def test_batch_errors():
         kaldo._check(ctx.h, kaldo.kaldo_batch_clear(ctx.h))
         st = kaldo.kaldo_batch_run(ctx.h, T, SIGMA, kaldo.KALDO_QUANTUM, kaldo.KALDO_FP32, None)
         assert st == kaldo.KALDO_ESTATE
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                    "golden", "batch_points.json")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_largest_crystals_of_the_full_draw_against_oracle(precision):
+    """The three costliest crystals of the 32-crystal workload at their real
+    size (54 atoms on 9^3, 49 on 9^3, 36 on 10^3) inside one persistent batch
+    launch, against oracle linewidths at sampled first-mode points stored by
+    tests/golden/make_batch_points.py.  Each crystal is added twice, each copy
+    restricted to one sampled point (kaldo_batch_set_k_range), so the launch
+    computes exactly those points."""
+    import json
+    from paper_2009_01967_amd import kaldo
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    crystals = batch_crystals()
+    _say(f"case: largest crystals of the full draw, {precision}")
+    with kaldo.Context(0) as ctx:
+        entries = []
+        for ent in gold["crystals"]:
+            c = crystals[ent["index"]]
+            assert c.name == ent["name"]
+            for j, k in enumerate(ent["points"]):
+                h = ctx.batch_add(c)
+                ctx.batch_set_k_range(h, k, k + 1)
+                entries.append((ent, j, k, h))
+        outs = ctx.batch_run(T=gold["T"], sigma_thz=gold["sigma_thz"], precision=precision)
+    for ent, j, k, h in entries:
+        g = outs[h][0, k]
+        g_ref = np.asarray(ent["gamma"][j])
+        mask = np.asarray(ent["mask"][j])
+        err = gamma_error(g, g_ref, mask)
+        _say(f"  {ent['name']} k = {k}: error {err:.3e} (tolerance {TOL[precision]:.0e})")
+        assert err < TOL[precision], (ent["name"], k, err)
+        assert np.all(g[~mask] == 0.0)
+        # points outside the range (its mirror -k included) stay 0
+        others = np.delete(np.arange(outs[h].shape[1]), [k])
+        assert np.count_nonzero(outs[h][:, others]) == 0
