@@ -430,6 +430,11 @@ def run_batch_headline(steps, warmup, div=64, share=1):
         tot, cnt = kaldo.kaldo_profile_read(ctx.h, name)
         phases[name] = tot / max(cnt, 1)
     log(f"batch fp32 phases (ms per launch, workgroup 0): {phases}")
+    per_crystal = {}
+    for i in range(len(crystals)):
+        tot, cnt = kaldo.kaldo_profile_read(ctx.h, f"batch_crystal_{i}")
+        if cnt:
+            per_crystal[i] = tot / cnt
     ex, dense = kaldo.kaldo_profile_flops(ctx.h)
     kaldo.kaldo_profile_enable(ctx.h, False)
     ctx.close()
@@ -471,7 +476,15 @@ def run_batch_headline(steps, warmup, div=64, share=1):
     lw64 = sum(m * c.n_modes for c, m in zip(crystals, sub)) * len(T)
     ran = ex / dense if dense else 1.0
     kernel_ms = graph_ms / max(launches, 1)
-    return dict(phases=phases, crystals=crystals, share=share, share_pts=share_pts, T=T, sigma=sigma, ms=ms, wall=wall, kernel_ms=kernel_ms, ran=ran, ex=ex / steps,
+    # per crystal: workgroup 0's clock over its rounds, against its algorithmic flops
+    crystal_rows = []
+    for i, c in enumerate(crystals):
+        if i in per_crystal:
+            f = batch_flops(c, pts[i])[2]
+            crystal_rows.append({"crystal": c.name, "ms": per_crystal[i], "tflops": f / (per_crystal[i] * 1e-3) / 1e12,
+                                 "frac": f / (per_crystal[i] * 1e-3) / FP32_MFMA_PEAK})
+    crystal_rows.sort(key=lambda r: -r["ms"])
+    return dict(per_crystal=crystal_rows, phases=phases, crystals=crystals, share=share, share_pts=share_pts, T=T, sigma=sigma, ms=ms, wall=wall, kernel_ms=kernel_ms, ran=ran, ex=ex / steps,
                 dense=dense / steps, fa=fa, fb=fb, fc=fc, lw=lw, pts=sum(pts), phonon_s=phonon_s, setup_s=setup_s,
                 g32=g32, fp64={"ms_per_launch": ms64, "value": lw64 / (ms64 * 1e-3), "unit": "linewidths/s",
                                "first_mode_points": f"ceil(N_k/{div}) per crystal, {sum(sub)} of "
@@ -801,6 +814,7 @@ def main():
             "mfma_tflops_issued": b["ex"] / (kms * 1e-3) / 1e12,
             "kernel_ms": kms,
             "phases_ms": b["phases"],
+            "per_crystal": b["per_crystal"],
         },
         "fp64": b["fp64"],
         "speedup_fp32_vs_fp64_per_flop": (b["fc"] / b["ms"]) / (b["fp64"]["gemm_tflops_algorithmic"] * 1e9),

@@ -229,9 +229,9 @@ struct EpiCrystal {
   // frequencies ascend with the mode index at every grid point, rows hold the
   // (Re, Im) pairs of modes s' in [mt BM / 2, (mt + 1) BM / 2), columns (s, s'').
   template <int P, int FM, int FN>
-  __device__ bool tile_empty(int mt, int nt, int z) const {
+  __device__ bool tile_empty(int, int nt, int z, int r0) const {
     constexpr int BM = 32 * FM, BN = 32 * FN;
-    const int m0 = mt * BM / 2;
+    const int m0 = r0 / 2;
     if (m0 >= n) return true;
     const int p = p0 + z, kk = kmap[z];
     const double a = OM[(size_t)m0 * nk + p] * rs, b = OM[(size_t)(min(n, m0 + BM / 2) - 1) * nk + p] * rs;
@@ -680,6 +680,7 @@ struct GridSync {
   unsigned long long phase[6];  // block 0's constant-rate clock ticks: step A with the collection
                                 // and Y padding, step B, GEMM 1, GEMM 2, waits at grid barriers,
                                 // set average
+  unsigned long long t_begin;   // block 0's clock before the first round
 };
 
 // block 0 adds the ticks since *t0 to phase p and restarts the clock
@@ -728,47 +729,93 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned nblocks) {
   return s_abort != 0;
 }
 
-// The tiles of one GEMM phase over the persistent grid: XCD x (= block % 8)
-// takes a contiguous run of the logical tiles, as a launch of k_gemm would.
-template <int P, int FM, int FN, class Epi>
-__device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int b, int G) {
-  g.m_tiles = (g.m_valid + 32 * FM - 1) / (32 * FM);
+// The tiles of one GEMM phase over the persistent grid.  The logical tiles go
+// to the 8 XCDs (x = block % 8) in chunks of 8 consecutive tiles dealt round
+// robin, and the 64 workgroups of an XCD take its tiles in order, each the
+// next one 64 places on.  A chunk holds the row tiles of two or three column
+// panels, so the workgroups of an XCD still share operand panels in its L2,
+// while every XCD gets its share of every partner.  Row tile mt has 32
+// rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of several heights cover the
+// 2n realified rows with little padding).
+template <int P, int FN, class Epi>
+__device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int b, int G,
+                                                const CrystalPlan& C) {
+  constexpr int CH = 8;
+  constexpr unsigned long long mult = P == KALDO_BF16X3 ? 3 : 1;
+  g.m_tiles = C.m_tiles2;
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
   g.group_m = g.m_tiles < 8 ? g.m_tiles : 8;
   g.group_n = g.n_tiles;
   const int total = g.m_tiles * g.n_tiles * g.nz;
-  const int x = b & 7, per = G >> 3, l = b >> 3;
-  const int q = total >> 3, r8 = total & 7;
-  const int start = x * q + (x < r8 ? x : r8), len = q + (x < r8 ? 1 : 0);
-  for (int i = l; i < len; i += per) {
+  const int nchunks = (total + CH - 1) / CH;
+  const int x = b & 7, per = G >> 3;
+  for (int j = b >> 3;; j += per) {
+    const int c = x + 8 * (j / CH);
+    if (c >= nchunks) break;
+    const int t = c * CH + j % CH;
+    if (t >= total) continue;
     int mt, nt, z;
-    gemm_tile_coords(g, start + i, mt, nt, z);
-    gemm_tile<P, FM, FN, Epi>(g, e, mt, nt, z, lds);
+    gemm_tile_coords(g, t, mt, nt, z);
+    const int fm = C.rt_fm[mt], r0 = 32 * C.rt_u0[mt];
+    g.tile_flops = 2ull * (32 * fm) * (32 * FN) * (unsigned long long)g.K * mult;
+    if constexpr (P == KALDO_FP64) {
+      gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+    } else {
+      if (fm == 4) gemm_tile<P, 4, FN, Epi>(g, e, mt, nt, z, lds, r0);
+      else if (fm == 3) gemm_tile<P, 3, FN, Epi>(g, e, mt, nt, z, lds, r0);
+      else gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+    }
     __syncthreads();
   }
 }
 
-// Row tiles of the persistent kernel's GEMMs: 32 FM rows, FM chosen per
-// crystal (2, 3 or 4 for FP32 and BF16X3, 2 for FP64) to pad the 2n realified
-// rows least; 32 FN = 128 columns.
+// Columns of the persistent kernel's GEMM tiles: 32 FN = 128.
 template <int P>
 struct BatchShape {
   static constexpr int FN = 4;
-  static constexpr bool kFmChoice = P != KALDO_FP64;
 };
 
-inline int batch_fm(int precision, int mrows) {
-  if (precision == KALDO_FP64) return 2;
-  int best = 4;
-  long long best_rows = 1LL << 40;
-  for (int fm = 4; fm >= 2; --fm) {
-    const long long rows = (long long)((mrows + 32 * fm - 1) / (32 * fm)) * 32 * fm;
-    if (rows < best_rows) {
-      best_rows = rows;
-      best = fm;
-    }
+// Row tiles covering the realified rows of a crystal: u units of 32 rows in
+// tiles of 4 units (128 rows), the remainder in tiles of 3 or 2 units (FP32
+// and BF16X3).  A tile of 3 units did about 0.75-0.8 of the work per second of
+// a tile of 4 on the 32-crystal batch, so the remainder tiles pay only where
+// the contraction is long (2n >= 256 rows) or tiles of 4 alone would pad the
+// rows by more than a quarter; otherwise, and for FP64 (tiles of 2 units: its
+// accumulators are twice as wide), the tiles are all alike.
+// KALDO_TUNE_FIXED keeps the eager calls' tile (4 units, FP64 2) for bitwise
+// agreement with them.
+static std::vector<int> batch_row_tiles(int precision, int mrows, bool fixed) {
+  const int u = (mrows + 31) / 32;
+  std::vector<int> f;
+  const bool mixed = mrows >= 256 || 4 * (128 * ((u + 3) / 4)) > 5 * mrows;
+  if (precision == KALDO_FP64 || fixed || !mixed) {
+    const int fm = precision == KALDO_FP64 ? 2 : 4;
+    f.assign((u + fm - 1) / fm, fm);
+    return f;
   }
-  return best;
+  const int q4 = u / 4, rem = u % 4;
+  if (rem == 0) {
+    f.assign(q4, 4);
+  } else if (rem == 3) {
+    f.assign(q4, 4);
+    f.push_back(3);
+  } else if (rem == 2) {
+    if (q4 >= 1) {
+      f.assign(q4 - 1, 4);
+      f.push_back(3);
+      f.push_back(3);
+    } else {
+      f.push_back(2);
+    }
+  } else if (q4 >= 2) {
+    f.assign(q4 - 2, 4);
+    f.insert(f.end(), {3, 3, 3});
+  } else if (q4 == 1) {
+    f = {3, 2};
+  } else {
+    f = {2};
+  }
+  return f;
 }
 
 // The stages of one round, each over every workgroup of the grid (grid-stride
@@ -838,21 +885,17 @@ struct BatchStages {
     g.tally = &gs->flops;
     return g;
   }
-  template <int FM>
-  __device__ void gemm1_fm(const BatchRound& R) const {
+  __device__ void gemm1(const BatchRound& R) const {
     const CrystalPlan& C = plans[R.c];
     const long long nn = (long long)C.n * C.n;
     GemmOps g = gemm1_ops(R);
-    g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)C.ldk * (P == KALDO_BF16X3 ? 3 : 1);
     const E1 e{static_cast<T*>(C.Yh), static_cast<T*>(C.Yl), nn * C.ldk, nn, C.n, C.ldk};
-    gemm_persistent<P, FM, FN>(g, e, lds, b, G);
+    gemm_persistent<P, FN>(g, e, lds, b, G, C);
   }
-  template <int FM>
-  __device__ void gemm2_fm(const BatchRound& R) const {
+  __device__ void gemm2(const BatchRound& R) const {
     const CrystalPlan& C = plans[R.c];
     const long long nn = (long long)C.n * C.n;
     GemmOps g = gemm1_ops(R);
-    g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)C.ldk * (P == KALDO_BF16X3 ? 3 : 1);
     g.a_hi = static_cast<const T*>(C.Aph) + (size_t)R.p0 * C.mrows * C.ldk;
     g.a_lo = S_lo<P>(C.Apl, (size_t)R.p0 * C.mrows * C.ldk);
     g.b_hi = C.Yh;
@@ -860,27 +903,7 @@ struct BatchStages {
     g.a_map = nullptr;
     const E2 e{C.OM, C.IW, C.OCC, C.kmap + (size_t)R.k * C.nk + R.p0, C.partial, nn, C.n, C.nk, C.nT, R.k, R.p0,
                C.m_tiles2, C.rs};
-    gemm_persistent<P, FM, FN>(g, e, lds, b, G);
-  }
-  __device__ void gemm1(const BatchRound& R) const {
-    const int fm = plans[R.c].fm;
-    if constexpr (BatchShape<P>::kFmChoice) {
-      if (fm == 3) gemm1_fm<3>(R);
-      else if (fm == 4) gemm1_fm<4>(R);
-      else gemm1_fm<2>(R);
-    } else {
-      gemm1_fm<2>(R);
-    }
-  }
-  __device__ void gemm2(const BatchRound& R) const {
-    const int fm = plans[R.c].fm;
-    if constexpr (BatchShape<P>::kFmChoice) {
-      if (fm == 3) gemm2_fm<3>(R);
-      else if (fm == 4) gemm2_fm<4>(R);
-      else gemm2_fm<2>(R);
-    } else {
-      gemm2_fm<2>(R);
-    }
+    gemm_persistent<P, FN>(g, e, lds, b, G, C);
   }
   // the partial sums of the round into gacc (first round of k: overwrite),
   // after the last round of k the raw linewidths of k and -k
@@ -916,7 +939,7 @@ struct BatchStages {
 template <int P, int NT>
 __global__ void __launch_bounds__(256)
     k_batch_persistent(const CrystalPlan* __restrict__ plans, int nplans, const BatchRound* __restrict__ rounds,
-                       int nrounds, GridSync* __restrict__ gs) {
+                       int nrounds, GridSync* __restrict__ gs, unsigned long long* __restrict__ rtimes) {
   using S = BatchStages<P, NT>;
   constexpr int FN = BatchShape<P>::FN;
   constexpr int L1 = GemmLds<P, 4, FN, typename S::E1>::bytes, L2 = GemmLds<P, 4, FN, typename S::E2>::bytes;
@@ -934,6 +957,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   unsigned long long t0 = wall_clock64();
+  if (b == 0 && threadIdx.x == 0) gs->t_begin = t0;
   if (nrounds > 0) {
     st.step_a(rounds[0]);
     if (grid_barrier(gs, G)) return;
@@ -960,6 +984,8 @@ __global__ void __launch_bounds__(256)
     phase_mark(gs, b, t0, 1);
     if (grid_barrier(gs, G)) return;
     phase_mark(gs, b, t0, 4);
+    // block 0's clock at the end of each round (per-crystal times for the profile)
+    if (b == 0 && threadIdx.x == 0) rtimes[r] = t0;
   }
   if (nrounds > 0) {
     st.collect(rounds[nrounds - 1]);
@@ -981,10 +1007,10 @@ static double batch_dense_flops(const std::vector<CrystalPlan>& plans, const std
   double total = 0.0;
   for (const BatchRound& r : rounds) {
     const CrystalPlan& C = plans[r.c];
-    const int FM = C.fm;
-    const double tiles = (double)((C.mrows + 32 * FM - 1) / (32 * FM)) *
-                         (double)(((long long)C.n * C.n + 32 * FN - 1) / (32 * FN)) * r.cnt;
-    total += 2.0 * tiles * 2.0 * (32 * FM) * (32 * FN) * C.ldk * (P == KALDO_BF16X3 ? 3.0 : 1.0);
+    double rows = 0.0;
+    for (int i = 0; i < C.m_tiles2; ++i) rows += 32.0 * C.rt_fm[i];
+    const double ntiles = (double)(((long long)C.n * C.n + 32 * FN - 1) / (32 * FN)) * r.cnt;
+    total += 2.0 * 2.0 * rows * (32 * FN) * ntiles * C.ldk * (P == KALDO_BF16X3 ? 3.0 : 1.0);
   }
   return total;
 }
@@ -1017,18 +1043,21 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<CrystalPlan> sorted;
   std::vector<BatchRound> rounds;
+  std::vector<int> round_handle;
   size_t pool = 0;  // elements of X (and of Y) of the largest crystal's partner batch
   for (int idx : order) {
     const CrystalPlan& cp = plans[idx];
     const int c = (int)sorted.size();
     sorted.push_back(cp);
     pool = std::max(pool, (size_t)cp.xy_elems);
+    const int handle = (int)(std::find(parent->batch.begin(), parent->batch.end(), subs[idx]) - parent->batch.begin());
     bool fc = true;
     for (int k : points[idx]) {
       const int km = k_mirror(k, cp.G0, cp.G1, cp.G2);
       for (int p0 = 0; p0 < cp.nk; p0 += cp.zb) {
         const int cnt = std::min(cp.zb, cp.nk - p0);
         rounds.push_back(BatchRound{c, k, km, p0, cnt, p0 == 0 ? 1 : 0, p0 + cnt >= cp.nk ? 1 : 0, fc ? 1 : 0});
+        round_handle.push_back(handle);
         fc = false;
       }
     }
@@ -1043,8 +1072,17 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   // that batch and eager results agree bit for bit
   const bool fixed = parent->tuning == KALDO_TUNE_FIXED;
   for (CrystalPlan& cp : sorted) {
-    cp.fm = fixed ? (precision == KALDO_FP64 ? 2 : 4) : batch_fm(precision, cp.mrows);
-    cp.m_tiles2 = (cp.mrows + 32 * cp.fm - 1) / (32 * cp.fm);
+    const std::vector<int> fms = batch_row_tiles(precision, cp.mrows, fixed);
+    // the partial sums were sized for tiles of 64 rows
+    if ((int)fms.size() > 32 || (int)fms.size() > (cp.mrows + 63) / 64)
+      return fail(parent, KALDO_EINVAL, "persistent batch kernel: too many row tiles for a crystal");
+    cp.m_tiles2 = (int)fms.size();
+    int u0 = 0;
+    for (size_t i = 0; i < fms.size(); ++i) {
+      cp.rt_fm[i] = (unsigned char)fms[i];
+      cp.rt_u0[i] = (unsigned char)u0;
+      u0 += fms[i];
+    }
     cp.Xh = xy;
     cp.Xl = split == 2 ? xy + plane : nullptr;
     cp.Yh = xy + split * plane;
@@ -1052,7 +1090,8 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   }
   const size_t pb = (sorted.size() * sizeof(CrystalPlan) + 255) & ~(size_t)255;
   const size_t rb = (rounds.size() * sizeof(BatchRound) + 255) & ~(size_t)255;
-  KALDO_HIP(parent, parent->d_batch.ensure(pb + rb + 256));
+  const size_t tb = (rounds.size() * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  KALDO_HIP(parent, parent->d_batch.ensure(pb + rb + 256 + tb));
   char* base = parent->d_batch.as<char>();
   KALDO_HIP(parent, hipMemcpy(base, sorted.data(), sorted.size() * sizeof(CrystalPlan), hipMemcpyHostToDevice));
   KALDO_HIP(parent, hipMemcpy(base + pb, rounds.data(), rounds.size() * sizeof(BatchRound), hipMemcpyHostToDevice));
@@ -1071,6 +1110,8 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   parent->batch_nt = nt;
   parent->batch_rounds_off = pb;
   parent->batch_sync_off = pb + rb;
+  parent->batch_times_off = pb + rb + 256;
+  parent->batch_round_handle = round_handle;
   parent->batch_dense = precision == KALDO_FP64    ? batch_dense_flops<KALDO_FP64>(sorted, rounds)
                         : precision == KALDO_FP32 ? batch_dense_flops<KALDO_FP32>(sorted, rounds)
                                                   : batch_dense_flops<KALDO_BF16X3>(sorted, rounds);
@@ -1088,7 +1129,9 @@ kaldo_status batch_persistent_launch(kaldo_ctx parent) {
   const dim3 grid(parent->batch_grid), block(256);
   const int np = parent->batch_nplans, nr = parent->batch_nrounds;
   hipStream_t s = parent->stream;
-#define KALDO_BP(PV, NTV) hipLaunchKernelGGL((k_batch_persistent<PV, NTV>), grid, block, 0, s, plans, np, rounds, nr, gs)
+  unsigned long long* rtimes = reinterpret_cast<unsigned long long*>(base + parent->batch_times_off);
+#define KALDO_BP(PV, NTV) \
+  hipLaunchKernelGGL((k_batch_persistent<PV, NTV>), grid, block, 0, s, plans, np, rounds, nr, gs, rtimes)
   const int nt = parent->batch_nt;
   if (parent->batch_precision == KALDO_FP64) {
     if (nt == 1) KALDO_BP(KALDO_FP64, 1); else if (nt == 4) KALDO_BP(KALDO_FP64, 4); else KALDO_BP(KALDO_FP64, 8);
@@ -1122,6 +1165,23 @@ kaldo_status batch_persistent_check(kaldo_ctx parent) {
       for (int p = 0; p < 6; ++p) {
         auto& e = parent->prof_tab[names[p]];
         e.total_ms += (double)h.phase[p] / (double)khz;
+        e.launches += 1;
+      }
+      // per crystal: the clock between the ends of consecutive rounds, summed
+      // over the crystal's rounds ("batch_crystal_<handle>")
+      const size_t nr = parent->batch_round_handle.size();
+      std::vector<unsigned long long> t(nr);
+      KALDO_HIP(parent, hipMemcpy(t.data(), parent->d_batch.as<char>() + parent->batch_times_off,
+                                  nr * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+      std::map<int, double> per;
+      unsigned long long prev = h.t_begin;
+      for (size_t r = 0; r < nr; ++r) {
+        per[parent->batch_round_handle[r]] += (double)(t[r] - prev) / (double)khz;
+        prev = t[r];
+      }
+      for (const auto& kv : per) {
+        auto& e = parent->prof_tab["batch_crystal_" + std::to_string(kv.first)];
+        e.total_ms += kv.second;
         e.launches += 1;
       }
     }

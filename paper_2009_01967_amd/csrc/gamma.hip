@@ -332,9 +332,8 @@ struct EpiGamma {
   // ascend with the mode index, so the mismatches w -+ w' - w'' over the tile
   // span intervals given by its corner modes (widened by a rounding margin).
   template <int P, int FM, int FN>
-  __device__ bool tile_empty(int mt, int nt, int) const {
+  __device__ bool tile_empty(int, int nt, int, int r0) const {
     constexpr int BM = 32 * FM, BN = 32 * FN;
-    const int r0 = mt * BM;
     if (r0 >= n) return true;  // padding rows only
     const double a = OM[r0] * rs, b = OM[min(n, r0 + BM) - 1] * rs;  // w' range
     const double W = sqrt(delta_cut<P>(DK)) * (1.0 + 1e-9) + 1e-9;

@@ -79,8 +79,9 @@ struct BlockBytes : std::integral_constant<int, 0> {};
 template <class Epi>
 struct BlockBytes<Epi, std::void_t<decltype(Epi::kBlockBytes)>> : std::integral_constant<int, Epi::kBlockBytes> {};
 
-// An epilogue with kSkipEmpty = true provides tile_empty<P, FM, FN>(mt, nt, z),
-// true when it would discard every output of block tile (mt, nt, z), and
+// An epilogue with kSkipEmpty = true provides tile_empty<P, FM, FN>(mt, nt, z, r0),
+// true when it would discard every output of block tile (mt, nt, z) whose first
+// row is r0, and
 // clear_tile<P, FM, FN>(mt, nt, z), which writes what it would have written for
 // such a tile; the core then skips the tile's loads and MFMAs.
 template <class Epi, class = void>
@@ -174,7 +175,8 @@ __device__ __forceinline__ void gemm_tile_coords(const GemmOps& g, int tile, int
 // chunk's MFMAs.  Twice the MFMA work per barrier in the same LDS space as the
 // double-buffered 64-byte chunks; faster on long contractions.
 template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
-__device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int mt, int nt, int z, char* lds) {
+__device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int mt, int nt, int z, char* lds,
+                                          int rbase = -1) {
   using T = typename Operand<P>::T;
   using Acc = typename Operand<P>::Acc;
   constexpr int S = Operand<P>::split;
@@ -192,9 +194,12 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   constexpr int ROWS = BM + (BD ? 0 : BN);
   constexpr int BUF = S * ROWS * RB;          // one buffer: all planes, A rows then B rows
   constexpr int EPT = 16 / (int)sizeof(T);    // elements per 16-byte slot
+  // first row of the tile: row tile mt of equal tiles, unless the caller
+  // places tiles of several heights (rbase)
+  const int rb = rbase >= 0 ? rbase : mt * BM;
   if constexpr (SkipEmpty<Epi>::value) {
     // uniform across the block (block indices and operand-independent data only)
-    if (epi.template tile_empty<P, FM, FN>(mt, nt, z)) {
+    if (epi.template tile_empty<P, FM, FN>(mt, nt, z, rb)) {
       epi.template clear_tile<P, FM, FN>(mt, nt, z);
       return;
     }
@@ -221,7 +226,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   long long aoff[NA], boff[NB > 0 ? NB : 1];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
-    int row = mt * BM + row0 + RPP * u;
+    int row = rb + row0 + RPP * u;
     row = row < g.m_valid ? row : g.m_valid - 1;
     aoff[u] = (long long)(g.a_map ? g.a_map[z] : z) * g.a_z + (long long)row * g.lda + slot * EPT;
   }
@@ -422,7 +427,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   at.mt = mt;
   at.nt = nt;
   at.z = z;
-  at.m0 = mt * BM + wm * 16 * FM;
+  at.m0 = rb + wm * 16 * FM;
   at.c0 = (long long)nt * BN + wn * 16 * FN;
   at.lane = lane;
   at.wm = wm;

@@ -125,8 +125,9 @@ namespace kaldo {
 struct CrystalPlan {
   int valid, precision;
   int n, N, nk, ng, nT, ldk, mrows, zb, G0, G1, G2, klo, khi;
-  int m_tiles2;     // row tiles of GEMM 2 in the persistent kernel's tile shape
-  int fm;           // that shape's rows / 32
+  int m_tiles2;     // row tiles of both GEMMs in the persistent kernel
+  unsigned char rt_fm[32];  // row tile i: 32 rt_fm[i] rows from row 32 rt_u0[i]
+  unsigned char rt_u0[32];
   long long xy_elems;  // elements of X (and of Y) for one partner batch
   double C, rs;     // linewidth prefactor / N_k with the delta's normalisation; 1 / delta scale
   void *Z, *Xh, *Xl, *Yh, *Yl;
@@ -241,7 +242,8 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_batch;
   kaldo::DevBuf d_batch_xy;          // the persistent kernel's shared X and Y pool
   int batch_grid = 0, batch_nplans = 0, batch_nrounds = 0, batch_precision = -1, batch_nt = 1;
-  size_t batch_rounds_off = 0, batch_sync_off = 0;
+  size_t batch_rounds_off = 0, batch_sync_off = 0, batch_times_off = 0;
+  std::vector<int> batch_round_handle;  // batch handle of each round's crystal (per-crystal timing)
   double batch_dense = 0.0;          // MFMA flops of every tile of one launch of the persistent kernel
   double prof_batch_executed = 0.0;  // tallied flops of persistent launches since profiling was enabled
   std::vector<int> klist_host;       // its host copy (kept alive for the stream-ordered upload)
