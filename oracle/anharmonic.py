@@ -39,6 +39,19 @@ Readings of points the paper leaves open:
   omega'') replaced by 1, so the same counting (1/N_k, the 1/2 on creation).
 * gamma is averaged over each degenerate set at k (only set averages are
   basis independent).
+* Adaptive width (Appendix A: in crystals the width can be estimated from the
+  phonon velocities; the paper cites that estimate and gives no formula).  For
+  a process whose partners are q' and q'' (q'' fixed by momentum), the energy
+  mismatch f(q') varies across one cell of the q grid with gradient
+  v' - v'' (absorption) or v'' - v' (decay, q'' = q - q'); to first order a
+  uniform q' over the cell, whose sides are b_a / G_a, spreads f with
+  standard deviation sigma_grid = sqrt(sum_a ((v' - v'') . b_a / G_a)^2 / 12)
+  (a uniform variable on an interval of width w has variance w^2 / 12).  The
+  Gaussian of that process has standard deviation
+  max(a sigma_grid, sigma_min), with a the user's scale and sigma_min the
+  fixed width as a floor (v' = v'' would give a zero width).  Within a
+  degenerate set a single mode's velocity depends on the eigenvector basis;
+  the velocity used is the set mean (its trace), which does not.
 """
 
 from __future__ import annotations
@@ -76,6 +89,27 @@ def triangular_delta(x, sigma_omega):
 
 
 DELTAS = {'gauss': gaussian_delta, 'lorentz': lorentzian_delta, 'triangle': triangular_delta}
+
+
+def adaptive_velocity_projections(crystal, ph):
+    """U[k, s, a] = vbar_ks . b_a / G_a [rad/ps]: the degenerate-set mean group
+    velocity of each mode projected on the reciprocal vectors b_a (rows of
+    2 pi cell^-T) over the grid divisions G_a (Appendix A, adaptive width)."""
+    b = 2.0 * np.pi * np.linalg.inv(crystal.cell).T           # rows: reciprocal vectors [rad/A]
+    G = np.asarray(ph.grid, dtype=float)
+    vbar = ph.velocity.copy()
+    for k in range(ph.n_k):
+        for S in ph.sets[k]:
+            vbar[k, S] = vbar[k, S].mean(axis=0)
+    return np.einsum('ksx,ax->ksa', vbar, b) / G[None, None, :]
+
+
+def adaptive_sigma(U1, U2, scale, sigma_min):
+    """Gaussian standard deviation of processes whose two partner modes have
+    projections U1 and U2 (broadcast, last axis a): max(scale sqrt(sum_a (U1 -
+    U2)^2 / 12), sigma_min)."""
+    d = U1 - U2
+    return np.maximum(scale * np.sqrt(np.sum(d * d, axis=-1) / 12.0), sigma_min)
 
 
 def rate_prefactor():
@@ -152,13 +186,20 @@ def _set_average(ph, k, g):
     return out
 
 
-def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, average=True, delta='gauss'):
+def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, average=True, delta='gauss',
+               adaptive=None):
     """gamma_mu [rad/ps] for every mode mu = (k, s), k in k_subset, each T.
 
     ``delta`` picks the finite-width energy delta of the appendix (Gaussian,
     Lorentzian or triangular; width 2 pi sigma_thz in angular frequency).
+    ``adaptive`` (a scale a, Gaussian only, needs ph with velocities): each
+    process gets its own width max(a sigma_grid, 2 pi sigma_thz) from the
+    velocities of its two partner modes (see the module header).
     Returns an array (nT, len(k_subset), n)."""
     delta_fn = DELTAS[delta]
+    if adaptive is not None:
+        assert delta == 'gauss'
+        U = adaptive_velocity_projections(crystal, ph)
     T = np.atleast_1d(np.asarray(T, dtype=float))
     ks = np.arange(ph.n_k) if k_subset is None else np.asarray(k_subset)
     n = crystal.n_modes
@@ -183,7 +224,11 @@ def linewidths(crystal, ph, T, sigma_thz, stats='quantum', k_subset=None, averag
                   & ph.mask[kpps][:, None, None, :])
             with np.errstate(divide='ignore', invalid='ignore'):
                 inv = np.where(m3, 1.0 / (w1 * w2 * w3), 0.0)
-            delta = delta_fn(w1 + sign * w2 - w3, sig)
+            if adaptive is None:
+                delta = delta_fn(w1 + sign * w2 - w3, sig)
+            else:
+                s_e = adaptive_sigma(U[kps][:, None, :, None, :], U[kpps][:, None, None, :, :], adaptive, sig)
+                delta = delta_fn(w1 + sign * w2 - w3, s_e)
             for it, t in enumerate(T):
                 n2 = np.where(ph.mask[kps][:, None, :, None], occupation(w2, t, stats), 0.0)
                 n3 = np.where(ph.mask[kpps][:, None, None, :], occupation(w3, t, stats), 0.0)
