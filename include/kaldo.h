@@ -299,6 +299,25 @@ kaldo_status kaldo_kappa_qhgk(kaldo_ctx ctx, double* kappa_out);
  * than {1,1,1} or d_out == NULL. */
 kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out);
 
+/* Adaptive widths of the energy delta (paper Appendix A: in crystals the width
+ * can be estimated from the phonon velocities) for the later kaldo_linewidths
+ * calls on this context.  scale a > 0: every process gets its own Gaussian of
+ * standard deviation
+ *   max(a sigma_grid, 2 pi sigma_thz),
+ *   sigma_grid = sqrt(sum_a ((v' -+ v'') . b_a / G_a)^2 / 12),
+ * the spread of the energy mismatch w +- w' - w'' when the partner q' moves
+ * over one cell of the q grid (reciprocal vectors b_a = 2 pi cell^-T rows,
+ * grid divisions G_a; - for absorption, + for decay in the partners (p, k+p)
+ * of one V); v are the mean group velocities of the modes' degenerate sets
+ * (basis independent), and sigma_thz of the kaldo_linewidths call is the
+ * smallest width.  0 turns it off (the default).  With adaptive widths
+ * kaldo_linewidths needs the Gaussian delta and a grid other than {1,1,1}
+ * (KALDO_EINVAL otherwise), and no tile is skipped by the delta window;
+ * kaldo_kappa_bte takes the fixed width and refuses such linewidths; the
+ * batch calls and kaldo_phase_space keep fixed widths.
+ * Errors: KALDO_EINVAL for a negative or non-finite scale. */
+kaldo_status kaldo_adaptive_width(kaldo_ctx ctx, double scale);
+
 /* Options of the QHGK conductivity (paper Appendix A, the "QHGK" engine) for
  * the later kaldo_kappa_qhgk and kaldo_mode_diffusivity calls on this context:
  *   bandwidth  eta [rad/ps] > 0: every mode's linewidth in the Lorentzian

@@ -35,7 +35,74 @@ struct ProjArgs {
   int kind;      // kaldo_delta (selects the kernel instance)
   int npair;     // leading slot pairs (2m, 2m + 1) of A_k in sum/difference form
   const int* klist;  // first-mode point of block row kl: klist[k0 + kl] (null: k0 + kl)
+  const double* UT;  // adaptive widths: scaled velocity projections [n][3][nk] (kDeltaGaussAdaptive)
 };
+
+// ---- adaptive widths -------------------------------------------------------------
+// UT[s][a][k] = (c / sigma_min) vbar_ks . b_a / G_a with c = scale / sqrt(12):
+// the degenerate-set mean velocity of mode (k, s) (a single mode's velocity
+// depends on the basis inside its set, the mean does not) projected on the
+// reciprocal vectors over the grid divisions (Bg[a][x] = b_a[x] / G_a).  The
+// Gaussian of a process with partner modes 1 and 2 then has standard
+// deviation sigma_min rho, rho = max(1, |UT_1 -+ UT_2|) (minus for
+// absorption, plus for decay, where the partner at -p has velocity -v).
+__global__ void k_adapt_table(double* __restrict__ UT, const double* __restrict__ vel, const int* __restrict__ setid,
+                              int nk, int n, double3 B0, double3 B1, double3 B2, double scale) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)nk * n) return;
+  const int k = (int)(idx / n), s = (int)(idx % n);
+  const int* sid = setid + (size_t)k * n;
+  const int first = sid[s];
+  int last = first;
+  while (last + 1 < n && sid[last + 1] == first) ++last;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int u = first; u <= last; ++u) {
+    const double* v = vel + ((size_t)k * n + u) * 3;
+    v0 += v[0];
+    v1 += v[1];
+    v2 += v[2];
+  }
+  const double m = scale / (last - first + 1);
+  v0 *= m;
+  v1 *= m;
+  v2 *= m;
+  UT[((size_t)s * 3 + 0) * nk + k] = v0 * B0.x + v1 * B0.y + v2 * B0.z;
+  UT[((size_t)s * 3 + 1) * nk + k] = v0 * B1.x + v1 * B1.y + v2 * B1.z;
+  UT[((size_t)s * 3 + 2) * nk + k] = v0 * B2.x + v1 * B2.y + v2 * B2.z;
+}
+
+kaldo_status adaptive_table(kaldo_ctx ctx, double sigma_omega, const double** UT) {
+  const int nk = ctx->nk, n = ctx->nm;
+  // reciprocal vectors b_a = 2 pi (cell^-1)^T rows, over the grid divisions
+  const double* c = ctx->cell;
+  const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+                     c[2] * (c[3] * c[7] - c[4] * c[6]);
+  // inverse of the cell matrix (rows = lattice vectors): inv[x][a]
+  double inv[9];
+  inv[0] = (c[4] * c[8] - c[5] * c[7]) / det;
+  inv[1] = (c[2] * c[7] - c[1] * c[8]) / det;
+  inv[2] = (c[1] * c[5] - c[2] * c[4]) / det;
+  inv[3] = (c[5] * c[6] - c[3] * c[8]) / det;
+  inv[4] = (c[0] * c[8] - c[2] * c[6]) / det;
+  inv[5] = (c[2] * c[3] - c[0] * c[5]) / det;
+  inv[6] = (c[3] * c[7] - c[4] * c[6]) / det;
+  inv[7] = (c[1] * c[6] - c[0] * c[7]) / det;
+  inv[8] = (c[0] * c[4] - c[1] * c[3]) / det;
+  // b_a[x] = 2 pi inv[x][a]
+  double3 B[3];
+  for (int a = 0; a < 3; ++a) {
+    const double f = kTwoPi / ctx->grid[a];
+    B[a] = make_double3(f * inv[0 * 3 + a], f * inv[1 * 3 + a], f * inv[2 * 3 + a]);
+  }
+  KALDO_HIP(ctx, ctx->d_adapt.ensure((size_t)nk * n * 3 * sizeof(double)));
+  const double scale = ctx->adaptive_scale / sqrt(12.0) / sigma_omega;
+  hipLaunchKernelGGL(k_adapt_table, dim3(blocks_for((long long)nk * n, 256)), dim3(256), 0, ctx->stream,
+                     ctx->d_adapt.as<double>(), ctx->d_vel.as<double>(), ctx->d_setid.as<int>(), nk, n, B[0], B[1],
+                     B[2], scale);
+  KALDO_HIP(ctx, hipGetLastError());
+  *UT = ctx->d_adapt.as<double>();
+  return KALDO_OK;
+}
 
 // ---- zero fill (a kernel, so that it can sit in a captured graph) ----------------
 __global__ void k_fill_zero(uint4* __restrict__ p16, unsigned char* __restrict__ tail, size_t n16, size_t ntail) {
@@ -241,10 +308,16 @@ __global__ void __launch_bounds__(256)
       cplx<R> Ep[NM][NM];
       double wp[NM];
       R np_[NT][NM], iwp[NM];
+      constexpr bool ADAPT = DK == kDeltaGaussAdaptive;
+      R up[ADAPT ? NM : 1][3];  // adaptive widths: scaled velocity projections of (p, s')
 #pragma unroll
       for (int s1 = 0; s1 < NM; ++s1) {
 #pragma unroll
         for (int a = 0; a < NM; ++a) Ep[a][s1] = ET[((size_t)s1 * NM + a) * nk + p];
+        if constexpr (ADAPT) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) up[s1][a] = (R)P.UT[((size_t)s1 * 3 + a) * nk + p];
+        }
         wp[s1] = OM[(size_t)s1 * nk + p] * P.rc;  // frequencies in units of the delta's scale
         iwp[s1] = (R)IW[(size_t)s1 * nk + p];
 #pragma unroll
@@ -302,7 +375,7 @@ __global__ void __launch_bounds__(256)
         for (int s2 = 0; s2 < NM; ++s2) {
           const size_t col = (size_t)s2 * NM * nk + kk + z;
           const double d2 = ws - OM[(size_t)s2 * nk + kk + z] * P.rc;  // (w - w'') / scale
-          if constexpr (DK != KALDO_DELTA_LORENTZ && std::is_same<R, float>::value) {
+          if constexpr ((DK == KALDO_DELTA_GAUSS || DK == KALDO_DELTA_TRIANGLE) && std::is_same<R, float>::value) {
             // a column whose every element, over the wave's partners and all
             // s', lies beyond the delta's cut adds nothing: skip its step C
             // (FP32 only: FP64 keeps more of the tail and runs one wave per
@@ -324,6 +397,11 @@ __global__ void __launch_bounds__(256)
             for (int b = 0; b < NM; ++b) cfma_conj(Tc[a], F[a][b], ET[col + (size_t)b * nk]);
           }
           const R iw2 = (R)IW[(size_t)s2 * nk + kk + z];
+          R uq[3];  // adaptive widths: (k + p, s'')
+          if constexpr (ADAPT) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) uq[a] = (R)P.UT[((size_t)s2 * 3 + a) * nk + kk + z];
+          }
           R n2[NT];
 #pragma unroll
           for (int t = 0; t < NT; ++t) n2[t] = t < P.nT ? (R)OCC[((size_t)t * NM + s2) * nk + kk + z] : (R)0;
@@ -333,8 +411,23 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int a = 0; a < NM; ++a) cfma(V, Ep[a][s1], Tc[a]);
             const R v2 = (V.re * V.re + V.im * V.im) * (iwp[s1] * iw2);
-            const R gp = delta_shape<R, DK>(d2 + wp[s1]) * v2;
-            const R gm = (R)0.5 * delta_shape<R, DK>(d2 - wp[s1]) * v2;
+            R gp, gm;
+            if constexpr (ADAPT) {
+              // widths sigma_min rho: rho = max(1, |u' - u''|) (absorption), max(1, |u' + u''|) (decay)
+              R dp = 0, dm = 0;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const R x = up[s1][a] - uq[a], y = up[s1][a] + uq[a];
+                dp += x * x;
+                dm += y * y;
+              }
+              const R ip = (R)1 / sqrt(dp > (R)1 ? dp : (R)1), im = (R)1 / sqrt(dm > (R)1 ? dm : (R)1);
+              gp = delta_shape<R, KALDO_DELTA_GAUSS>((d2 + wp[s1]) * (double)ip) * (ip * v2);
+              gm = (R)0.5 * delta_shape<R, KALDO_DELTA_GAUSS>((d2 - wp[s1]) * (double)im) * (im * v2);
+            } else {
+              gp = delta_shape<R, DK>(d2 + wp[s1]) * v2;
+              gm = (R)0.5 * delta_shape<R, DK>(d2 - wp[s1]) * v2;
+            }
             // gp (n' - n'') + gm (1 + n' + n'') = gm + n' (gp + gm) + n'' (gm - gp)
             const R sp = gp + gm, sm = gm - gp;
 #pragma unroll
@@ -431,6 +524,7 @@ static void launch_project(dim3 grid, hipStream_t st, const cplx<R>* A, const cp
   }
   if (P.kind == KALDO_DELTA_GAUSS) KALDO_KIND(KALDO_DELTA_GAUSS)
   else if (P.kind == KALDO_DELTA_LORENTZ) KALDO_KIND(KALDO_DELTA_LORENTZ)
+  else if (P.kind == kDeltaGaussAdaptive) KALDO_KIND(kDeltaGaussAdaptive)
   else KALDO_KIND(KALDO_DELTA_TRIANGLE)
 #undef KALDO_KIND
 }
@@ -490,6 +584,13 @@ static kaldo_status linewidths_small(kaldo_ctx ctx, double sigma_thz) {
   delta_scale(ctx->delta, sig, dscale, dnorm);
   P.rc = 1.0 / dscale;
   P.kind = ctx->delta;
+  P.UT = nullptr;
+  if (ctx->adaptive_scale > 0.0) {
+    // Gaussian widths per process, sig the smallest (the scale and norm above are sig's)
+    P.kind = kDeltaGaussAdaptive;
+    const kaldo_status as = adaptive_table(ctx, sig, &P.UT);
+    if (as != KALDO_OK) return as;
+  }
   // FP64 runs step B over single slots: at one wave per SIMD the paired
   // loop was slower there
   P.npair = sizeof(R) == 4 ? ctx->fc3.n_dpair : 0;

@@ -580,6 +580,8 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
     return fail(ctx, KALDO_ESTATE, "no fc3 resident: pass one");
   }
   if (k_lo(ctx) >= k_hi(ctx)) return fail(ctx, KALDO_EINVAL, "the k range holds no grid point");
+  if (ctx->adaptive_scale > 0.0 && (delta != KALDO_DELTA_GAUSS || ctx->nk == 1))
+    return fail(ctx, KALDO_EINVAL, "adaptive widths need the Gaussian delta and a grid other than {1,1,1}");
   ctx->nT = nT;
   for (int t = 0; t < nT; ++t) ctx->T[t] = T[t];
   ctx->stats = stats;
@@ -587,6 +589,7 @@ kaldo_status kaldo_linewidths(kaldo_ctx ctx, const kaldo_fc3* fc3, const double*
   ctx->sigma_thz = sigma_thz;
   ctx->have_gamma = false;
   ctx->gamma_external = false;
+  ctx->gamma_adaptive = ctx->adaptive_scale > 0.0;
   if ((st = run_linewidths(ctx, sigma_thz, precision)) != KALDO_OK) return st;
   ctx->g_lo = k_lo(ctx);
   ctx->g_hi = k_hi(ctx);
@@ -635,6 +638,8 @@ kaldo_status kaldo_kappa_bte(kaldo_ctx ctx, kaldo_bte_method method, int32_t max
   if (terms_out) *terms_out = 0;
   if (!ctx->have_gamma || !ctx->have_fc3 || ctx->gamma_external)
     return fail(ctx, KALDO_ESTATE, "kaldo_kappa_bte before kaldo_linewidths");
+  if (ctx->gamma_adaptive)
+    return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: the scattering operator takes the fixed width, not adaptive ones");
   if (method != KALDO_BTE_INVERSE && method != KALDO_BTE_SELF_CONSISTENT)
     return fail(ctx, KALDO_EINVAL, "kaldo_kappa_bte: unknown method");
   if (method == KALDO_BTE_SELF_CONSISTENT && (max_terms < 1 || !(tol > 0.0) || !std::isfinite(tol)))
@@ -684,6 +689,15 @@ kaldo_status kaldo_mode_diffusivity(kaldo_ctx ctx, double* d_out) {
   kaldo_status st;
   if ((st = run_mode_diffusivity(ctx)) != KALDO_OK) return st;
   return copy_out(ctx, d_out, ctx->d_diff.p, (size_t)ctx->nT * ctx->nm * 3 * sizeof(double));
+}
+
+kaldo_status kaldo_adaptive_width(kaldo_ctx ctx, double scale) {
+  if (!ctx) return KALDO_EINVAL;
+  ctx->err.clear();
+  if (!std::isfinite(scale) || scale < 0.0)
+    return fail(ctx, KALDO_EINVAL, "kaldo_adaptive_width: scale must be finite and >= 0");
+  ctx->adaptive_scale = scale;
+  return KALDO_OK;
 }
 
 kaldo_status kaldo_qhgk_options(kaldo_ctx ctx, double bandwidth, double threshold) {

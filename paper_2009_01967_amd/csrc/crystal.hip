@@ -222,8 +222,11 @@ struct EpiCrystal {
   long long ncol;               // n * n
   int n, nk, nT, k, p0, m_tiles;
   double rs;                    // 1 / (scale of the delta)
+  const double* UT = nullptr;   // adaptive widths: scaled velocity projections [s][3][k] (kDeltaGaussAdaptive)
   static constexpr bool kAllShapes = DK == KALDO_DELTA_GAUSS;
-  static constexpr bool kSkipEmpty = DK != KALDO_DELTA_LORENTZ;  // the Lorentzian has no cut
+  static constexpr bool kAdapt = DK == kDeltaGaussAdaptive;
+  // the Lorentzian has no cut; adaptive widths have no common one
+  static constexpr bool kSkipEmpty = DK == KALDO_DELTA_GAUSS || DK == KALDO_DELTA_TRIANGLE;
 
   // Every element of block tile (mt, nt) of partner z beyond the delta's cut:
   // frequencies ascend with the mode index at every grid point, rows hold the
@@ -268,6 +271,7 @@ struct EpiCrystal {
     // column data: w - w'' (first mode minus k+p mode), 1/w'', n''
     double dcol[FN];
     R iw2[FN], n2[FN][NT], o[FN][NT];
+    R uq[kAdapt ? FN : 1][3];  // adaptive widths: (k + p, s'')
 #pragma unroll
     for (int q = 0; q < FN; ++q) {
       const long long col = at.c0 + 16 * q + (at.lane & 15);
@@ -276,6 +280,10 @@ struct EpiCrystal {
       const int s2 = cv ? (int)(col - (long long)s * n) : 0;
       dcol[q] = (OM[(size_t)s * nk + k] - OM[(size_t)s2 * nk + kk]) * rs;
       iw2[q] = cv ? (R)IW[(size_t)s2 * nk + kk] : (R)0;
+      if constexpr (kAdapt) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) uq[q][a] = (R)UT[((size_t)s2 * 3 + a) * nk + kk];
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         n2[q][t] = t < nT ? (R)OCC[((size_t)t * n + s2) * nk + kk] : (R)0;
@@ -287,31 +295,53 @@ struct EpiCrystal {
       // row data of the lane's two (Re, Im) pairs: w', 1/w', n'
       double w1[2];
       R iw1[2], n1[2][NT];
+      R up[kAdapt ? 2 : 1][3];  // adaptive widths: (p, s')
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
         const int ic = i < n ? i : n - 1;
         w1[h] = OM[(size_t)ic * nk + p] * rs;
         iw1[h] = i < n ? (R)IW[(size_t)ic * nk + p] : (R)0;
+        if constexpr (kAdapt) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) up[h][c] = (R)UT[((size_t)ic * 3 + c) * nk + p];
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)OCC[((size_t)t * n + ic) * nk + p] : (R)0;
       }
 #pragma unroll
       for (int q = 0; q < FN; ++q) {
         // a 16 x 16 sub-tile with every element outside the delta's cutoff adds nothing
-        bool need = false;
+        if constexpr (!kAdapt) {
+          bool need = false;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
-          need = need || fmin(xp * xp, xm * xm) < cut;
+          for (int h = 0; h < 2; ++h) {
+            const double xp = dcol[q] + w1[h], xm = dcol[q] - w1[h];
+            need = need || fmin(xp * xp, xm * xm) < cut;
+          }
+          if (__ballot(need) == 0) continue;
         }
-        if (__ballot(need) == 0) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const R vr = (R)acc[a][q][2 * h], vi = (R)acc[a][q][2 * h + 1];
           const R v2 = (vr * vr + vi * vi) * iw1[h] * iw2[q];
-          const R gp = delta_shape<R, DK>(dcol[q] + w1[h]);
-          const R gm = delta_shape<R, DK>(dcol[q] - w1[h]);
+          R gp, gm;
+          if constexpr (kAdapt) {
+            // widths sigma_min rho: rho = max(1, |u' - u''|) (absorption), max(1, |u' + u''|) (decay)
+            R dp = 0, dm = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const R x = up[h][c] - uq[q][c], y = up[h][c] + uq[q][c];
+              dp += x * x;
+              dm += y * y;
+            }
+            const R ip = (R)1 / sqrt(dp > (R)1 ? dp : (R)1), im = (R)1 / sqrt(dm > (R)1 ? dm : (R)1);
+            gp = delta_shape<R, KALDO_DELTA_GAUSS>((dcol[q] + w1[h]) * (double)ip) * ip;
+            gm = delta_shape<R, KALDO_DELTA_GAUSS>((dcol[q] - w1[h]) * (double)im) * im;
+          } else {
+            gp = delta_shape<R, DK>(dcol[q] + w1[h]);
+            gm = delta_shape<R, DK>(dcol[q] - w1[h]);
+          }
           const R hh = (R)0.5 * gm, a1 = gp + hh, a2 = hh - gp;
 #pragma unroll
           for (int t = 0; t < NT; ++t) o[q][t] += v2 * (hh + n1[h][t] * a1 + n2[q][t] * a2);
@@ -498,6 +528,12 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   delta_scale(ctx->delta, sig, dscale, dnorm);
   const double C = kPi / 8.0 * kHbar * kEvUnit * kEvUnit * kEvUnit / nk * dnorm;
   const std::string shape = std::to_string(P) + "/" + std::to_string(n) + "/";
+  // adaptive widths: Gaussian per process, sig the smallest (dscale and dnorm are sig's)
+  const double* UT = nullptr;
+  if (ctx->adaptive_scale > 0.0) {
+    const kaldo_status as = adaptive_table(ctx, sig, &UT);
+    if (as != KALDO_OK) return as;
+  }
   if (planning(ctx)) {
     // everything the persistent batch kernel needs to run this crystal
     CrystalPlan& cp = ctx->cplan;
@@ -617,10 +653,10 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       g2.a_map = nullptr;
       int v = 0;
       const std::string key2 = "cr2/" + shape + std::to_string(cnt) + "/" + std::to_string(nT) + "/" +
-                               std::to_string(ctx->delta);
+                               std::to_string(UT ? kDeltaGaussAdaptive : ctx->delta);
 #define KALDO_EPI(NTV, DKV)                                                                                          \
   {                                                                                                             \
-    EpiCrystal<NTV, DKV> e2{OM, IW, OCC, kmap + (size_t)k * nk + p0, partial, nn, n, nk, nT, k, p0, 0, 1.0 / dscale}; \
+    EpiCrystal<NTV, DKV> e2{OM, IW, OCC, kmap + (size_t)k * nk + p0, partial, nn, n, nk, nT, k, p0, 0, 1.0 / dscale, UT}; \
     /* the partial layout depends on the row tiling of the variant that runs */                               \
     const int vt = autotune(ctx, key2, gemm_variants<P, decltype(e2)>(), 0, [&](int w) {                                           \
       e2.m_tiles = gemm_m_tiles<P>(w, mrows);                                                                   \
@@ -637,7 +673,8 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
     else if (nT <= 4) KALDO_EPI(4, DKV) \
     else KALDO_EPI(8, DKV)              \
   }
-      if (ctx->delta == KALDO_DELTA_GAUSS) KALDO_EPI_NT(KALDO_DELTA_GAUSS)
+      if (UT) KALDO_EPI_NT(kDeltaGaussAdaptive)
+      else if (ctx->delta == KALDO_DELTA_GAUSS) KALDO_EPI_NT(KALDO_DELTA_GAUSS)
       else if (ctx->delta == KALDO_DELTA_LORENTZ) KALDO_EPI_NT(KALDO_DELTA_LORENTZ)
       else KALDO_EPI_NT(KALDO_DELTA_TRIANGLE)
 #undef KALDO_EPI_NT

@@ -26,6 +26,9 @@ constexpr double kKappaSI = kElectronVolt / (1e-10 * 1e-12);
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kNuMinThz = 0.01;       // modes below are excluded
+// Internal delta kind: Gaussian whose width is set per process from the
+// velocities of its two partner modes (kaldo_adaptive_width)
+constexpr int kDeltaGaussAdaptive = 3;
 constexpr double kNuUnstableThz = -0.05; // below: imaginary mode error
 constexpr double kDegenerateThz = 1e-5;  // chained gap for degenerate sets
 
@@ -219,6 +222,8 @@ struct kaldo_ctx_s {
   int delta = KALDO_DELTA_GAUSS;
   double sigma_thz = 0.0;               // delta width of the last linewidths
   bool gamma_external = false;          // the resident gamma came from kaldo_set_gamma / kaldo_gamma_interpolate
+  double adaptive_scale = 0.0;          // kaldo_adaptive_width: scale of the per-process width (0: off)
+  bool gamma_adaptive = false;          // the resident gamma was computed with adaptive widths
   double qhgk_bandwidth = 0.0;          // kaldo_qhgk_options: every linewidth in tau_{mu mu'} (0: off)
   double qhgk_threshold = 0.0;          // kaldo_qhgk_options: tau = 0 beyond this |w - w'| (0: off)
   kaldo::Arena arena;                   // caller's workspace (kaldo_set_workspace), if any
@@ -235,6 +240,7 @@ struct kaldo_ctx_s {
   kaldo::DevBuf d_bte;               // full BTE: scattering operator pieces, set tables, solve
   kaldo::DevBuf d_klist;             // first-mode points a linewidth run computes (int)
   kaldo::DevBuf d_interp;            // gamma interpolation: source modes, bins, knots, raw values
+  kaldo::DevBuf d_adapt;             // adaptive widths: scaled velocity projections [n][3][Nk]
   kaldo::CrystalPlan cplan{};        // the last planning pass of the many-branch path
   size_t xy_budget = (size_t)256 << 20;  // bytes of step-B and GEMM-1 outputs per partner batch
   bool xy_shared = false;                // planning a batch: X and Y come from the parent's shared pool
@@ -318,6 +324,8 @@ kaldo_status run_kappa_rta(kaldo_ctx ctx);
 hipError_t noalloc_setup(int device);
 kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out);
 kaldo_status run_kappa_qhgk(kaldo_ctx ctx);
+// the scaled velocity projections of the adaptive widths, UT[s][a][k] (see k_adapt_table)
+kaldo_status adaptive_table(kaldo_ctx ctx, double sigma_omega, const double** UT);
 kaldo_status run_gamma_interpolate(kaldo_ctx ctx, const double* omega_src, const double* gamma_src, int64_t n_src,
                                    int n_bins);
 // gamma[t][k][s] = mean of graw over the degenerate set of (k, s), on the context's stream

@@ -53,7 +53,7 @@ EXPORTED = ["kaldo_create", "kaldo_destroy", "kaldo_last_error", "kaldo_phonons"
             "kaldo_profile_read", "kaldo_phase_space", "kaldo_set_k_range", "kaldo_batch_set_k_range",
             "kaldo_set_workspace", "kaldo_profile_flops", "kaldo_mode_diffusivity",
             "kaldo_kappa_rta_noalloc", "kaldo_kappa_bte", "kaldo_batch_plan", "kaldo_qhgk_options",
-            "kaldo_set_gamma", "kaldo_gamma_interpolate"]
+            "kaldo_set_gamma", "kaldo_gamma_interpolate", "kaldo_adaptive_width"]
 
 
 class kaldo_structure(C.Structure):
@@ -121,6 +121,8 @@ def load_library(path: str = LIB_PATH):
     lib.kaldo_kappa_qhgk.restype = C.c_int
     lib.kaldo_mode_diffusivity.argtypes = [C.c_void_p, C.c_void_p]
     lib.kaldo_mode_diffusivity.restype = C.c_int
+    lib.kaldo_adaptive_width.argtypes = [C.c_void_p, C.c_double]
+    lib.kaldo_adaptive_width.restype = C.c_int
     lib.kaldo_qhgk_options.argtypes = [C.c_void_p, C.c_double, C.c_double]
     lib.kaldo_qhgk_options.restype = C.c_int
     lib.kaldo_set_gamma.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int, C.c_void_p]
@@ -290,6 +292,10 @@ def kaldo_kappa_qhgk(ctx, kappa_out=None) -> int:
 
 def kaldo_mode_diffusivity(ctx, d_out) -> int:
     return load_library().kaldo_mode_diffusivity(ctx, _out_ptr(d_out))
+
+
+def kaldo_adaptive_width(ctx, scale: float) -> int:
+    return load_library().kaldo_adaptive_width(ctx, float(scale))
 
 
 def kaldo_qhgk_options(ctx, bandwidth: float = 0.0, threshold: float = 0.0) -> int:
@@ -517,6 +523,11 @@ class Context:
             out = np.zeros((self.nT, 3, 3))
         _check(self.h, kaldo_kappa_qhgk(self.h, out))
         return out
+
+    def adaptive_width(self, scale=1.0):
+        """Per-process Gaussian widths from the velocities for later linewidths
+        (scale 0 turns them off); the linewidths' sigma_thz is the smallest width."""
+        _check(self.h, kaldo_adaptive_width(self.h, scale))
 
     def qhgk_options(self, bandwidth=0.0, threshold=0.0):
         """QHGK bandwidth eta and energy threshold [rad/ps] for later kappa_qhgk
