@@ -426,7 +426,7 @@ def run_batch_headline(steps, warmup, div=64, share=1):
     graph_ms, launches = kaldo.kaldo_profile_read(ctx.h, "batch_graph")
     phases = {}
     for name in ("batch_a_collect", "batch_step_b", "batch_gemm1", "batch_gemm2", "batch_barrier_wait",
-                 "batch_set_average"):
+                 "batch_wait_gemm1_phase", "batch_wait_gemm2_phase", "batch_set_average"):
         tot, cnt = kaldo.kaldo_profile_read(ctx.h, name)
         phases[name] = tot / max(cnt, 1)
     log(f"batch fp32 phases (ms per launch, workgroup 0): {phases}")

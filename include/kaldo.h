@@ -454,7 +454,10 @@ kaldo_status kaldo_set_tuning(kaldo_ctx ctx, kaldo_tuning mode);
  *   batch kernel as workgroup 0 sees them (its own work in each stage, summed
  *   over the rounds): "batch_a_collect" (step A, collection, Y padding),
  *   "batch_step_b", "batch_gemm1", "batch_gemm2", "batch_barrier_wait" (its
- *   waits at grid barriers) and "batch_set_average".
+ *   waits at grid barriers; "batch_wait_gemm1_phase" and
+ *   "batch_wait_gemm2_phase" split them by the phase they end) and
+ *   "batch_set_average"; and each crystal's share of the launch,
+ *   "batch_crystal_<handle>" (workgroup 0's clock over the crystal's rounds).
  * kaldo_profile_enable(ctx, 1) enables and clears the totals, 0 disables
  * and clears them.
  * kaldo_profile_read synchronises the stream and returns, for one kernel

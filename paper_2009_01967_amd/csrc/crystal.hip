@@ -173,6 +173,52 @@ __global__ void k_cr_x(typename Operand<P>::T* __restrict__ Xh, typename Operand
   cr_x_elem<P, ZT, RZ>(Xh, Xl, Z, PH, cg_delta, cg_order, cpair, pairmap, n, N, nk, ng, ldk, p0, zb, idx);
 }
 
+// Step B as cr_x_elem, for the partners zc .. zc + zn of the batch with their
+// phases staged in LDS: phs[d * ZC + u] = e^{2 pi i p.Delta_d} for p = p0 +
+// zc + u (written by the caller).
+template <int P, int ZT, typename RZ>
+__device__ __forceinline__ void cr_x_elem_lds(typename Operand<P>::T* __restrict__ Xh,
+                                              typename Operand<P>::T* __restrict__ Xl,
+                                              const cplx<RZ>* __restrict__ Z, const cplx<RZ>* __restrict__ phs,
+                                              int ZC, const int* __restrict__ cg_delta,
+                                              const int* __restrict__ cg_order, const int4* __restrict__ cpair,
+                                              const int* __restrict__ pairmap, int n, int N, int ng, int ldk, int zc,
+                                              int zn, long long idx) {
+  const int half = ldk / 2;
+  const long long nn = (long long)n * n;
+  const int a2 = (int)(idx % half);
+  const long long row = idx / half;  // s * n + a'
+  const int a1 = (int)(row % n);
+  const int s = (int)(row / n);
+  int cp = -1;
+  if (a2 < n) cp = pairmap[(size_t)(a1 / 3) * N + a2 / 3];
+  const int e9 = 3 * (a1 % 3) + a2 % 3;
+  for (int z0 = 0; z0 < zn; z0 += ZT) {
+    RZ re[ZT], im[ZT];
+#pragma unroll
+    for (int u = 0; u < ZT; ++u) re[u] = im[u] = (RZ)0;
+    if (cp >= 0) {
+      const int4 pr = cpair[cp];
+      for (int q = pr.z; q < pr.w; ++q) {
+        const int g = cg_order[q];
+        const cplx<RZ> zz = Z[((size_t)s * ng + g) * 9 + e9];
+        const cplx<RZ>* ph = phs + (size_t)cg_delta[g] * ZC + z0;
+#pragma unroll
+        for (int u = 0; u < ZT; ++u) {
+          const RZ fr = ph[u].re, fi = ph[u].im;
+          re[u] += fr * zz.re - fi * zz.im;
+          im[u] += fr * zz.im + fi * zz.re;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < ZT; ++u)
+      if (z0 + u < zn)
+        store_operand2<P>(Xh, Xl, ((size_t)(zc + z0 + u) * nn + row) * ldk + 2 * (size_t)a2, (double)re[u],
+                          (double)im[u]);
+  }
+}
+
 // the realified pair h (0, 1) of a lane's 4 accumulator rows inside a 16-row tile at row m
 template <int P>
 __device__ __forceinline__ int cr_pair_mode(int m, int lane, int h) {
@@ -544,6 +590,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
     cp.N = N;
     cp.nk = nk;
     cp.ng = ng;
+    cp.nd = ctx->fc3.n_delta;
     cp.nT = nT;
     cp.ldk = ldk;
     cp.mrows = mrows;
@@ -714,11 +761,42 @@ struct BatchRound {
 struct GridSync {
   unsigned count, gen, abort, pad;
   unsigned long long flops;     // MFMA flops of the GEMM block tiles that ran (not skipped)
-  unsigned long long phase[6];  // block 0's constant-rate clock ticks: step A with the collection
-                                // and Y padding, step B, GEMM 1, GEMM 2, waits at grid barriers,
-                                // set average
+  unsigned long long phase[7];  // block 0's constant-rate clock ticks: step A with the collection
+                                // and Y padding, step B, GEMM 1, GEMM 2, waits at the grid barrier
+                                // after the GEMM 1 phase, set average, waits after the GEMM 2 phase
   unsigned long long t_begin;   // block 0's clock before the first round
+  unsigned long long claims[5]; // chunks claimed so far by step B, step A, the collection, GEMM 1, GEMM 2
 };
+
+// Stage work handed out in chunks: workgroups claim chunk indices from the
+// stage's counter until a claim comes back past the stage's nch chunks, so a
+// workgroup that left the phase's GEMM tiles early takes more of the stage.
+// Every workgroup makes exactly one claim past the end per stage, so after a
+// stage the counter stands at base + nch + G in every workgroup's view, and
+// the grid barriers between phases keep two uses of one counter apart.
+// Elements per chunk: about four chunks per workgroup, between one and 16
+// elements per thread (small stages keep every workgroup busy, large ones
+// claim seldom).
+__device__ __forceinline__ long long stage_chunk(long long cnt, int G) {
+  long long ch = cnt / (4LL * G);
+  ch = ch < 256 ? 256 : (ch > 4096 ? 4096 : ch);
+  return (ch + 255) & ~255LL;
+}
+
+template <class F>
+__device__ __forceinline__ void claimed(unsigned long long* ctr, unsigned long long& base, long long nch, int G,
+                                        F&& f) {
+  __shared__ long long s_chunk;
+  for (;;) {
+    if (threadIdx.x == 0) s_chunk = (long long)(atomicAdd(ctr, 1ull) - base);
+    __syncthreads();
+    const long long c = s_chunk;
+    __syncthreads();
+    if (c >= nch) break;
+    f(c);
+  }
+  base += (unsigned long long)nch + (unsigned long long)G;
+}
 
 // block 0 adds the ticks since *t0 to phase p and restarts the clock
 __device__ __forceinline__ void phase_mark(GridSync* gs, int b, unsigned long long& t0, int p) {
@@ -766,44 +844,41 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned nblocks) {
   return s_abort != 0;
 }
 
-// The tiles of one GEMM phase over the persistent grid.  The logical tiles go
-// to the 8 XCDs (x = block % 8) in chunks of 8 consecutive tiles dealt round
-// robin, and the 64 workgroups of an XCD take its tiles in order, each the
-// next one 64 places on.  A chunk holds the row tiles of two or three column
-// panels, so the workgroups of an XCD still share operand panels in its L2,
-// while every XCD gets its share of every partner.  Row tile mt has 32
-// rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of several heights cover the
-// 2n realified rows with little padding).
+// The tiles of one GEMM phase over the persistent grid, in chunks of up to 8
+// consecutive logical tiles (a chunk of 8 holds the row tiles of two or three
+// column panels, which share their operand panels in L2; phases with fewer
+// than 4 G tiles get smaller chunks) that the workgroups claim one at a time
+// (claimed(): a workgroup that finished early takes more).  Row tile mt has 32 rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of
+// several heights cover the 2n realified rows with little padding).
 template <int P, int FN, class Epi>
-__device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int b, int G,
-                                                const CrystalPlan& C) {
-  constexpr int CH = 8;
+__device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int G, const CrystalPlan& C,
+                                                unsigned long long* ctr, unsigned long long& base) {
   constexpr unsigned long long mult = P == KALDO_BF16X3 ? 3 : 1;
   g.m_tiles = C.m_tiles2;
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
   g.group_m = g.m_tiles < 8 ? g.m_tiles : 8;
   g.group_n = g.n_tiles;
   const int total = g.m_tiles * g.n_tiles * g.nz;
-  const int nchunks = (total + CH - 1) / CH;
-  const int x = b & 7, per = G >> 3;
-  for (int j = b >> 3;; j += per) {
-    const int c = x + 8 * (j / CH);
-    if (c >= nchunks) break;
-    const int t = c * CH + j % CH;
-    if (t >= total) continue;
-    int mt, nt, z;
-    gemm_tile_coords(g, t, mt, nt, z);
-    const int fm = C.rt_fm[mt], r0 = 32 * C.rt_u0[mt];
-    g.tile_flops = 2ull * (32 * fm) * (32 * FN) * (unsigned long long)g.K * mult;
-    if constexpr (P == KALDO_FP64) {
-      gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
-    } else {
-      if (fm == 4) gemm_tile<P, 4, FN, Epi>(g, e, mt, nt, z, lds, r0);
-      else if (fm == 3) gemm_tile<P, 3, FN, Epi>(g, e, mt, nt, z, lds, r0);
-      else gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+  // fewer tiles per chunk when the phase has few: every workgroup gets some
+  int CH = total / (4 * G);
+  CH = CH < 1 ? 1 : (CH > 8 ? 8 : CH);
+  claimed(ctr, base, (total + CH - 1) / CH, G, [&](long long c) {
+    const int t1 = (int)(c * CH + CH < total ? c * CH + CH : total);
+    for (int t = (int)(c * CH); t < t1; ++t) {
+      int mt, nt, z;
+      gemm_tile_coords(g, t, mt, nt, z);
+      const int fm = C.rt_fm[mt], r0 = 32 * C.rt_u0[mt];
+      g.tile_flops = 2ull * (32 * fm) * (32 * FN) * (unsigned long long)g.K * mult;
+      if constexpr (P == KALDO_FP64) {
+        gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+      } else {
+        if (fm == 4) gemm_tile<P, 4, FN, Epi>(g, e, mt, nt, z, lds, r0);
+        else if (fm == 3) gemm_tile<P, 3, FN, Epi>(g, e, mt, nt, z, lds, r0);
+        else gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  });
 }
 
 // Columns of the persistent kernel's GEMM tiles: 32 FN = 128.
@@ -870,6 +945,7 @@ struct BatchStages {
   char* lds;
   int b, G;
   long long gtid, gthreads;
+  int lds_bytes;
 
   // K padding of the crystal's Y layout in the shared pool (never written by
   // GEMM 1, read as zeros by GEMM 2)
@@ -885,23 +961,49 @@ struct BatchStages {
       if constexpr (Operand<P>::split == 2) static_cast<T*>(C.Yl)[o] = T{};
     }
   }
-  // step A of a new first-mode point
-  __device__ void step_a(const BatchRound& R) const {
+  // step A of a new first-mode point, in claimed chunks
+  __device__ void step_a(const BatchRound& R, unsigned long long& base) const {
     const CrystalPlan& C = plans[R.c];
     const long long cnt = (long long)C.n * C.ng * 9;
-    for (long long i = gtid; i < cnt; i += gthreads)
-      cr_zg_elem<RZ>(static_cast<cplx<RZ>*>(C.Z), static_cast<const cplx<double>*>(C.E),
-                     static_cast<const int2*>(C.cgb), static_cast<const int*>(C.bi), static_cast<const int*>(C.bR2),
-                     static_cast<const double*>(C.bval), C.n, C.ng, C.G0, C.G1, C.G2, R.k, i);
+    const long long CH = stage_chunk(cnt, G);
+    claimed(&gs->claims[1], base, (cnt + CH - 1) / CH, G, [&](long long c) {
+      const long long e = c * CH + CH < cnt ? c * CH + CH : cnt;
+      for (long long i = c * CH + threadIdx.x; i < e; i += blockDim.x)
+        cr_zg_elem<RZ>(static_cast<cplx<RZ>*>(C.Z), static_cast<const cplx<double>*>(C.E),
+                       static_cast<const int2*>(C.cgb), static_cast<const int*>(C.bi),
+                       static_cast<const int*>(C.bR2), static_cast<const double*>(C.bval), C.n, C.ng, C.G0, C.G1,
+                       C.G2, R.k, i);
+    });
   }
-  __device__ void step_b(const BatchRound& R) const {
+  // step B of a round, in claimed chunks; the phases of as many partners as
+  // fit (a multiple of 8) are staged in LDS per pass, in the compute precision
+  __device__ void step_b(const BatchRound& R, unsigned long long& base) const {
     const CrystalPlan& C = plans[R.c];
     const long long cnt = (long long)C.n * C.n * (C.ldk / 2);
-    for (long long i = gtid; i < cnt; i += gthreads)
-      cr_x_elem<P, 8, RZ>(static_cast<T*>(C.Xh), static_cast<T*>(C.Xl), static_cast<const cplx<RZ>*>(C.Z),
-                          static_cast<const cplx<double>*>(C.PH), static_cast<const int*>(C.cg_delta),
-                          static_cast<const int*>(C.cg_order), static_cast<const int4*>(C.cpair),
-                          static_cast<const int*>(C.pairmap), C.n, C.N, C.nk, C.ng, C.ldk, R.p0, R.cnt, i);
+    const long long CH = stage_chunk(cnt, G);
+    const int nd = C.nd;
+    int ZC = (int)(lds_bytes / ((long long)nd * sizeof(cplx<RZ>))) & ~7;
+    ZC = ZC < ((R.cnt + 7) & ~7) ? ZC : ((R.cnt + 7) & ~7);
+    cplx<RZ>* phs = reinterpret_cast<cplx<RZ>*>(lds);
+    const cplx<double>* PH = static_cast<const cplx<double>*>(C.PH);
+    claimed(&gs->claims[0], base, (cnt + CH - 1) / CH, G, [&](long long c) {
+      const long long e = c * CH + CH < cnt ? c * CH + CH : cnt;
+      for (int zc = 0; zc < R.cnt; zc += ZC) {
+        const int zn = R.cnt - zc < ZC ? R.cnt - zc : ZC;
+        for (int i = threadIdx.x; i < nd * zn; i += blockDim.x) {
+          const int d = i / zn, u = i - d * zn;
+          const cplx<double> v = PH[(size_t)d * C.nk + R.p0 + zc + u];
+          phs[d * ZC + u] = {(RZ)v.re, (RZ)v.im};
+        }
+        __syncthreads();
+        for (long long i = c * CH + threadIdx.x; i < e; i += blockDim.x)
+          cr_x_elem_lds<P, 8, RZ>(static_cast<T*>(C.Xh), static_cast<T*>(C.Xl), static_cast<const cplx<RZ>*>(C.Z),
+                                  phs, ZC, static_cast<const int*>(C.cg_delta), static_cast<const int*>(C.cg_order),
+                                  static_cast<const int4*>(C.cpair), static_cast<const int*>(C.pairmap), C.n, C.N,
+                                  C.ng, C.ldk, zc, zn, i);
+        __syncthreads();
+      }
+    });
   }
   __device__ GemmOps gemm1_ops(const BatchRound& R) const {
     const CrystalPlan& C = plans[R.c];
@@ -922,14 +1024,14 @@ struct BatchStages {
     g.tally = &gs->flops;
     return g;
   }
-  __device__ void gemm1(const BatchRound& R) const {
+  __device__ void gemm1(const BatchRound& R, unsigned long long& base) const {
     const CrystalPlan& C = plans[R.c];
     const long long nn = (long long)C.n * C.n;
     GemmOps g = gemm1_ops(R);
     const E1 e{static_cast<T*>(C.Yh), static_cast<T*>(C.Yl), nn * C.ldk, nn, C.n, C.ldk};
-    gemm_persistent<P, FN>(g, e, lds, b, G, C);
+    gemm_persistent<P, FN>(g, e, lds, G, C, &gs->claims[3], base);
   }
-  __device__ void gemm2(const BatchRound& R) const {
+  __device__ void gemm2(const BatchRound& R, unsigned long long& base) const {
     const CrystalPlan& C = plans[R.c];
     const long long nn = (long long)C.n * C.n;
     GemmOps g = gemm1_ops(R);
@@ -940,15 +1042,15 @@ struct BatchStages {
     g.a_map = nullptr;
     const E2 e{C.OM, C.IW, C.OCC, C.kmap + (size_t)R.k * C.nk + R.p0, C.partial, nn, C.n, C.nk, C.nT, R.k, R.p0,
                C.m_tiles2, C.rs};
-    gemm_persistent<P, FN>(g, e, lds, b, G, C);
+    gemm_persistent<P, FN>(g, e, lds, G, C, &gs->claims[4], base);
   }
   // the partial sums of the round into gacc (first round of k: overwrite),
   // after the last round of k the raw linewidths of k and -k
-  __device__ void collect(const BatchRound& R) const {
+  __device__ void collect(const BatchRound& R, unsigned long long& base) const {
     const CrystalPlan& C = plans[R.c];
     const int n = C.n, nk = C.nk;
-    for (int st = b; st < n * C.nT; st += G) {
-      const int s = st % n, t = st / n;
+    claimed(&gs->claims[2], base, (long long)n * C.nT, G, [&](long long st) {
+      const int s = (int)(st % n), t = (int)(st / n);
       const double v = cr_collect_sum(C.partial, n, C.nT, C.m_tiles2, R.cnt, s, t, reinterpret_cast<double*>(lds));
       if (threadIdx.x == 0) {
         double* ga = C.gacc + (size_t)t * n + s;
@@ -961,7 +1063,7 @@ struct BatchStages {
         }
       }
       __syncthreads();
-    }
+    });
   }
 };
 
@@ -973,18 +1075,27 @@ struct BatchStages {
 // later; the collection reads the partial sums that GEMM 2 writes one phase
 // later; step B writes X, read by GEMM 1 one phase later), so two grid
 // barriers per round suffice.
+// LDS bytes of the persistent kernel: the larger GEMM stage (row tiles of up
+// to 128 rows), at least 2 KB for the collection's reduction
+template <int P, int NT>
+struct BatchLds {
+  using S = BatchStages<P, NT>;
+  static constexpr int FN = BatchShape<P>::FN;
+  static constexpr int L1 = GemmLds<P, 4, FN, typename S::E1>::bytes, L2 = GemmLds<P, 4, FN, typename S::E2>::bytes;
+  static constexpr int LM = L1 > L2 ? L1 : L2;
+  static constexpr int bytes = LM > 2048 ? LM : 2048;
+};
+
 template <int P, int NT>
 __global__ void __launch_bounds__(256)
     k_batch_persistent(const CrystalPlan* __restrict__ plans, int nplans, const BatchRound* __restrict__ rounds,
                        int nrounds, GridSync* __restrict__ gs, unsigned long long* __restrict__ rtimes) {
   using S = BatchStages<P, NT>;
   constexpr int FN = BatchShape<P>::FN;
-  constexpr int L1 = GemmLds<P, 4, FN, typename S::E1>::bytes, L2 = GemmLds<P, 4, FN, typename S::E2>::bytes;
-  constexpr int LM = L1 > L2 ? L1 : L2;
-  constexpr int LB = LM > 2048 ? LM : 2048;
+  constexpr int LB = BatchLds<P, NT>::bytes;
   __shared__ __attribute__((aligned(16))) char lds[LB];
   const int G = (int)gridDim.x, b = (int)blockIdx.x;
-  const S st{plans, rounds, gs, lds, b, G, (long long)b * 256 + threadIdx.x, (long long)G * 256};
+  const S st{plans, rounds, gs, lds, b, G, (long long)b * 256 + threadIdx.x, (long long)G * 256, LB};
   // points outside a crystal's k range keep gamma = 0
   for (int c = 0; c < nplans; ++c) {
     const CrystalPlan& C = plans[c];
@@ -995,37 +1106,39 @@ __global__ void __launch_bounds__(256)
   }
   unsigned long long t0 = wall_clock64();
   if (b == 0 && threadIdx.x == 0) gs->t_begin = t0;
+  // claim counters' bases: step B, step A, the collection, GEMM 1, GEMM 2
+  unsigned long long base_b = 0, base_a = 0, base_c = 0, base_g1 = 0, base_g2 = 0;
   if (nrounds > 0) {
-    st.step_a(rounds[0]);
+    st.step_a(rounds[0], base_a);
     if (grid_barrier(gs, G)) return;
     phase_mark(gs, b, t0, 0);
-    st.step_b(rounds[0]);
+    st.step_b(rounds[0], base_b);
     if (grid_barrier(gs, G)) return;
     phase_mark(gs, b, t0, 1);
   }
   for (int r = 0; r < nrounds; ++r) {
     const BatchRound R = rounds[r];
     // phase X
-    st.gemm1(R);
+    st.gemm1(R, base_g1);
     phase_mark(gs, b, t0, 2);
     if (R.first_crystal) st.zero_pad(R);
-    if (r + 1 < nrounds && rounds[r + 1].first) st.step_a(rounds[r + 1]);
-    if (r > 0) st.collect(rounds[r - 1]);
+    if (r + 1 < nrounds && rounds[r + 1].first) st.step_a(rounds[r + 1], base_a);
+    if (r > 0) st.collect(rounds[r - 1], base_c);
     phase_mark(gs, b, t0, 0);
     if (grid_barrier(gs, G)) return;
     phase_mark(gs, b, t0, 4);
     // phase Y
-    st.gemm2(R);
+    st.gemm2(R, base_g2);
     phase_mark(gs, b, t0, 3);
-    if (r + 1 < nrounds) st.step_b(rounds[r + 1]);
+    if (r + 1 < nrounds) st.step_b(rounds[r + 1], base_b);
     phase_mark(gs, b, t0, 1);
     if (grid_barrier(gs, G)) return;
-    phase_mark(gs, b, t0, 4);
+    phase_mark(gs, b, t0, 6);
     // block 0's clock at the end of each round (per-crystal times for the profile)
     if (b == 0 && threadIdx.x == 0) rtimes[r] = t0;
   }
   if (nrounds > 0) {
-    st.collect(rounds[nrounds - 1]);
+    st.collect(rounds[nrounds - 1], base_c);
     if (grid_barrier(gs, G)) return;
   }
   // degenerate-set averages of every crystal
@@ -1108,7 +1221,14 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   // KALDO_TUNE_FIXED keeps the fixed tile shape of eager calls (variant 0), so
   // that batch and eager results agree bit for bit
   const bool fixed = parent->tuning == KALDO_TUNE_FIXED;
+  // step B stages the phases of 8 partners for every cell offset Delta in LDS
+  const int lds_bytes = precision == KALDO_FP64 ? BatchLds<KALDO_FP64, 1>::bytes
+                        : precision == KALDO_FP32 ? BatchLds<KALDO_FP32, 1>::bytes
+                                                  : BatchLds<KALDO_BF16X3, 1>::bytes;
+  const size_t ph_bytes = precision == KALDO_FP64 ? 16 : 8;
   for (CrystalPlan& cp : sorted) {
+    if ((size_t)cp.nd * 8 * ph_bytes > (size_t)lds_bytes)
+      return fail(parent, KALDO_EINVAL, "persistent batch kernel: too many fc3 cell offsets for its LDS");
     const std::vector<int> fms = batch_row_tiles(precision, cp.mrows, fixed);
     // the partial sums were sized for tiles of 64 rows
     if ((int)fms.size() > 32 || (int)fms.size() > (cp.mrows + 63) / 64)
@@ -1197,13 +1317,16 @@ kaldo_status batch_persistent_check(kaldo_ctx parent) {
     parent->prof_dense += parent->batch_dense;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, parent->device) == hipSuccess && khz > 0) {
-      static const char* names[6] = {"batch_a_collect", "batch_step_b", "batch_gemm1", "batch_gemm2",
-                                     "batch_barrier_wait", "batch_set_average"};
-      for (int p = 0; p < 6; ++p) {
+      static const char* names[7] = {"batch_a_collect", "batch_step_b", "batch_gemm1", "batch_gemm2",
+                                     "batch_wait_gemm1_phase", "batch_set_average", "batch_wait_gemm2_phase"};
+      for (int p = 0; p < 7; ++p) {
         auto& e = parent->prof_tab[names[p]];
         e.total_ms += (double)h.phase[p] / (double)khz;
         e.launches += 1;
       }
+      auto& w = parent->prof_tab["batch_barrier_wait"];
+      w.total_ms += (double)(h.phase[4] + h.phase[6]) / (double)khz;
+      w.launches += 1;
       // per crystal: the clock between the ends of consecutive rounds, summed
       // over the crystal's rounds ("batch_crystal_<handle>")
       const size_t nr = parent->batch_round_handle.size();

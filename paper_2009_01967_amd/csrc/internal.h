@@ -127,7 +127,7 @@ namespace kaldo {
 // crystal from them).  Plain data, copied to the device as is.
 struct CrystalPlan {
   int valid, precision;
-  int n, N, nk, ng, nT, ldk, mrows, zb, G0, G1, G2, klo, khi;
+  int n, N, nk, ng, nd, nT, ldk, mrows, zb, G0, G1, G2, klo, khi;
   int m_tiles2;     // row tiles of both GEMMs in the persistent kernel
   unsigned char rt_fm[32];  // row tile i: 32 rt_fm[i] rows from row 32 rt_u0[i]
   unsigned char rt_u0[32];
