@@ -847,8 +847,9 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned nblocks) {
 // The tiles of one GEMM phase over the persistent grid, in chunks of up to 8
 // consecutive logical tiles (a chunk of 8 holds the row tiles of two or three
 // column panels, which share their operand panels in L2; phases with fewer
-// than 4 G tiles get smaller chunks) that the workgroups claim one at a time
-// (claimed(): a workgroup that finished early takes more).  Row tile mt has 32 rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of
+// than 4 G tiles get smaller chunks, and the last 2 G tiles go singly) that
+// the workgroups claim one at a time (claimed(): a workgroup that finished
+// early takes more).  Row tile mt has 32 rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of
 // several heights cover the 2n realified rows with little padding).
 template <int P, int FN, class Epi>
 __device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int G, const CrystalPlan& C,
@@ -859,12 +860,17 @@ __device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* 
   g.group_m = g.m_tiles < 8 ? g.m_tiles : 8;
   g.group_n = g.n_tiles;
   const int total = g.m_tiles * g.n_tiles * g.nz;
-  // fewer tiles per chunk when the phase has few: every workgroup gets some
+  // fewer tiles per chunk when the phase has few: every workgroup gets some;
+  // the last 2 G tiles (at most) go one at a time, so that the phase ends
+  // within about one tile of its last workgroup
   int CH = total / (4 * G);
   CH = CH < 1 ? 1 : (CH > 8 ? 8 : CH);
-  claimed(ctr, base, (total + CH - 1) / CH, G, [&](long long c) {
-    const int t1 = (int)(c * CH + CH < total ? c * CH + CH : total);
-    for (int t = (int)(c * CH); t < t1; ++t) {
+  const int nbig = (total - (total < 2 * G ? total : 2 * G)) / CH;
+  const int single0 = nbig * CH;
+  claimed(ctr, base, nbig + (total - single0), G, [&](long long c) {
+    const int t0 = c < nbig ? (int)c * CH : single0 + (int)(c - nbig);
+    const int t1 = c < nbig ? t0 + CH : t0 + 1;
+    for (int t = t0; t < t1; ++t) {
       int mt, nt, z;
       gemm_tile_coords(g, t, mt, nt, z);
       const int fm = C.rt_fm[mt], r0 = 32 * C.rt_u0[mt];
