@@ -46,7 +46,7 @@ MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 # (--no-cpu --no-mfma --no-c2), each scaled by what the counter reads for a
 # plain 1 GiB device copy (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0).  Set to None when that kernel changes.
-HEADLINE_TRAFFIC = None
+HEADLINE_TRAFFIC = {"fetch_bytes": 140790077842 * 1024 * 2.0, "write_bytes": 85572191095 * 1024 * 1.0}
 
 
 def log(*a):
@@ -458,6 +458,27 @@ def run_batch_headline(steps, warmup, div=64, share=1):
     ms64 = f0.elapsed_time(f1)
     ctx.close()
     log(f"batch fp64 (first ceil(N_k/{div}) points): {ms64:.1f} ms per launch")
+    # ---- BF16X3 on the same points
+    ctx = kaldo.Context(0, stream.cuda_stream)
+    for i, (c, m) in enumerate(zip(crystals, sub)):
+        ctx.batch_add(c)
+        ctx.batch_set_k_range(i, 0, m)
+    gbf = [np.zeros((len(T), c.n_k, c.n_modes)) for c in crystals]
+    kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_BF16X3, gbf))
+    torch.cuda.synchronize()
+    f0.record(stream)
+    kaldo._check(ctx.h, kaldo.kaldo_batch_run(ctx.h, T, sigma, kaldo.KALDO_QUANTUM, kaldo.KALDO_BF16X3, None))
+    f1.record(stream)
+    torch.cuda.synchronize()
+    msbf = f0.elapsed_time(f1)
+    ctx.close()
+    log(f"batch bf16x3 (first ceil(N_k/{div}) points): {msbf:.1f} ms per launch")
+    errbf = 0.0
+    for a, b, m in zip(gbf, g64, sub):
+        x, y = a[:, :m], b[:, :m]
+        on = y > 0
+        floor = 1e-6 * np.abs(y).max()
+        errbf = max(errbf, float(np.max(np.abs(x[on] - y[on]) / np.maximum(y[on], floor))))
     err = 0.0
     for a, b, m in zip(g32, g64, sub):
         x, y = a[:, :m], b[:, :m]
@@ -491,6 +512,11 @@ def run_batch_headline(steps, warmup, div=64, share=1):
                                                     f"{sum(c.n_k for c in crystals)}",
                                "gemm_tflops_algorithmic": fc64 / (ms64 * 1e-3) / 1e12,
                                "frac_of_fp64_mfma_peak": fc64 / (ms64 * 1e-3) / FP64_MFMA_PEAK},
+                bf16x3={"ms_per_launch": msbf, "value": lw64 / (msbf * 1e-3), "unit": "linewidths/s",
+                        "first_mode_points": f"ceil(N_k/{div}) per crystal, the FP64 leg's",
+                        "gemm_tflops_algorithmic": fc64 / (msbf * 1e-3) / 1e12,
+                        "frac_of_bf16x3_rate": fc64 / (msbf * 1e-3) / (BF16_MFMA_PEAK / 3.0),
+                        "gamma_rel_err_vs_fp64": errbf, "speedup_vs_fp64": ms64 / msbf},
                 err_fp32_vs_fp64=err)
 
 
@@ -817,6 +843,7 @@ def main():
             "per_crystal": b["per_crystal"],
         },
         "fp64": b["fp64"],
+        "bf16x3": b["bf16x3"],
         "speedup_fp32_vs_fp64_per_flop": (b["fc"] / b["ms"]) / (b["fp64"]["gemm_tflops_algorithmic"] * 1e9),
         "gamma_rel_err_fp32_vs_fp64": b["err_fp32_vs_fp64"],
     }
