@@ -251,7 +251,21 @@ static kaldo_status load_fc2(kaldo_ctx ctx, const kaldo_fc2* f) {
     if (pair[2 * p + 1] == 0) pair[2 * p] = (int)q;
     pair[2 * p + 1] = (int)q + 1;
   }
+  // the coupled atom pairs row by row (i, j, first block, end): the sparse
+  // displacement Hessian of the QHGK velocities has one 3 x 3 block per pair
+  std::vector<int> rows((size_t)N + 1, 0), plist;
+  for (int64_t q = 0; q < nb;) {
+    int64_t e = q;
+    while (e < nb && bi[e] == bi[q] && bj[e] == bj[q]) ++e;
+    plist.insert(plist.end(), {bi[q], bj[q], (int)q, (int)e});
+    rows[(size_t)bi[q] + 1] += 1;
+    q = e;
+  }
+  for (int i = 0; i < N; ++i) rows[(size_t)i + 1] += rows[i];
   kaldo_status st;
+  if ((st = upload(ctx, ctx->d_fc2_rows, rows.data(), rows.size())) != KALDO_OK) return st;
+  if ((st = upload(ctx, ctx->d_fc2_plist, plist.data(), plist.size())) != KALDO_OK) return st;
+  ctx->n_fc2_pairs = (int)(plist.size() / 4);
   if ((st = upload(ctx, ctx->d_fc2_pair, pair.data(), pair.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, ctx->d_fc2_R, R.data(), R.size())) != KALDO_OK) return st;
   if ((st = upload(ctx, ctx->d_fc2_val, val.data(), val.size())) != KALDO_OK) return st;

@@ -192,6 +192,9 @@ struct kaldo_ctx_s {
   bool have_fc2 = false;
   int64_t nb2 = 0;
   kaldo::DevBuf d_fc2_pair;          // int2 [N*N] -> [start, end)
+  kaldo::DevBuf d_fc2_rows;          // int [N + 1]: the coupled pairs of atom i are [rows[i], rows[i + 1])
+  kaldo::DevBuf d_fc2_plist;         // int4 per coupled pair: i, j, first block, end block
+  int n_fc2_pairs = 0;
   kaldo::DevBuf d_fc2_R;             // int [nb][3]
   kaldo::DevBuf d_fc2_val;           // double [nb][9]
   kaldo::DevBuf d_fc2_i, d_fc2_j;    // int [nb]

@@ -2,12 +2,12 @@
 //   RTA  (paper eq. RTA):   kappa_ab = 1/(N_k V) sum_mu c_mu tau_mu v_mu,a v_mu,b, tau = 1/(2 gamma)
 //   QHGK (Sec. II.C):       kappa_ab = 1/V sum_{mu mu'} c_{mu mu'} v_{mu mu' a} v_{mu mu' b} tau_{mu mu'}
 // All accumulation is FP64 with fixed-order (deterministic) reductions.
-#include <rocblas/rocblas.h>
-
 #include <mutex>
 
 #include "common.h"
+#include "gemm.h"
 #include "internal.h"
+#include "mfma.h"
 
 namespace kaldo {
 
@@ -170,29 +170,6 @@ kaldo_status run_kappa_rta_noalloc(kaldo_ctx ctx, double* kappa_out) {
 // most (first-mode block, u slice) partial sums per temperature of k_qhgk_pairs
 constexpr int kQhgkMaxSlices = 2048;
 
-// M_a (column major): M_a[a][b] = sum_R (x_i - x_j - R.cell)_a fc2 / sqrt(m_i m_j), ps^-2 A
-__global__ void k_displacement_hessian(double* __restrict__ M, const int2* __restrict__ pair,
-                                       const int* __restrict__ R, const double* __restrict__ val,
-                                       const double* __restrict__ mass, const double* __restrict__ pos,
-                                       const double* __restrict__ cell, int N) {
-  const int n = 3 * N;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n * n) return;
-  const int a = (int)(idx % n), b = (int)(idx / n);
-  const int i = a / 3, al = a % 3, j = b / 3, be = b % 3;
-  const int2 pr = pair[i * N + j];
-  double acc[3] = {0, 0, 0};
-  for (int q = pr.x; q < pr.y; ++q) {
-    const double v = val[9 * q + 3 * al + be];
-    for (int d = 0; d < 3; ++d) {
-      const double Rc = R[3 * q] * cell[d] + R[3 * q + 1] * cell[3 + d] + R[3 * q + 2] * cell[6 + d];
-      acc[d] += (pos[3 * i + d] - pos[3 * j + d] - Rc) * v;
-    }
-  }
-  const double scale = kEvUnit / sqrt(mass[i] * mass[j]);
-  for (int d = 0; d < 3; ++d) M[(size_t)d * n * n + (size_t)b * n + a] = acc[d] * scale;
-}
-
 // The second modes u that a block of first modes s0 <= s < s1 pairs with
 // under an energy threshold: frequencies ascend at Gamma, so every u with
 // |w_s - w_u| <= thr lies in [lo, hi), found by bisection with the bounds
@@ -344,33 +321,146 @@ __global__ void k_diffusivity_reduce(double* __restrict__ D, const double* __res
   D[i] = 1e-2 * v / (hi - lo);
 }
 
-// V_d = E^T M_d E for d = 0..2 (column major, n x n each) in d_scratch2
+// ---- generalised velocity V_d = E^T M_d E at Gamma ----------------------------------
+// M_d[a][b] = sum over the fc2 blocks of the pair (i, j) of
+// (x_i - x_j - R.cell)_d fc2[alpha][beta] / sqrt(m_i m_j) (a = 3 i + alpha,
+// b = 3 j + beta) has one 3 x 3 block per coupled atom pair: it is applied as
+// a sparse product (k_vel_spmm), and the dense E^T (M_d E) runs on the FP64
+// matrix cores (the GEMM core of the projection with a plain store).
+
+// C[p][d][alpha][beta]: the three displacement-weighted blocks of coupled pair p
+__global__ void k_vel_coeffs(double* __restrict__ C, const int4* __restrict__ plist, const int* __restrict__ R,
+                             const double* __restrict__ val, const double* __restrict__ mass,
+                             const double* __restrict__ pos, const double* __restrict__ cell, int npairs) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 9LL * npairs) return;
+  const int p = (int)(idx / 9), ab = (int)(idx % 9);
+  const int4 pr = plist[p];
+  const int i = pr.x, j = pr.y;
+  double acc[3] = {0, 0, 0};
+  for (int q = pr.z; q < pr.w; ++q) {
+    const double v = val[9 * q + ab];
+    for (int d = 0; d < 3; ++d) {
+      const double Rc = R[3 * q] * cell[d] + R[3 * q + 1] * cell[3 + d] + R[3 * q + 2] * cell[6 + d];
+      acc[d] += (pos[3 * i + d] - pos[3 * j + d] - Rc) * v;
+    }
+  }
+  const double scale = kEvUnit / sqrt(mass[i] * mass[j]);
+  for (int d = 0; d < 3; ++d) C[(size_t)p * 27 + d * 9 + ab] = acc[d] * scale;
+}
+
+// XT_d[u][a] = (M_d E)[a][u] for d = 0..2, rows of length ld (zeros for a >= n):
+// one block per eigenvector u, staged in LDS when it fits, one thread per row a.
+template <bool LDS>
+__global__ void __launch_bounds__(256) k_vel_spmm(double* __restrict__ XT, const double* __restrict__ E,
+                                                  const double* __restrict__ C, const int* __restrict__ rows,
+                                                  const int4* __restrict__ plist, int n, int ld) {
+  extern __shared__ double ecol[];
+  const int u = blockIdx.x;
+  const double* eu = E + (size_t)u * n;
+  if constexpr (LDS) {
+    for (int b = threadIdx.x; b < n; b += blockDim.x) ecol[b] = eu[b];
+    __syncthreads();
+  }
+  const double* ev = LDS ? ecol : eu;
+  const size_t plane = (size_t)n * ld;
+  for (int a = threadIdx.x; a < ld; a += blockDim.x) {
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (a < n) {
+      const int i = a / 3, al = a % 3;
+      for (int p = rows[i]; p < rows[i + 1]; ++p) {
+        const int j = plist[p].y;
+        const double* c = C + (size_t)p * 27 + 3 * al;
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+          const double e = ev[3 * j + be];
+          x0 += c[be] * e;
+          x1 += c[9 + be] * e;
+          x2 += c[18 + be] * e;
+        }
+      }
+    }
+    const size_t o = (size_t)u * ld + a;
+    XT[o] = x0;
+    XT[plane + o] = x1;
+    XT[2 * plane + o] = x2;
+  }
+}
+
+// E rows of length ld (zeros for a >= n): the B operand of the velocity GEMM
+__global__ void k_vel_pad(double* __restrict__ Ep, const double* __restrict__ E, int n, int ld) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * ld) return;
+  const int s = (int)(idx / ld), a = (int)(idx % ld);
+  Ep[idx] = a < n ? E[(size_t)s * n + a] : 0.0;
+}
+
+// GEMM epilogue: the FP64 tile stored as out[row * ldc + col] (row < m, col < c)
+struct EpiStoreV {
+  double* out;
+  long long ldc;
+  int m, c;
+  template <int P, int FM, int FN>
+  __device__ __forceinline__ void apply(typename Operand<P>::Acc (&acc)[FM][FN], const TileAt& at, char*) const {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int q = 0; q < FN; ++q) {
+        const int col = (int)at.c0 + 16 * q + (at.lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = at.m0 + 16 * a + acc_row<P>(at.lane, r);
+          if (row < m && col < c) out[(size_t)row * ldc + col] = acc[a][q][r];
+        }
+      }
+  }
+};
+
+// V_d = E^T M_d E for d = 0..2, column major (V_d[u * n + s] = (E^T M_d E)[s][u]),
+// in d_scratch2, computed as V_d^T[u][s] = sum_a XT_d[u][a] E[s][a]
 static kaldo_status qhgk_velocity(kaldo_ctx ctx, double** Vout, double** part_out) {
-  const int N = ctx->n_atoms, n = ctx->nm;
-  const size_t nn = (size_t)n * n;
+  const int n = ctx->nm, np = (n + 15) & ~15, npairs = ctx->n_fc2_pairs;
+  const size_t nn = (size_t)n * n, xn = (size_t)n * np;
   hipStream_t st = ctx->stream;
   // real eigenvectors: column s of d_dyn (Gamma path keeps them real)
   const double* E = ctx->d_dyn.as<double>();
-  KALDO_HIP(ctx, ctx->d_scratch2.ensure(3 * nn * sizeof(double) * 2 + kQhgkMaxSlices * 9 * KALDO_MAX_T * sizeof(double)));
-  double* M = ctx->d_scratch2.as<double>();
-  double* X = M + 3 * nn;  // X then V reuses M
-  double* part = X + 3 * nn;
+  KALDO_HIP(ctx, ctx->d_scratch2.ensure((3 * nn + 4 * xn + (size_t)npairs * 27 +
+                                         (size_t)kQhgkMaxSlices * 9 * KALDO_MAX_T) * sizeof(double)));
+  double* V = ctx->d_scratch2.as<double>();
+  double* XT = V + 3 * nn;
+  double* Ep = XT + 3 * xn;
+  double* Cp = Ep + xn;
+  double* part = Cp + (size_t)npairs * 27;
   KALDO_HIP(ctx, ctx->d_tabs.ensure(9 * sizeof(double)));
   KALDO_HIP(ctx, hipMemcpyAsync(ctx->d_tabs.p, ctx->cell, 9 * sizeof(double), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_displacement_hessian, dim3(blocks_for((long long)nn, 256)), dim3(256), 0, st, M,
-                     ctx->d_fc2_pair.as<int2>(), ctx->d_fc2_R.as<int>(), ctx->d_fc2_val.as<double>(),
-                     ctx->d_masses.as<double>(), ctx->d_positions.as<double>(), ctx->d_tabs.as<double>(), N);
+  hipLaunchKernelGGL(k_vel_coeffs, dim3(blocks_for(9LL * npairs, 256)), dim3(256), 0, st, Cp,
+                     ctx->d_fc2_plist.as<int4>(), ctx->d_fc2_R.as<int>(), ctx->d_fc2_val.as<double>(),
+                     ctx->d_masses.as<double>(), ctx->d_positions.as<double>(), ctx->d_tabs.as<double>(), npairs);
   KALDO_HIP(ctx, hipGetLastError());
-  const double one = 1.0, zero = 0.0;
+  const size_t lds = (size_t)n * sizeof(double);
+  if (lds <= 64 * 1024)
+    hipLaunchKernelGGL(k_vel_spmm<true>, dim3(n), dim3(256), lds, st, XT, E, Cp, ctx->d_fc2_rows.as<int>(),
+                       ctx->d_fc2_plist.as<int4>(), n, np);
+  else
+    hipLaunchKernelGGL(k_vel_spmm<false>, dim3(n), dim3(256), 0, st, XT, E, Cp, ctx->d_fc2_rows.as<int>(),
+                       ctx->d_fc2_plist.as<int4>(), n, np);
+  KALDO_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_vel_pad, dim3(blocks_for((long long)xn, 256)), dim3(256), 0, st, Ep, E, n, np);
+  KALDO_HIP(ctx, hipGetLastError());
   for (int d = 0; d < 3; ++d) {
-    if (rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, M + d * nn, n, E, n,
-                      &zero, X + d * nn, n) != rocblas_status_success)
-      return fail(ctx, KALDO_EDEVICE, "rocblas_dgemm failed");
-    if (rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one, E, n, X + d * nn,
-                      n, &zero, M + d * nn, n) != rocblas_status_success)
-      return fail(ctx, KALDO_EDEVICE, "rocblas_dgemm failed");
+    GemmOps g{};
+    g.a_hi = XT + d * xn;
+    g.b_hi = Ep;
+    g.lda = g.ldb = np;
+    g.K = np;
+    g.nz = 1;
+    g.m_valid = n;
+    g.c_valid = n;
+    const EpiStoreV e{V + d * nn, n, n, n};
+    gemm_launch_tile<KALDO_FP64, 2, 4>(g, e, st);
+    KALDO_HIP(ctx, hipGetLastError());
   }
-  *Vout = M;
+  *Vout = V;
   *part_out = part;
   return KALDO_OK;
 }
