@@ -47,6 +47,9 @@ MFMA_WORKLOADS = ("cage-46at-5x5x5", "sige-1000at-gamma")
 # plain 1 GiB device copy (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0).  Set to None when that kernel changes.
 HEADLINE_TRAFFIC = {"fetch_bytes": 140790077842 * 1024 * 2.0, "write_bytes": 85572191095 * 1024 * 1.0}
+# The same for the few-branch kernel k_project_small<float,6,3,true,0> on the
+# 2-atom diamond cell (--c2-only, KiB per dispatch, same scales).
+C2_TRAFFIC = {"fetch_bytes": 53591.0 * 1024 * 2.0, "write_bytes": 5115.8 * 1024 * 1.0}
 
 
 def log(*a):
@@ -690,7 +693,8 @@ def c2_section(r):
             "achieved": (f_b + f_c) / (proj32 * 1e-3) / 1e12 if proj32 else None,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": (f_b + f_c) / (proj32 * 1e-3) / FP32_VECTOR_PEAK if proj32 else None,
-            "traffic": None,
+            "traffic": C2_TRAFFIC["fetch_bytes"] + C2_TRAFFIC["write_bytes"] if C2_TRAFFIC else None,
+            "traffic_unit": "bytes per launch (HBM, calibrated FETCH_SIZE + WRITE_SIZE)",
             "intermediate_bytes": intermediate_bytes(nk, n, nd, nT, npts),
             "algorithmic_bytes": survey_algorithmic_bytes(r["c"], nT),
             "flops_per_launch": f_b + f_c,
@@ -762,6 +766,9 @@ def main():
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--no-main", action="store_true",
                     help="only the many-branch workloads (prints their JSON; for profiling and the child section)")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the few-branch diamond workload (prints its JSON section; for profiling), with "
+                         "--steps timed FP32 steps after --warmup")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -787,6 +794,11 @@ def main():
         import torch
         torch.cuda.init()
         print(json.dumps({"measured_peaks": measured_peaks()}))
+        return
+    if args.c2_only:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"fewbranch_c2": c2_section(run_c2(steps=max(args.steps, 2), warmup=max(args.warmup, 1)))}))
         return
     if args.no_main:
         print(json.dumps({"mfma_paths": [run_mfma(name, steps=2, warmup=1) for name in MFMA_WORKLOADS]}))
