@@ -851,9 +851,16 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned nblocks) {
 // the workgroups claim one at a time (claimed(): a workgroup that finished
 // early takes more).  Row tile mt has 32 rt_fm[mt] rows from row 32 rt_u0[mt] (tiles of
 // several heights cover the 2n realified rows with little padding).
+// FP32 tiles take 128-byte K chunks (gemm_tile's WD): the operands stream
+// from HBM, and a 64-byte chunk's MFMAs were too short to cover the next
+// chunk's loads.
+template <int P>
+struct BatchWide : std::integral_constant<bool, P == KALDO_FP32> {};
+
 template <int P, int FN, class Epi>
 __device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* lds, int G, const CrystalPlan& C,
                                                 unsigned long long* ctr, unsigned long long& base) {
+  constexpr bool WD = BatchWide<P>::value;
   constexpr unsigned long long mult = P == KALDO_BF16X3 ? 3 : 1;
   g.m_tiles = C.m_tiles2;
   g.n_tiles = (int)((g.c_valid + 32 * FN - 1) / (32 * FN));
@@ -878,9 +885,9 @@ __device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* 
       if constexpr (P == KALDO_FP64) {
         gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
       } else {
-        if (fm == 4) gemm_tile<P, 4, FN, Epi>(g, e, mt, nt, z, lds, r0);
-        else if (fm == 3) gemm_tile<P, 3, FN, Epi>(g, e, mt, nt, z, lds, r0);
-        else gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
+        if (fm == 4) gemm_tile<P, 4, FN, Epi, false, false, WD>(g, e, mt, nt, z, lds, r0);
+        else if (fm == 3) gemm_tile<P, 3, FN, Epi, false, false, WD>(g, e, mt, nt, z, lds, r0);
+        else gemm_tile<P, 2, FN, Epi, false, false, WD>(g, e, mt, nt, z, lds, r0);
       }
       __syncthreads();
     }
@@ -1087,7 +1094,9 @@ template <int P, int NT>
 struct BatchLds {
   using S = BatchStages<P, NT>;
   static constexpr int FN = BatchShape<P>::FN;
-  static constexpr int L1 = GemmLds<P, 4, FN, typename S::E1>::bytes, L2 = GemmLds<P, 4, FN, typename S::E2>::bytes;
+  static constexpr bool WD = BatchWide<P>::value;
+  static constexpr int L1 = GemmLds<P, 4, FN, typename S::E1, false, false, WD>::bytes,
+                       L2 = GemmLds<P, 4, FN, typename S::E2, false, false, WD>::bytes;
   static constexpr int LM = L1 > L2 ? L1 : L2;
   static constexpr int bytes = LM > 2048 ? LM : 2048;
 };

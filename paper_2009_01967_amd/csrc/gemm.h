@@ -126,13 +126,14 @@ __device__ __forceinline__ int lds_off(int row, int slot) {
   else return row * (CB + 16) + slot * 16;
 }
 
-// LDS bytes of one block tile of k_gemm<P, FM, FN, Epi, BD, WC>.
-template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
+// LDS bytes of one block tile of k_gemm<P, FM, FN, Epi, BD, WC> (and of
+// gemm_tile with wide double-buffered chunks, WD).
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false, bool WD = false>
 struct GemmLds {
   using T = typename Operand<P>::T;
   static constexpr int S = Operand<P>::split;
   static constexpr int BM = 32 * FM, BN = 32 * FN;
-  static constexpr int CB = WC ? 128 : GemmChunk<P>::CB;
+  static constexpr int CB = WC || WD ? 128 : GemmChunk<P>::CB;
   static constexpr int NBUF = WC ? 1 : 2;
   static constexpr int RB = CB == 64 ? 64 : CB + 16;
   static constexpr int ROWS = BM + (BD ? 0 : BN);
@@ -174,7 +175,12 @@ __device__ __forceinline__ void gemm_tile_coords(const GemmOps& g, int tile, int
 // buffer, refilled between two barriers from registers loaded during the
 // chunk's MFMAs.  Twice the MFMA work per barrier in the same LDS space as the
 // double-buffered 64-byte chunks; faster on long contractions.
-template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false>
+// WD (FP32 only, K a multiple of 16): 128-byte chunks (32 k) in two LDS
+// buffers, so that the next chunk's loads have twice the MFMA time of a
+// 64-byte chunk to arrive; a last chunk of 16 k runs its first half alone.
+// The MFMAs run in the same order as with 64-byte chunks (bitwise the same
+// result).
+template <int P, int FM, int FN, class Epi, bool BD = false, bool WC = false, bool WD = false>
 __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int mt, int nt, int z, char* lds,
                                           int rbase = -1) {
   using T = typename Operand<P>::T;
@@ -182,8 +188,9 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   constexpr int S = Operand<P>::split;
   static_assert(!BD || P == KALDO_BF16X3, "direct B fragments are a BF16X3 variant");
   static_assert(!WC || (P == KALDO_BF16X3 && !BD), "wide chunks are a BF16X3 variant with B in LDS");
+  static_assert(!WD || P == KALDO_FP32, "wide double-buffered chunks are an FP32 variant");
   constexpr int BM = 32 * FM, BN = 32 * FN;
-  constexpr int CB = WC ? 128 : GemmChunk<P>::CB;
+  constexpr int CB = WC || WD ? 128 : GemmChunk<P>::CB;
   constexpr int KCH = CB / (int)sizeof(T);    // elements per row chunk
   constexpr int RB = CB == 64 ? 64 : CB + 16; // LDS bytes per tile row (see lds_off)
   constexpr int SLOTS = CB / 16;              // 16-byte slots per row chunk
@@ -219,6 +226,14 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   // chunk, so a chunk start and a slot offset inside the chunk add without carry
   constexpr int BKL = BlockBytes<Epi>::value / (int)sizeof(T);
   static_assert(BKL == 0 || (KCH % BKL == 0 && BKL % EPT == 0), "B blocks must tile the chunk");
+  static_assert(!WD || BKL == 0, "wide double-buffered chunks read K-contiguous B rows");
+  // WD: a half last chunk (K = 16 mod 32) loads its second half's slots from
+  // the first half again (inside the row; those LDS slots are never read)
+  const int kshift = WD ? (slot * EPT >= 16 ? 16 : 0) : 0;
+  const auto kin = [&](int k0) -> int {
+    if constexpr (WD) return k0 + slot * EPT < g.K ? k0 : k0 - kshift;
+    else return k0;
+  };
   const auto bk = [&](int k0) -> long long {
     if constexpr (BKL > 0) return (long long)(k0 / BKL) * g.b_kb + k0 % BKL;
     else return (long long)k0;
@@ -254,9 +269,9 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
     static_for<NA + NB>([&](auto uc) __attribute__((always_inline)) {                                                 \
       constexpr int u_ = decltype(uc)::value;                                          \
       if constexpr (u_ < NA)                                                           \
-        rg[s_][u_] = *reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + (K0));        \
+        rg[s_][u_] = *reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + kin(K0));     \
       else                                                                             \
-        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + bk(K0));  \
+        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + bk(kin(K0))); \
     });                                                                                \
   });
 #define KALDO_SSTORE(BUFI)                                                             \
@@ -299,7 +314,9 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
         *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + bk(K0));                                       \
   }
 
-  const int nchunk = g.K / KCH;
+  // WD: chunks of 32 k, the last one of 16 k when K = 16 mod 32
+  const int nchunk = WD ? (g.K + KCH - 1) / KCH : g.K / KCH;
+  const bool half_last = WD && (g.K % KCH) != 0;
   {
     u32x4 rg[S][NA + NB];
     KALDO_GLOAD(0)
@@ -356,8 +373,10 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
           }
       }
     } else if constexpr (P == KALDO_FP32) {
+      const int hn = half_last && ch + 1 == nchunk ? 1 : CB / 64;
 #pragma unroll
       for (int h = 0; h < CB / 64; ++h) {
+        if (h >= hn) break;
         f32x4 af[FM], bf[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
