@@ -902,17 +902,19 @@ struct BatchShape {
 
 // Row tiles covering the realified rows of a crystal: u units of 32 rows in
 // tiles of 4 units (128 rows), the remainder in tiles of 3 or 2 units (FP32
-// and BF16X3).  A tile of 3 units did about 0.75-0.8 of the work per second of
-// a tile of 4 on the 32-crystal batch, so the remainder tiles pay only where
-// the contraction is long (2n >= 256 rows) or tiles of 4 alone would pad the
-// rows by more than a quarter; otherwise, and for FP64 (tiles of 2 units: its
-// accumulators are twice as wide), the tiles are all alike.
+// and BF16X3).  With 64-byte K chunks (BF16X3) a tile of 3 units did about
+// 0.75-0.8 of the work per second of a tile of 4 on the 32-crystal batch, so
+// there the remainder tiles pay only where the contraction is long (2n >= 256
+// rows) or tiles of 4 alone would pad the rows by more than a quarter; with
+// the 128-byte chunks of FP32 they always pay (216 rows: 128 + 96 instead of
+// 2 x 128 took the 36-atom cells from 0.48 to 0.52 of the peak).  FP64 (tiles
+// of 2 units: its accumulators are twice as wide) keeps equal tiles.
 // KALDO_TUNE_FIXED keeps the eager calls' tile (4 units, FP64 2) for bitwise
 // agreement with them.
 static std::vector<int> batch_row_tiles(int precision, int mrows, bool fixed) {
   const int u = (mrows + 31) / 32;
   std::vector<int> f;
-  const bool mixed = mrows >= 256 || 4 * (128 * ((u + 3) / 4)) > 5 * mrows;
+  const bool mixed = precision == KALDO_FP32 || mrows >= 256 || 4 * (128 * ((u + 3) / 4)) > 5 * mrows;
   if (precision == KALDO_FP64 || fixed || !mixed) {
     const int fm = precision == KALDO_FP64 ? 2 : 4;
     f.assign((u + fm - 1) / fm, fm);

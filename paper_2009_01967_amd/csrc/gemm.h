@@ -269,9 +269,9 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
     static_for<NA + NB>([&](auto uc) __attribute__((always_inline)) {                                                 \
       constexpr int u_ = decltype(uc)::value;                                          \
       if constexpr (u_ < NA)                                                           \
-        rg[s_][u_] = *reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + kin(K0));     \
+        rg[s_][u_] = *gmem(reinterpret_cast<const u32x4*>(ap[s_] + aoff[u_] + kin(K0))); \
       else                                                                             \
-        rg[s_][u_] = *reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + bk(kin(K0))); \
+        rg[s_][u_] = *gmem(reinterpret_cast<const u32x4*>(bp[s_] + boff[u_ - NA] + bk(kin(K0)))); \
     });                                                                                \
   });
 #define KALDO_SSTORE(BUFI)                                                             \
@@ -311,7 +311,7 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
 #define KALDO_BLOAD(K0, DST)                                                                              \
   _Pragma("unroll") for (int c = 0; c < FN; ++c) {                                                      \
     _Pragma("unroll") for (int s = 0; s < 2; ++s) DST[c][s] =                                           \
-        *reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + bk(K0));                                       \
+        *gmem(reinterpret_cast<const bf16x8*>(bp[s] + bfo[c] + bk(K0)));                                 \
   }
 
   // WD: chunks of 32 k, the last one of 16 k when K = 16 mod 32

@@ -42,6 +42,17 @@ struct Operand<KALDO_BF16X3> {
   static constexpr int split = 2;  // hi and lo planes
 };
 
+// Global-memory view of a pointer into a device buffer.  Inside kernels that
+// take their buffers from a table in memory (the persistent batch kernel) the
+// compiler cannot tell the address space and issues flat loads and stores;
+// those count against the LDS wait counter as well, so every wait for an LDS
+// read would also wait for the memory operations in flight.  Through this view
+// they are global_* instructions.  Only for device memory (never LDS).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Store v into an operand plane; for BF16X3 as hi = bf16(v), lo = bf16(v - hi).
 template <int P>
 __device__ __forceinline__ void store_operand(typename Operand<P>::T* hi, typename Operand<P>::T* lo, size_t o,
@@ -49,10 +60,10 @@ __device__ __forceinline__ void store_operand(typename Operand<P>::T* hi, typena
   if constexpr (P == KALDO_BF16X3) {
     const float f = (float)v;
     const __bf16 h = (__bf16)f;
-    hi[o] = h;
-    lo[o] = (__bf16)(f - (float)h);
+    gmem(hi)[o] = h;
+    gmem(lo)[o] = (__bf16)(f - (float)h);
   } else {
-    hi[o] = (typename Operand<P>::T)v;
+    gmem(hi)[o] = (typename Operand<P>::T)v;
   }
 }
 
@@ -65,12 +76,14 @@ __device__ __forceinline__ void store_operand2(typename Operand<P>::T* hi, typen
     const __bf16 h0 = (__bf16)f0, h1 = (__bf16)f1;
     const __bf16 l0 = (__bf16)(f0 - (float)h0), l1 = (__bf16)(f1 - (float)h1);
     typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
-    *reinterpret_cast<bf16x2*>(hi + o) = bf16x2{h0, h1};
-    *reinterpret_cast<bf16x2*>(lo + o) = bf16x2{l0, l1};
+    *gmem(reinterpret_cast<bf16x2*>(hi + o)) = bf16x2{h0, h1};
+    *gmem(reinterpret_cast<bf16x2*>(lo + o)) = bf16x2{l0, l1};
   } else if constexpr (P == KALDO_FP32) {
-    *reinterpret_cast<float2*>(hi + o) = make_float2((float)v0, (float)v1);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    *gmem(reinterpret_cast<f32x2*>(hi + o)) = f32x2{(float)v0, (float)v1};
   } else {
-    *reinterpret_cast<double2*>(hi + o) = make_double2(v0, v1);
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    *gmem(reinterpret_cast<f64x2*>(hi + o)) = f64x2{v0, v1};
   }
 }
 
