@@ -685,6 +685,7 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
       g1.b_z = nn * ldk;
       g1.a_map = kmap + (size_t)k * nk + p0;
       g1.K = ldk;
+      g1.kv = 2 * n;  // realified contraction over the n atoms' coordinates
       g1.nz = cnt;
       g1.m_valid = mrows;
       g1.c_valid = nn;
@@ -881,7 +882,7 @@ __device__ __forceinline__ void gemm_persistent(GemmOps& g, const Epi& e, char* 
       int mt, nt, z;
       gemm_tile_coords(g, t, mt, nt, z);
       const int fm = C.rt_fm[mt], r0 = 32 * C.rt_u0[mt];
-      g.tile_flops = 2ull * (32 * fm) * (32 * FN) * (unsigned long long)g.K * mult;
+      g.tile_flops = 2ull * (32 * fm) * (32 * FN) * (unsigned long long)gemm_k_exec<P>(g) * mult;
       if constexpr (P == KALDO_FP64) {
         gemm_tile<P, 2, FN, Epi>(g, e, mt, nt, z, lds, r0);
       } else {
@@ -1033,6 +1034,7 @@ struct BatchStages {
     g.b_z = nn * C.ldk;
     g.a_map = C.kmap + (size_t)R.k * C.nk + R.p0;
     g.K = C.ldk;
+    g.kv = 2 * C.n;
     g.nz = R.cnt;
     g.m_valid = C.mrows;
     g.c_valid = nn;
@@ -1177,7 +1179,10 @@ static double batch_dense_flops(const std::vector<CrystalPlan>& plans, const std
     double rows = 0.0;
     for (int i = 0; i < C.m_tiles2; ++i) rows += 32.0 * C.rt_fm[i];
     const double ntiles = (double)(((long long)C.n * C.n + 32 * FN - 1) / (32 * FN)) * r.cnt;
-    total += 2.0 * 2.0 * rows * (32 * FN) * ntiles * C.ldk * (P == KALDO_BF16X3 ? 3.0 : 1.0);
+    GemmOps g{};
+    g.K = C.ldk;
+    g.kv = 2 * C.n;
+    total += 2.0 * 2.0 * rows * (32 * FN) * ntiles * gemm_k_exec<P>(g) * (P == KALDO_BF16X3 ? 3.0 : 1.0);
   }
   return total;
 }

@@ -51,7 +51,10 @@ struct GemmOps {
                       // at (k / L) * b_kb + c * L + k % L, L = kBlockBytes of
                       // elements (ldb = L); otherwise B rows are K-contiguous
   const int* a_map;   // if set, batch item z takes A item a_map[z] (else z)
-  int K;              // multiple of the chunk (128 bytes of one row)
+  int K;              // multiple of 16 elements (FP64 and the BF16X3 wide chunks: of the chunk)
+  int kv;             // FP32: the contraction's own length, K - 16 < kv <= K, beyond which
+                      // one operand is zero: the MFMA steps of the last 16 k stop at kv
+                      // (rounded up to 4); 0 = K
   int m_tiles, n_tiles, nz; // filled in by the launcher from the tile shape
   int m_valid;        // rows of A (= output rows); loads beyond are clamped
   long long c_valid;  // rows of B (= output columns) per batch item
@@ -65,6 +68,13 @@ struct GemmOps {
   int group_m;        // row tiles per group of the tile order (0: 8; clamped to m_tiles)
   int group_n;        // column panels per chunk of the tile order (0: all)
 };
+
+// The contraction length the MFMAs run over (FP32 stops at kv, rounded up to 4).
+template <int P>
+__host__ __device__ inline int gemm_k_exec(const GemmOps& g) {
+  if (P != KALDO_FP32 || g.kv <= g.K - 16 || g.kv >= g.K) return g.K;
+  return g.K - 16 + ((g.kv - (g.K - 16) + 3) / 4) * 4;
+}
 
 // Bytes of one row per K chunk, and the chunk in elements.
 template <int P>
@@ -317,6 +327,9 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
   // WD: chunks of 32 k, the last one of 16 k when K = 16 mod 32
   const int nchunk = WD ? (g.K + KCH - 1) / KCH : g.K / KCH;
   const bool half_last = WD && (g.K % KCH) != 0;
+  // FP32: MFMA steps of 4 k in the last 16 k (4: all of them)
+  const int kvalid = g.kv > g.K - 16 && g.kv < g.K ? g.kv : g.K;
+  const int tail_q = P == KALDO_FP32 ? (kvalid - (g.K - 16) + 3) / 4 : 4;
   {
     u32x4 rg[S][NA + NB];
     KALDO_GLOAD(0)
@@ -373,10 +386,13 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
           }
       }
     } else if constexpr (P == KALDO_FP32) {
-      const int hn = half_last && ch + 1 == nchunk ? 1 : CB / 64;
+      const bool lastc = ch + 1 == nchunk;
+      const int hn = half_last && lastc ? 1 : CB / 64;
 #pragma unroll
       for (int h = 0; h < CB / 64; ++h) {
         if (h >= hn) break;
+        // a partial last 16 k goes after the loop (fewer registers live here)
+        if (lastc && h + 1 == hn && tail_q < 4) break;
         f32x4 af[FM], bf[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
@@ -441,6 +457,32 @@ __device__ __forceinline__ void gemm_tile(const GemmOps& g, const Epi& epi, int 
 #undef KALDO_GLOAD
 #undef KALDO_SSTORE
 #undef KALDO_BLOAD
+  if constexpr (P == KALDO_FP32) {
+    if (tail_q < 4) {
+      // the last 16 k hold 4 tail_q that are not padding (their chunk is still
+      // in its buffer): step j takes k = 4 j + (lane group), one float per lane
+      // from slot j of the group
+      const char* base = lds + (WC ? 0 : ((nchunk - 1) & 1) * BUF);
+      const int h = half_last ? 0 : CB / 64 - 1;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (j >= tail_q) break;
+        float a1[FM], b1[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+          a1[a] = *reinterpret_cast<const float*>(base + lds_off<CB>(arow + 16 * a, 4 * h + j) + 4 * grp);
+#pragma unroll
+        for (int c = 0; c < FN; ++c)
+          b1[c] = *reinterpret_cast<const float*>(base + lds_off<CB>(brow + 16 * c, 4 * h + j) + 4 * grp);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int c = 0; c < FN; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[a], b1[c], acc[a][c], 0, 0, 0);
+      }
+      __syncthreads();  // the epilogue may reuse the operand buffers
+    }
+  }
 
   TileAt at;
   at.mt = mt;
@@ -549,7 +591,7 @@ inline void gemm_launch_tile(GemmOps g, const Epi& e, hipStream_t st) {
   g.group_n = g.group_n <= 0 ? g.n_tiles : (g.group_n < g.n_tiles ? g.group_n : g.n_tiles);
   const long long blocks = (long long)g.m_tiles * g.n_tiles * g.nz;
   // BF16X3 issues three bf16 products per element product
-  g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)g.K * (P == KALDO_BF16X3 ? 3 : 1);
+  g.tile_flops = 2ull * (32 * FM) * (32 * FN) * (unsigned long long)gemm_k_exec<P>(g) * (P == KALDO_BF16X3 ? 3 : 1);
   if (g.tally_dense) *g.tally_dense += (double)g.tile_flops * (double)blocks;
   hipLaunchKernelGGL((k_gemm<P, FM, FN, Epi, BD, WC>), dim3((unsigned)blocks), dim3(256), 0, st, g, e);
 }
