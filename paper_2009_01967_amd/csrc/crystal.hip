@@ -33,6 +33,13 @@
 
 namespace kaldo {
 
+// a complex value from a device buffer through the global-memory view
+template <typename R>
+__device__ __forceinline__ cplx<R> gload(const cplx<R>* p) {
+  const R* q = reinterpret_cast<const R*>(p);
+  return {gmem(q)[0], gmem(q)[1]};
+}
+
 // output row of the realified pair (i, c)
 template <int P>
 __host__ __device__ __forceinline__ int cr_row(int i, int c) {
@@ -56,22 +63,27 @@ __device__ __forceinline__ void cr_zg_elem(cplx<RZ>* __restrict__ Z, const cplx<
   const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
   const long long Gt = (long long)G0 * G1 * G2;
   const cplx<double>* e = E + ((size_t)k * n + s) * n;
-  const int2 r = cgb[g];
+  const int* rg = reinterpret_cast<const int*>(cgb) + 2 * (size_t)g;  // (first, end) blocks of group g
+  const int b0 = gmem(rg)[0], b1 = gmem(rg)[1];
   double re = 0.0, im = 0.0;
-  for (int b = r.x; b < r.y; ++b) {
-    const int i3 = 3 * bi[b];
+  for (int b = b0; b < b1; ++b) {
+    const int i3 = 3 * gmem(bi)[b];
     const double* v = bval + 27 * (size_t)b + e9;
-    const cplx<double> e0 = e[i3], e1 = e[i3 + 1], e2 = e[i3 + 2];
-    const double sr = e0.re * v[0] + e1.re * v[9] + e2.re * v[18];
-    const double si = e0.im * v[0] + e1.im * v[9] + e2.im * v[18];
-    const long long num = (long long)m0 * bR2[3 * b] * (G1 * G2) + (long long)m1 * bR2[3 * b + 1] * (G0 * G2) +
-                          (long long)m2 * bR2[3 * b + 2] * (G0 * G1);
+    const cplx<double> e0 = gload(e + i3), e1 = gload(e + i3 + 1), e2 = gload(e + i3 + 2);
+    const double v0 = gmem(v)[0], v9 = gmem(v)[9], v18 = gmem(v)[18];
+    const double sr = e0.re * v0 + e1.re * v9 + e2.re * v18;
+    const double si = e0.im * v0 + e1.im * v9 + e2.im * v18;
+    const long long num = (long long)m0 * gmem(bR2)[3 * b] * (G1 * G2) +
+                          (long long)m1 * gmem(bR2)[3 * b + 1] * (G0 * G2) +
+                          (long long)m2 * gmem(bR2)[3 * b + 2] * (G0 * G1);
     double c, sn;
     unit_phase(num, Gt, c, sn);  // e^{+2 pi i k.R2}
     re += sr * c - si * sn;
     im += sr * sn + si * c;
   }
-  Z[idx] = {(RZ)re, (RZ)im};
+  RZ* zp = reinterpret_cast<RZ*>(Z + idx);
+  gmem(zp)[0] = (RZ)re;
+  gmem(zp)[1] = (RZ)im;
 }
 
 template <typename RZ>
@@ -191,18 +203,20 @@ __device__ __forceinline__ void cr_x_elem_lds(typename Operand<P>::T* __restrict
   const int a1 = (int)(row % n);
   const int s = (int)(row / n);
   int cp = -1;
-  if (a2 < n) cp = pairmap[(size_t)(a1 / 3) * N + a2 / 3];
+  if (a2 < n) cp = gmem(pairmap)[(size_t)(a1 / 3) * N + a2 / 3];
   const int e9 = 3 * (a1 % 3) + a2 % 3;
   for (int z0 = 0; z0 < zn; z0 += ZT) {
     RZ re[ZT], im[ZT];
 #pragma unroll
     for (int u = 0; u < ZT; ++u) re[u] = im[u] = (RZ)0;
     if (cp >= 0) {
-      const int4 pr = cpair[cp];
-      for (int q = pr.z; q < pr.w; ++q) {
-        const int g = cg_order[q];
-        const cplx<RZ> zz = Z[((size_t)s * ng + g) * 9 + e9];
-        const cplx<RZ>* ph = phs + (size_t)cg_delta[g] * ZC + z0;
+      // (z, w) of cpair[cp]: the range of this block pair's groups in cg_order
+      const int* prw = reinterpret_cast<const int*>(cpair) + 4 * (size_t)cp;
+      const int q0 = gmem(prw)[2], q1 = gmem(prw)[3];
+      for (int q = q0; q < q1; ++q) {
+        const int g = gmem(cg_order)[q];
+        const cplx<RZ> zz = gload(Z + ((size_t)s * ng + g) * 9 + e9);
+        const cplx<RZ>* ph = phs + (size_t)gmem(cg_delta)[g] * ZC + z0;
 #pragma unroll
         for (int u = 0; u < ZT; ++u) {
           const RZ fr = ph[u].re, fi = ph[u].im;
@@ -282,16 +296,16 @@ struct EpiCrystal {
     constexpr int BM = 32 * FM, BN = 32 * FN;
     const int m0 = r0 / 2;
     if (m0 >= n) return true;
-    const int p = p0 + z, kk = kmap[z];
-    const double a = OM[(size_t)m0 * nk + p] * rs, b = OM[(size_t)(min(n, m0 + BM / 2) - 1) * nk + p] * rs;
+    const int p = p0 + z, kk = gmem(kmap)[z];
+    const double a = gmem(OM)[(size_t)m0 * nk + p] * rs, b = gmem(OM)[(size_t)(min(n, m0 + BM / 2) - 1) * nk + p] * rs;
     const double W = sqrt(delta_cut<P>(DK)) * (1.0 + 1e-9) + 1e-9;
     const long long c1 = min(ncol, (long long)nt * BN + BN) - 1;
     for (long long c = (long long)nt * BN; c <= c1;) {
       const int s = (int)(c / n);
       const long long ce = min(c1, (long long)(s + 1) * n - 1);
-      const double ws = OM[(size_t)s * nk + k] * rs;
-      const double lo = OM[(size_t)(c - (long long)s * n) * nk + kk] * rs;
-      const double hi = OM[(size_t)(ce - (long long)s * n) * nk + kk] * rs;
+      const double ws = gmem(OM)[(size_t)s * nk + k] * rs;
+      const double lo = gmem(OM)[(size_t)(c - (long long)s * n) * nk + kk] * rs;
+      const double hi = gmem(OM)[(size_t)(ce - (long long)s * n) * nk + kk] * rs;
       if (ws - hi + a < W && ws - lo + b > -W) return false;  // w + w' - w''
       if (ws - hi - b < W && ws - lo - a > -W) return false;  // w - w' - w''
       c = ce + 1;
@@ -303,7 +317,7 @@ struct EpiCrystal {
     const long long first = (long long)nt * 32 * FN;
     for (int i = threadIdx.x; i < 32 * FN * nT; i += blockDim.x) {
       const int col = i / nT, t = i % nT;
-      if (first + col < ncol) partial[(((size_t)z * m_tiles + mt) * ncol + first + col) * nT + t] = 0.0;
+      if (first + col < ncol) gmem(partial)[(((size_t)z * m_tiles + mt) * ncol + first + col) * nT + t] = 0.0;
     }
   }
 
@@ -313,7 +327,7 @@ struct EpiCrystal {
     using R = typename std::conditional<P == KALDO_FP64, double, float>::type;
     constexpr double cut = delta_cut<P>(DK);
     const int p = p0 + at.z;
-    const int kk = kmap[at.z];
+    const int kk = gmem(kmap)[at.z];
     // column data: w - w'' (first mode minus k+p mode), 1/w'', n''
     double dcol[FN];
     R iw2[FN], n2[FN][NT], o[FN][NT];
@@ -324,15 +338,15 @@ struct EpiCrystal {
       const bool cv = col < ncol;
       const int s = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)s * n) : 0;
-      dcol[q] = (OM[(size_t)s * nk + k] - OM[(size_t)s2 * nk + kk]) * rs;
-      iw2[q] = cv ? (R)IW[(size_t)s2 * nk + kk] : (R)0;
+      dcol[q] = (gmem(OM)[(size_t)s * nk + k] - gmem(OM)[(size_t)s2 * nk + kk]) * rs;
+      iw2[q] = cv ? (R)gmem(IW)[(size_t)s2 * nk + kk] : (R)0;
       if constexpr (kAdapt) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) uq[q][a] = (R)UT[((size_t)s2 * 3 + a) * nk + kk];
+        for (int a = 0; a < 3; ++a) uq[q][a] = (R)gmem(UT)[((size_t)s2 * 3 + a) * nk + kk];
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        n2[q][t] = t < nT ? (R)OCC[((size_t)t * n + s2) * nk + kk] : (R)0;
+        n2[q][t] = t < nT ? (R)gmem(OCC)[((size_t)t * n + s2) * nk + kk] : (R)0;
         o[q][t] = 0;
       }
     }
@@ -346,14 +360,14 @@ struct EpiCrystal {
       for (int h = 0; h < 2; ++h) {
         const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
         const int ic = i < n ? i : n - 1;
-        w1[h] = OM[(size_t)ic * nk + p] * rs;
-        iw1[h] = i < n ? (R)IW[(size_t)ic * nk + p] : (R)0;
+        w1[h] = gmem(OM)[(size_t)ic * nk + p] * rs;
+        iw1[h] = i < n ? (R)gmem(IW)[(size_t)ic * nk + p] : (R)0;
         if constexpr (kAdapt) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) up[h][c] = (R)UT[((size_t)ic * 3 + c) * nk + p];
+          for (int c = 0; c < 3; ++c) up[h][c] = (R)gmem(UT)[((size_t)ic * 3 + c) * nk + p];
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)OCC[((size_t)t * n + ic) * nk + p] : (R)0;
+        for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)gmem(OCC)[((size_t)t * n + ic) * nk + p] : (R)0;
       }
 #pragma unroll
       for (int q = 0; q < FN; ++q) {
@@ -415,7 +429,7 @@ __device__ __forceinline__ double cr_collect_sum(const double* __restrict__ part
   for (int z = 0; z < zb; ++z)
     for (int mt = 0; mt < m_tiles; ++mt)
       for (int s2 = threadIdx.x; s2 < n; s2 += 256)
-        v += partial[(((size_t)z * m_tiles + mt) * nn + (size_t)s * n + s2) * nT + t];
+        v += gmem(partial)[(((size_t)z * m_tiles + mt) * nn + (size_t)s * n + s2) * nT + t];
   red[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

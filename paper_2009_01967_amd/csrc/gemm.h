@@ -536,7 +536,7 @@ __device__ __forceinline__ void column_flush(char* lds, double* dst, long long n
   __syncthreads();
   for (int i = (int)threadIdx.x; i < 32 * FN * NT; i += 256) {
     const int col = i / NT, t = i % NT;
-    if (t < nT && col < ncols_left) dst[(long long)col * nT + t] = red[i] + red[32 * FN * NT + i];
+    if (t < nT && col < ncols_left) gmem(dst)[(long long)col * nT + t] = red[i] + red[32 * FN * NT + i];
   }
 }
 
