@@ -1012,8 +1012,11 @@ struct BatchStages {
     const long long cnt = (long long)C.n * C.n * (C.ldk / 2);
     const long long CH = stage_chunk(cnt, G);
     const int nd = C.nd;
-    int ZC = (int)(lds_bytes / ((long long)nd * sizeof(cplx<RZ>))) & ~7;
-    ZC = ZC < ((R.cnt + 7) & ~7) ? ZC : ((R.cnt + 7) & ~7);
+    // partners per thread at a time (16 where the registers allow it: FP32 with
+    // one temperature), and per LDS pass a multiple of that
+    constexpr int ZT = P == KALDO_FP32 && NT == 1 ? 16 : 8;
+    int ZC = (int)(lds_bytes / ((long long)nd * sizeof(cplx<RZ>))) & ~(ZT - 1);
+    ZC = ZC < ((R.cnt + ZT - 1) & ~(ZT - 1)) ? ZC : ((R.cnt + ZT - 1) & ~(ZT - 1));
     cplx<RZ>* phs = reinterpret_cast<cplx<RZ>*>(lds);
     const cplx<double>* PH = static_cast<const cplx<double>*>(C.PH);
     claimed(&gs->claims[0], base, (cnt + CH - 1) / CH, G, [&](long long c) {
@@ -1027,7 +1030,7 @@ struct BatchStages {
         }
         __syncthreads();
         for (long long i = c * CH + threadIdx.x; i < e; i += blockDim.x)
-          cr_x_elem_lds<P, 8, RZ>(static_cast<T*>(C.Xh), static_cast<T*>(C.Xl), static_cast<const cplx<RZ>*>(C.Z),
+          cr_x_elem_lds<P, ZT, RZ>(static_cast<T*>(C.Xh), static_cast<T*>(C.Xl), static_cast<const cplx<RZ>*>(C.Z),
                                   phs, ZC, static_cast<const int*>(C.cg_delta), static_cast<const int*>(C.cg_order),
                                   static_cast<const int4*>(C.cpair), static_cast<const int*>(C.pairmap), C.n, C.N,
                                   C.ng, C.ldk, zc, zn, i);
@@ -1257,13 +1260,13 @@ kaldo_status batch_persistent_prepare(kaldo_ctx parent, const std::vector<kaldo_
   // KALDO_TUNE_FIXED keeps the fixed tile shape of eager calls (variant 0), so
   // that batch and eager results agree bit for bit
   const bool fixed = parent->tuning == KALDO_TUNE_FIXED;
-  // step B stages the phases of 8 partners for every cell offset Delta in LDS
+  // step B stages the phases of 16 partners for every cell offset Delta in LDS
   const int lds_bytes = precision == KALDO_FP64 ? BatchLds<KALDO_FP64, 1>::bytes
                         : precision == KALDO_FP32 ? BatchLds<KALDO_FP32, 1>::bytes
                                                   : BatchLds<KALDO_BF16X3, 1>::bytes;
   const size_t ph_bytes = precision == KALDO_FP64 ? 16 : 8;
   for (CrystalPlan& cp : sorted) {
-    if ((size_t)cp.nd * 8 * ph_bytes > (size_t)lds_bytes)
+    if ((size_t)cp.nd * 16 * ph_bytes > (size_t)lds_bytes)
       return fail(parent, KALDO_EINVAL, "persistent batch kernel: too many fc3 cell offsets for its LDS");
     const std::vector<int> fms = batch_row_tiles(precision, cp.mrows, fixed);
     // the partial sums were sized for tiles of 64 rows
