@@ -338,36 +338,65 @@ struct EpiCrystal {
       const bool cv = col < ncol;
       const int s = cv ? (int)(col / n) : 0;
       const int s2 = cv ? (int)(col - (long long)s * n) : 0;
+      // unconditional loads of valid addresses, then selects: no branches
+      // (and no wait for each load at their joins)
       dcol[q] = (gmem(OM)[(size_t)s * nk + k] - gmem(OM)[(size_t)s2 * nk + kk]) * rs;
-      iw2[q] = cv ? (R)gmem(IW)[(size_t)s2 * nk + kk] : (R)0;
+      const R iwv = (R)gmem(IW)[(size_t)s2 * nk + kk];
+      iw2[q] = cv ? iwv : (R)0;
       if constexpr (kAdapt) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) uq[q][a] = (R)gmem(UT)[((size_t)s2 * 3 + a) * nk + kk];
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        n2[q][t] = t < nT ? (R)gmem(OCC)[((size_t)t * n + s2) * nk + kk] : (R)0;
+        // (one temperature: nT = 1, the load needs no guard)
+        n2[q][t] = NT == 1 || t < nT ? (R)gmem(OCC)[((size_t)t * n + s2) * nk + kk] : (R)0;
         o[q][t] = 0;
       }
     }
-#pragma unroll
-    for (int a = 0; a < FM; ++a) {
-      // row data of the lane's two (Re, Im) pairs: w', 1/w', n'
-      double w1[2];
-      R iw1[2], n1[2][NT];
-      R up[kAdapt ? 2 : 1][3];  // adaptive widths: (p, s')
+    // row data of the lane's two (Re, Im) pairs in every row fragment: w',
+    // 1/w', n'; with one temperature all of it is loaded before any use, so
+    // that the loads are in flight together instead of one fragment at a time
+    constexpr int FA = NT == 1 && !kAdapt ? FM : 1;
+    double w1a[FA][2];
+    R iw1a[FA][2], n1a[FA][2][NT];
+    const auto rows = [&](int a, double (&w1)[2], R (&iw1)[2], R (&n1)[2][NT], R (&up)[kAdapt ? 2 : 1][3]) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int i = cr_pair_mode<P>(at.m0 + 16 * a, at.lane, h);
         const int ic = i < n ? i : n - 1;
         w1[h] = gmem(OM)[(size_t)ic * nk + p] * rs;
-        iw1[h] = i < n ? (R)gmem(IW)[(size_t)ic * nk + p] : (R)0;
+        const R iwv = (R)gmem(IW)[(size_t)ic * nk + p];
+        iw1[h] = i < n ? iwv : (R)0;
         if constexpr (kAdapt) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) up[h][c] = (R)gmem(UT)[((size_t)ic * 3 + c) * nk + p];
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) n1[h][t] = t < nT ? (R)gmem(OCC)[((size_t)t * n + ic) * nk + p] : (R)0;
+        for (int t = 0; t < NT; ++t)
+          n1[h][t] = NT == 1 || t < nT ? (R)gmem(OCC)[((size_t)t * n + ic) * nk + p] : (R)0;
+      }
+    };
+    if constexpr (FA > 1) {
+      R up0[1][3];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) rows(a, w1a[a], iw1a[a], n1a[a], up0);
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      double w1[2];
+      R iw1[2], n1[2][NT];
+      R up[kAdapt ? 2 : 1][3];  // adaptive widths: (p, s')
+      if constexpr (FA > 1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          w1[h] = w1a[a][h];
+          iw1[h] = iw1a[a][h];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) n1[h][t] = n1a[a][h][t];
+        }
+      } else {
+        rows(a, w1, iw1, n1, up);
       }
 #pragma unroll
       for (int q = 0; q < FN; ++q) {
