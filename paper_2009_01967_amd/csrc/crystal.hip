@@ -128,6 +128,24 @@ __global__ void k_cr_realify(typename Operand<P>::T* __restrict__ Ach, typename 
   store_operand<P>(Ach, Acl, o + 1, cr1);
 }
 
+// idx = (s n + a') half + a'' split into its parts, with 32-bit divisions
+// when idx fits (64-bit integer division is a long instruction sequence)
+__device__ __forceinline__ void idx_split(long long idx, int half, int n, int& a2, long long& row, int& a1, int& s) {
+  if (idx < 0x7fffffffLL) {
+    const int ii = (int)idx;
+    const int r = ii / half;
+    a2 = ii - r * half;
+    s = r / n;
+    a1 = r - s * n;
+    row = r;
+  } else {
+    row = idx / half;
+    a2 = (int)(idx - row * half);
+    s = (int)(row / n);
+    a1 = (int)(row - (long long)s * n);
+  }
+}
+
 // Step B into the realified B operand of GEMM 1, every element written (zeros
 // outside the fc3 pairs and in the K padding): X[z][(s, a')][2 a'' + d] for
 // partners p = p0 + z.  One thread serves up to ZT partners of the same
@@ -140,10 +158,9 @@ __device__ __forceinline__ void cr_x_elem(typename Operand<P>::T* __restrict__ X
                                           int N, int nk, int ng, int ldk, int p0, int zb, long long idx) {
   const int half = ldk / 2;
   const long long nn = (long long)n * n;
-  const int a2 = (int)(idx % half);
-  const long long row = idx / half;  // s * n + a'
-  const int a1 = (int)(row % n);
-  const int s = (int)(row / n);
+  int a2, a1, s;
+  long long row;  // s * n + a'
+  idx_split(idx, half, n, a2, row, a1, s);
   int cp = -1;
   if (a2 < n) cp = pairmap[(size_t)(a1 / 3) * N + a2 / 3];
   const int e9 = 3 * (a1 % 3) + a2 % 3;
@@ -198,10 +215,9 @@ __device__ __forceinline__ void cr_x_elem_lds(typename Operand<P>::T* __restrict
                                               int zn, long long idx) {
   const int half = ldk / 2;
   const long long nn = (long long)n * n;
-  const int a2 = (int)(idx % half);
-  const long long row = idx / half;  // s * n + a'
-  const int a1 = (int)(row % n);
-  const int s = (int)(row / n);
+  int a2, a1, s;
+  long long row;  // s * n + a'
+  idx_split(idx, half, n, a2, row, a1, s);
   int cp = -1;
   if (a2 < n) cp = gmem(pairmap)[(size_t)(a1 / 3) * N + a2 / 3];
   const int e9 = 3 * (a1 % 3) + a2 % 3;
@@ -255,7 +271,9 @@ struct EpiStoreY {
     for (int q = 0; q < FN; ++q) {
       const long long col = at.c0 + 16 * q + (at.lane & 15);
       if (col >= ncol) continue;
-      const int s = (int)(col / n), a1 = (int)(col - (long long)s * n);
+      // col < n^2 fits in 32 bits: 32-bit division
+      const int ci = (int)col;
+      const int s = ci / n, a1 = ci - s * n;
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -301,7 +319,7 @@ struct EpiCrystal {
     const double W = sqrt(delta_cut<P>(DK)) * (1.0 + 1e-9) + 1e-9;
     const long long c1 = min(ncol, (long long)nt * BN + BN) - 1;
     for (long long c = (long long)nt * BN; c <= c1;) {
-      const int s = (int)(c / n);
+      const int s = (int)c / n;  // c < n^2
       const long long ce = min(c1, (long long)(s + 1) * n - 1);
       const double ws = gmem(OM)[(size_t)s * nk + k] * rs;
       const double lo = gmem(OM)[(size_t)(c - (long long)s * n) * nk + kk] * rs;
@@ -336,8 +354,9 @@ struct EpiCrystal {
     for (int q = 0; q < FN; ++q) {
       const long long col = at.c0 + 16 * q + (at.lane & 15);
       const bool cv = col < ncol;
-      const int s = cv ? (int)(col / n) : 0;
-      const int s2 = cv ? (int)(col - (long long)s * n) : 0;
+      const int ci = cv ? (int)col : 0;  // < n^2: 32-bit division
+      const int s = ci / n;
+      const int s2 = ci - s * n;
       // unconditional loads of valid addresses, then selects: no branches
       // (and no wait for each load at their joins)
       dcol[q] = (gmem(OM)[(size_t)s * nk + k] - gmem(OM)[(size_t)s2 * nk + kk]) * rs;
@@ -1113,7 +1132,7 @@ struct BatchStages {
     const CrystalPlan& C = plans[R.c];
     const int n = C.n, nk = C.nk;
     claimed(&gs->claims[2], base, (long long)n * C.nT, G, [&](long long st) {
-      const int s = (int)(st % n), t = (int)(st / n);
+      const int s = (int)st % n, t = (int)st / n;  // st < n nT
       const double v = cr_collect_sum(C.partial, n, C.nT, C.m_tiles2, R.cnt, s, t, reinterpret_cast<double*>(lds));
       if (threadIdx.x == 0) {
         double* ga = C.gacc + (size_t)t * n + s;
