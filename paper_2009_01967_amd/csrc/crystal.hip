@@ -57,9 +57,11 @@ __device__ __forceinline__ void cr_zg_elem(cplx<RZ>* __restrict__ Z, const cplx<
                                            const int2* __restrict__ cgb, const int* __restrict__ bi,
                                            const int* __restrict__ bR2, const double* __restrict__ bval, int n, int ng,
                                            int G0, int G1, int G2, int k, long long idx) {
-  const int e9 = (int)(idx % 9);
-  const int g = (int)((idx / 9) % ng);
-  const int s = (int)(idx / (9LL * ng));
+  // idx = (s ng + g) 9 + e9 < n ng 9, well inside 32 bits
+  const int ii = (int)idx;
+  const int e9 = ii % 9;
+  const int g = (ii / 9) % ng;
+  const int s = ii / (9 * ng);
   const int m0 = k / (G1 * G2), m1 = (k / G2) % G1, m2 = k % G2;
   const long long Gt = (long long)G0 * G1 * G2;
   const cplx<double>* e = E + ((size_t)k * n + s) * n;
@@ -608,6 +610,9 @@ static kaldo_status crystal_impl(kaldo_ctx ctx, double sigma_thz) {
   T* Yl = S == 2 ? Yh + xy_elems : nullptr;
   // d_scratch2: [Z | partial | gacc | graw | kmap]
   const size_t z_elems = (size_t)n * ng * 9;
+  // step A indexes Z in 32 bits
+  if (z_elems >= ((size_t)1 << 31))
+    return fail(ctx, KALDO_EINVAL, "crystal path: too many fc3 cell-offset groups for the step-A tensor");
   const size_t part = (size_t)zb * mt_max * nn * nT;
   const size_t gacc_n = (size_t)nT * n;
   const size_t graw_n = (size_t)nT * nk * n;
