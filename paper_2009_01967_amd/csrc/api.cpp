@@ -26,15 +26,16 @@ thread_local Arena* g_arena = nullptr;
 // batch kernel (one pool shared by the crystals, which run one after the
 // other): larger rounds than an eager call's (256 MB), so that each GEMM phase
 // has many block tiles per resident workgroup and the rounds, with their two
-// grid barriers each, are few.  16 GB (on the 32-crystal batch, 1/16 of the
-// points: 4 GB 13.63 s, 8 GB 13.35 s, 16 GB 13.27 s), at most a quarter of
-// the device memory free at planning time, at least 1 GB.
+// grid barriers each, are few.  32 GB (on the 32-crystal batch, 1/16 of the
+// points: 4 GB 13.63 s, 8 GB 13.35 s, 16 GB 13.27 s; later 16 GB 12.92 s,
+// 32 GB 12.85 s), at most a quarter of the device memory free at planning
+// time, at least 1 GB.
 // (KALDO_BATCH_XY_MB in the environment overrides it, for tuning.)
 static size_t batch_xy_budget() {
   const char* e = std::getenv("KALDO_BATCH_XY_MB");
   const long v = e ? std::atol(e) : 0;
   if (v > 0) return (size_t)v << 20;
-  size_t budget = (size_t)16 << 30;
+  size_t budget = (size_t)32 << 30;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::min(budget, free_b / 4);
   return std::max(budget, (size_t)1 << 30);
